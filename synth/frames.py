@@ -1,0 +1,228 @@
+"""Seeded synthetic frames for the tracker's workloads.
+
+This module only makes inputs: spot images, true shifts and shot noise.  It
+holds none of the tracking arithmetic (no correlation, no peak search, no
+sub-pixel step), so both the FP64 oracle and the GPU path can be fed from it
+without sharing code with each other.
+
+The image model follows the paper's synthetic study (Sec. IV): a Gaussian
+integrated over each pixel, a constant background added before Poisson shot
+noise, pixel values clipped to the sensor's range.  Shifts are applied to the
+noiseless spot by a Fourier phase ramp, so the true displacement is known
+exactly at sub-pixel precision.  The spot's Nyquist row and column are
+zeroed before shifting so the shifted image is the exact band-limited
+translate.
+
+Shift convention: a frame with true shift d = (dy, dx) satisfies
+frame(r) ~ ref(r - d).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.special import erf, j1
+
+SEED_BASE = 2310087700
+
+#: first zero of J1, used for the Airy-like ring pattern
+J1_ZERO = 3.8317059702075125
+
+
+def rng_for(config_index: int, salt: int = 0) -> np.random.Generator:
+    """Generator for one workload: PCG64 seeded with SEED_BASE + index (+ salt)."""
+    return np.random.Generator(np.random.PCG64(SEED_BASE + config_index + salt))
+
+
+def gaussian_spot(n: int, sigma: float, peak: float, center=None) -> np.ndarray:
+    """Pixel-integrated Gaussian on an n x n grid, scaled so the pixel at the
+    centre holds `peak`.  Pixel (y, x) covers [y-1/2, y+1/2] x [x-1/2, x+1/2];
+    the centre defaults to (n/2, n/2)."""
+    cy, cx = (n / 2, n / 2) if center is None else center
+    r = np.arange(n, dtype=np.float64)
+    s = math.sqrt(2.0) * sigma
+
+    def prof(c):
+        return erf((r + 0.5 - c) / s) - erf((r - 0.5 - c) / s)
+
+    gy, gx = prof(cy), prof(cx)
+    g = np.outer(gy, gx)
+    # normalise to the value of a pixel centred exactly on the spot
+    g0 = (erf(0.5 / s) - erf(-0.5 / s)) ** 2
+    return peak * g / g0
+
+
+def airy_spot(n: int, first_zero_px: float, peak: float) -> np.ndarray:
+    """Airy-like ring pattern peak * [2 J1(v)/v]^2, v = 3.8317 r / first_zero,
+    sampled at pixel centres around (n/2, n/2)."""
+    r = np.arange(n, dtype=np.float64) - n / 2
+    rr = np.hypot(r[:, None], r[None, :])
+    v = J1_ZERO * rr / first_zero_px
+    with np.errstate(invalid="ignore", divide="ignore"):
+        a = np.where(v > 0, 2.0 * j1(v) / np.where(v > 0, v, 1.0), 1.0)
+    return peak * a * a
+
+
+def zero_nyquist(img: np.ndarray) -> np.ndarray:
+    """Remove the Nyquist row and column (even sizes) from a real image."""
+    ny, nx = img.shape
+    f = np.fft.fft2(img)
+    if ny % 2 == 0:
+        f[ny // 2, :] = 0
+    if nx % 2 == 0:
+        f[:, nx // 2] = 0
+    return np.fft.ifft2(f).real
+
+
+def phase_ramp_shift(img: np.ndarray, d) -> np.ndarray:
+    """Translate a real image by d = (dy, dx) pixels, periodically, by a
+    Fourier phase ramp: out(r) = img(r - d) for band-limited img.
+    The image should already have its Nyquist row/column removed."""
+    ny, nx = img.shape
+    ky = np.fft.fftfreq(ny)[:, None]
+    kx = np.fft.rfftfreq(nx)[None, :]
+    f = np.fft.rfft2(img)
+    ramp = np.exp(-2j * np.pi * (ky * d[0] + kx * d[1]))
+    return np.fft.irfft2(f * ramp, s=(ny, nx))
+
+
+def noisy(mu: np.ndarray, rng: np.random.Generator, clip_max=None) -> np.ndarray:
+    """Poisson shot noise on the clamped mean image, optionally clipped."""
+    lam = np.clip(mu, 0.0, None)
+    out = rng.poisson(lam).astype(np.float64)
+    if clip_max is not None:
+        out = np.minimum(out, clip_max)
+    return out
+
+
+@dataclass
+class Workload:
+    """A set of frames with its references and the true shifts.
+
+    frames:   list (or stacked array) of 2-D arrays, one per frame/ROI
+    refs:     list of reference images (noiseless, unshifted mean images)
+    ref_ids:  reference index used by each frame
+    shifts:   true (dy, dx) per frame, float64 [n, 2]
+    dtype:    'u16' or 'f32' (how frames are handed to the tracker)
+    u:        upsampling factor
+    """
+
+    name: str
+    frames: list
+    refs: list
+    ref_ids: np.ndarray
+    shifts: np.ndarray
+    dtype: str
+    u: int
+    meta: dict = field(default_factory=dict)
+
+    def stacked(self) -> np.ndarray:
+        """Frames as one [n, ny, nx] array (uniform sizes only)."""
+        return np.stack(self.frames)
+
+
+def _shifted_frames(spot_nz, bg, shifts, rng, clip_max, as_dtype):
+    frames = []
+    for d in shifts:
+        mu = phase_ramp_shift(spot_nz, d) + bg
+        frames.append(noisy(mu, rng, clip_max).astype(as_dtype))
+    return frames
+
+
+def config1(n_frames: int = 100) -> Workload:
+    """Tiny plain case: 64x64 uint16 Gaussian spots (sigma 3, peak 1000,
+    background 10), shifts uniform in +-2 px, u = 20, FP64 reference."""
+    rng = rng_for(0)
+    n = 64
+    shifts = rng.uniform(-2.0, 2.0, size=(n_frames, 2))
+    spot = zero_nyquist(gaussian_spot(n, 3.0, 1000.0))
+    frames = _shifted_frames(spot, 10.0, shifts, rng, 65535.0, np.uint16)
+    ref = spot + 10.0
+    return Workload("gauss64_u20", frames, [ref], np.zeros(n_frames, np.int32),
+                    shifts, "u16", 20, dict(sigma=3.0, peak=1000.0, bg=10.0))
+
+
+def config2(n_frames: int = 10000) -> Workload:
+    """Streaming case: 256x256 12-bit Airy rings (first zero 8 px, peak 4000,
+    background 50), random-walk shifts with N(0, 0.3 px) steps, u = 100."""
+    rng = rng_for(1)
+    n = 256
+    steps = rng.normal(0.0, 0.3, size=(n_frames, 2))
+    steps[0] = 0.0
+    shifts = np.cumsum(steps, axis=0)
+    spot = zero_nyquist(airy_spot(n, 8.0, 4000.0))
+    frames = _fast_shifted_frames(spot, 50.0, shifts, rng, 4095.0, np.uint16)
+    ref = spot + 50.0
+    return Workload("airy256_u100", frames, [ref], np.zeros(n_frames, np.int32),
+                    shifts, "u16", 100, dict(peak=4000.0, bg=50.0, first_zero=8.0))
+
+
+def _fast_shifted_frames(spot_nz, bg, shifts, rng, clip_max, as_dtype, chunk=64):
+    """Same as _shifted_frames but batched through rfft2 for speed: the
+    spectrum of the spot is computed once and each frame needs one irfft2.
+    Poisson draws happen frame by frame in order, so the stream of random
+    numbers is identical to the unbatched version."""
+    ny, nx = spot_nz.shape
+    f = np.fft.rfft2(spot_nz)
+    ky = np.fft.fftfreq(ny)
+    kx = np.fft.rfftfreq(nx)
+    out = []
+    for s0 in range(0, len(shifts), chunk):
+        d = shifts[s0:s0 + chunk]
+        ry = np.exp(-2j * np.pi * ky[None, :] * d[:, 0:1])
+        rx = np.exp(-2j * np.pi * kx[None, :] * d[:, 1:2])
+        mu = np.fft.irfft2(f[None] * ry[:, :, None] * rx[:, None, :], s=(ny, nx)) + bg
+        for m in mu:
+            out.append(noisy(m, rng, clip_max).astype(as_dtype))
+    return out
+
+
+def config3(n_rois: int = 4096) -> Workload:
+    """Uneven batch: square ROIs with sizes uniform on {32,...,256}, Gaussian
+    spots with sigma ~ U(1.5, 6), peak log-uniform on 200-20000, background
+    ~ U(0, 100), shifts ~ U(-4, 4); one reference per ROI; u = 100."""
+    rng = rng_for(2)
+    sizes_set = np.array([32, 48, 64, 96, 128, 192, 256])
+    sizes = rng.choice(sizes_set, size=n_rois)
+    sig = rng.uniform(1.5, 6.0, size=n_rois)
+    pk = np.exp(rng.uniform(np.log(200.0), np.log(20000.0), size=n_rois))
+    bg = rng.uniform(0.0, 100.0, size=n_rois)
+    shifts = rng.uniform(-4.0, 4.0, size=(n_rois, 2))
+    frames, refs = [], []
+    for i in range(n_rois):
+        n = int(sizes[i])
+        spot = zero_nyquist(gaussian_spot(n, sig[i], pk[i]))
+        mu = phase_ramp_shift(spot, shifts[i]) + bg[i]
+        frames.append(noisy(mu, rng, 65535.0).astype(np.uint16))
+        refs.append(spot + bg[i])
+    return Workload("uneven_rois_u100", frames, refs, np.arange(n_rois, dtype=np.int32),
+                    shifts, "u16", 100, dict(sizes=sizes, sigma=sig, peak=pk, bg=bg))
+
+
+def config4(n_frames: int = 2048) -> Workload:
+    """Precision case: 512x512 uint16 Gaussian (sigma 4, peak 500, background
+    20), shifts uniform in +-3 px, u = 200."""
+    rng = rng_for(3)
+    n = 512
+    shifts = rng.uniform(-3.0, 3.0, size=(n_frames, 2))
+    spot = zero_nyquist(gaussian_spot(n, 4.0, 500.0))
+    frames = _fast_shifted_frames(spot, 20.0, shifts, rng, 65535.0, np.uint16, chunk=16)
+    ref = spot + 20.0
+    return Workload("gauss512_u200", frames, [ref], np.zeros(n_frames, np.int32),
+                    shifts, "u16", 200, dict(sigma=4.0, peak=500.0, bg=20.0))
+
+
+def config5(n_frames: int = 1024) -> Workload:
+    """Differentiation case: 128x128 FP32 Poisson-count frames of a Gaussian
+    (sigma 3, peak 2000, no background), shifts uniform in +-2 px, u = 100."""
+    rng = rng_for(4)
+    n = 128
+    shifts = rng.uniform(-2.0, 2.0, size=(n_frames, 2))
+    spot = zero_nyquist(gaussian_spot(n, 3.0, 2000.0))
+    frames = _fast_shifted_frames(spot, 0.0, shifts, rng, None, np.float32)
+    return Workload("gauss128_grad", frames, [spot.copy()], np.zeros(n_frames, np.int32),
+                    shifts, "f32", 100, dict(sigma=3.0, peak=2000.0, bg=0.0))
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
