@@ -1,0 +1,202 @@
+/*
+ * ccpt.h -- cross-correlation particle tracking on AMD MI355X (gfx950).
+ *
+ * C ABI of the per-frame displacement estimator of Werneck et al.,
+ * "Cross-correlation image analysis for real-time single particle
+ * tracking" (arXiv 2310.08770).
+ *
+ * Problem (Sec. II, Eq. 1): given a reference image E and a frame I, find
+ * the displacement minimising chi^2 between the translated frame and E
+ * under periodic boundaries.  For uniform noise (CC-U, Eq. 2-4) this is the
+ * maximum of the circular cross-correlation F^-1[F[I] conj F[E]]; for shot
+ * noise (CC-SN, Eq. 5-7) it is the extremum of the correlation of (I+eps)^2
+ * with 1/(E+eps).  The integer maximum is refined on a 1.5-pixel window
+ * sampled at 1.5u points per axis by a matrix-multiply DFT (Sec. III, first
+ * paragraph), whose maximum is the paper's sub-pixel estimate; the library
+ * then refines it in FP64 by Newton steps on the band-limited correlation.
+ *
+ * Conventions used throughout:
+ *  - pixels, (y, x) order, row-major images with a row pitch in elements;
+ *  - a result d means frame(r) ~ ref(r - d) (the paper's r0 is -d);
+ *  - CC-SN uses A = (I+eps)^2 and B = -1/(E+eps): the chi^2 minimum of
+ *    Eq. 6 is the maximum of this correlation;
+ *  - even N only: the Nyquist bin is interpolated as cos(pi s);
+ *  - grid: M = ceil(window*u) points per axis, centre index floor(M/2),
+ *    offsets (m - floor(M/2))/u; ties go to the lowest row-major index;
+ *  - integer lags are reported in [-N/2, N/2).
+ *
+ * Supported sizes: square N x N frames with N = 2^a 3^b, a >= 1,
+ * 16 <= N <= 512.  Other shapes return CCPT_E_UNSUPPORTED.
+ *
+ * Memory: every image/frame pointer, `out`, the gradient inputs and
+ * outputs are DEVICE pointers owned by the caller.  The small descriptor
+ * arrays (ccpt_image, ccpt_roi) are HOST arrays, read during the call.
+ * The context owns reference spectra, DFT tables, workspaces, captured
+ * graphs and the tuning table.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Track and
+ * grad calls are stream-ordered and return before the GPU work finishes;
+ * create, destroy, set_reference and fisher may allocate and synchronise.
+ * A context is not thread-safe: use one context per host thread/stream.
+ *
+ * Errors: every call returns CCPT_OK (0) or a negative code; nothing
+ * throws across the ABI.  ccpt_last_error() returns the message of the
+ * last failing call on a context.  Per-frame conditions are reported in
+ * ccpt_result.status bits, never as call failures.
+ */
+#ifndef CCPT_H
+#define CCPT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define CCPT_OK 0
+#define CCPT_E_INVALID (-1)         /* bad pointer, size, count, option or id */
+#define CCPT_E_UNSUPPORTED (-2)     /* frame shape outside the supported set */
+#define CCPT_E_NOREF (-3)           /* no reference set / ref_id out of range */
+#define CCPT_E_HIP (-4)             /* HIP runtime error (see ccpt_last_error) */
+#define CCPT_E_NONPOSITIVE_REF (-5) /* CC-SN reference with E + eps <= 0 */
+#define CCPT_E_NOMEM (-6)           /* device or host allocation failed */
+
+/* ---- per-frame status bits (ccpt_result.status) ---------------------- */
+#define CCPT_ST_NONFINITE 1u       /* NaN/Inf pixel: d, d_grid, peak are NaN */
+#define CCPT_ST_FLAT 2u            /* constant frame: everything is zero */
+#define CCPT_ST_NEAR_TIE 4u        /* reserved: top two integer lags within 1e-5 */
+#define CCPT_ST_NEWTON_FALLBACK 8u /* Hessian not negative definite or step > 1/u:
+                                      d = d_grid */
+#define CCPT_ST_WINDOW_EXIT 16u    /* Newton left the 0.75-px half window:
+                                      d = d_grid */
+
+/* ---- options ---------------------------------------------------------- */
+enum ccpt_mode { CCPT_MODE_CCU = 0, CCPT_MODE_CCSN = 1 };
+
+/* arithmetic of the upsampled matrix DFT (the FFTs are always FP32, the
+   Newton step always FP64) */
+enum ccpt_precision {
+  CCPT_PREC_FP32 = 0,   /* FP32 matrix cores */
+  CCPT_PREC_BF16X2 = 1, /* operands split into bf16 hi + lo, three bf16
+                           products accumulated in FP32 */
+  CCPT_PREC_FP16X2 = 2  /* same with fp16 hi + lo (scaled) */
+};
+
+enum ccpt_dtype { CCPT_U16 = 0, CCPT_F32 = 1 };
+
+#define CCPT_FLAG_GRAPH 1 /* capture each batch shape once in a hipGraph and
+                             replay it on later calls */
+
+typedef struct ccpt_options {
+  int mode;         /* ccpt_mode */
+  double eps;       /* CC-SN offset added to frames and reference (Eq. 6);
+                       Sec. IV suggests 200 x the noise gain; ignored by CC-U */
+  int upsample;     /* u >= 1: grid step 1/u px (Sec. III) */
+  double window;    /* side of the upsampled square in px; the paper uses 1.5 */
+  int precision;    /* ccpt_precision */
+  int newton_iters; /* 0..8 FP64 Newton steps after the grid (0 = grid only) */
+  int flags;        /* CCPT_FLAG_* */
+} ccpt_options;
+
+/* fills `o` with the paper's defaults: CC-U, eps 200, u 100, window 1.5,
+   FP32, 3 Newton steps, no flags */
+void ccpt_default_options(ccpt_options* o);
+
+/* an image in device memory */
+typedef struct ccpt_image {
+  const void* data; /* device pointer, row-major */
+  int ny, nx;       /* rows, columns */
+  int pitch;        /* elements between row starts (>= nx) */
+  int dtype;        /* ccpt_dtype */
+} ccpt_image;
+
+/* one frame or region of interest to track */
+typedef struct ccpt_roi {
+  const void* data; /* device pointer, row-major */
+  int ny, nx;
+  int pitch;  /* elements between row starts (>= nx) */
+  int dtype;  /* ccpt_dtype */
+  int ref_id; /* reference index given to ccpt_set_reference */
+} ccpt_roi;
+
+/* one tracking result, 72 bytes, written to device memory */
+typedef struct ccpt_result {
+  double d[2];     /* refined displacement (y, x), px */
+  double peak;     /* C(d) = band-limited correlation at d, normalised by 1/N^2 */
+  double hess[3];  /* d2C/dy2, d2C/dydx, d2C/dx2 at d (used by the adjoint) */
+  float d_grid[2]; /* maximum of the upsampled grid (the paper's estimate) */
+  int p[2];        /* integer-lag correlation maximum (y, x) */
+  unsigned status; /* CCPT_ST_* bits */
+  unsigned reserved;
+} ccpt_result;
+
+typedef struct ccpt_ctx ccpt_ctx;
+
+/* Creates a context on HIP device `device`.  `opts` may be NULL (defaults).
+   Returns CCPT_E_INVALID for out-of-range options, CCPT_E_HIP if the
+   device cannot be used. */
+int ccpt_create(ccpt_ctx** out, int device, const ccpt_options* opts);
+
+/* Frees everything the context owns (after synchronising its work). */
+void ccpt_destroy(ccpt_ctx* ctx);
+
+/* Sets the reference images (Sec. II: E; Sec. III for its role) and
+   replaces any earlier set.  For each reference the library forms
+   B = E (CC-U) or B = -1/(E+eps) (CC-SN, Eq. 7), transforms it and keeps
+   conj F[B] resident.  References may have different sizes; ids are
+   0..n_refs-1.  Synchronises `stream`.  Errors: CCPT_E_INVALID,
+   CCPT_E_UNSUPPORTED, CCPT_E_NONPOSITIVE_REF (CC-SN, any E + eps <= 0). */
+int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* stream);
+
+/* Tracks n frames (Sec. II Eq. 4/7 and Sec. III): for each roi i computes
+   the correlation with reference roi[i].ref_id, its integer maximum, the
+   upsampled-grid maximum and the FP64 Newton refinement, and writes
+   out[i].  Frames of different sizes may be mixed; each must match the
+   size of its reference.  `rois` is a host array; `out` is a device array
+   of n results.  A call with n = 1 is the plain per-frame path.  Returns
+   before the GPU finishes.  Errors: CCPT_E_INVALID, CCPT_E_UNSUPPORTED,
+   CCPT_E_NOREF, CCPT_E_HIP, CCPT_E_NOMEM. */
+int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* out,
+                     void* stream);
+
+/* Backward pass of ccpt_track_batch for L = sum_i g_d[i] . d_i + g_peak[i] C_i(d_i)
+   (implicit function theorem at the Newton maximiser; integer and grid
+   maxima are piecewise constant and carry no gradient).  `fwd` is the
+   device result array of the forward call on the same rois.  g_d: device
+   [n][2] doubles; g_peak: device [n] doubles or NULL.  g_frames: device
+   floats, the gradients of each roi packed one after another (ny*nx
+   each, row-major, no pitch), or NULL; g_ref: device floats, one ny*nx
+   block per reference in id order, summed over all rois using it, or
+   NULL.  Frames whose forward status has NONFINITE, FLAT,
+   NEWTON_FALLBACK or WINDOW_EXIT get zero gradient.  The reference set
+   must be the one used by the forward call. */
+int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_result* fwd,
+                    const double* g_d, const double* g_peak, float* g_frames, float* g_ref,
+                    void* stream);
+
+/* Poisson Fisher information of the displacement for an expected image
+   mu (Sec. IV shot-noise limit; Cramer-Rao bound = inverse): F_jl =
+   sum_r (d mu/d d_j)(d mu/d d_l) / mu(r), with the derivatives of the
+   band-limited translate mu(r - d) at d = 0.  `fisher` is a device array
+   of 3 doubles (yy, yx, xx).  Every pixel of mu must be > 0
+   (CCPT_E_INVALID otherwise, checked on the host after the copy). */
+int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* stream);
+
+/* Measures the candidate schedules for frames of size n x n in batches
+   of `batch` and keeps the fastest for later calls.  Needs a reference
+   of that size.  Synchronises the stream. */
+int ccpt_autotune(ccpt_ctx* ctx, int n, int batch, void* stream);
+
+/* Static text of a return code. */
+const char* ccpt_status_string(int code);
+
+/* Copies the message of the last failing call into buf (NUL-terminated);
+   returns the code of that call (CCPT_OK if none). */
+int ccpt_last_error(const ccpt_ctx* ctx, char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCPT_H */

@@ -1,0 +1,252 @@
+"""Python binding of libccpt (include/ccpt.h): argument marshalling only.
+
+PyTorch supplies device memory and streams; every step of the tracking
+path runs in the library's HIP kernels.  Loading fails loudly when the
+library has not been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_size_t, c_void_p
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccpt.so")
+
+# return codes
+OK = 0
+E_INVALID = -1
+E_UNSUPPORTED = -2
+E_NOREF = -3
+E_HIP = -4
+E_NONPOSITIVE_REF = -5
+E_NOMEM = -6
+
+# status bits
+ST_NONFINITE = 1
+ST_FLAT = 2
+ST_NEAR_TIE = 4
+ST_NEWTON_FALLBACK = 8
+ST_WINDOW_EXIT = 16
+
+MODES = {"ccu": 0, "ccsn": 1}
+PRECISIONS = {"fp32": 0, "bf16x2": 1, "fp16x2": 2}
+U16, F32 = 0, 1
+FLAG_GRAPH = 1
+
+RESULT_DTYPE = np.dtype([
+    ("d", "<f8", (2,)),
+    ("peak", "<f8"),
+    ("hess", "<f8", (3,)),
+    ("d_grid", "<f4", (2,)),
+    ("p", "<i4", (2,)),
+    ("status", "<u4"),
+    ("reserved", "<u4"),
+])
+RESULT_BYTES = RESULT_DTYPE.itemsize  # 72
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("mode", c_int), ("eps", c_double), ("upsample", c_int), ("window", c_double),
+                ("precision", c_int), ("newton_iters", c_int), ("flags", c_int)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("data", c_void_p), ("ny", c_int), ("nx", c_int), ("pitch", c_int), ("dtype", c_int)]
+
+
+class Roi(ctypes.Structure):
+    _fields_ = [("data", c_void_p), ("ny", c_int), ("nx", c_int), ("pitch", c_int), ("dtype", c_int),
+                ("ref_id", c_int)]
+
+
+class CcptError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ccpt error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2310_08770_amd.build.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ccpt_default_options.argtypes = [POINTER(Options)]
+        L.ccpt_default_options.restype = None
+        L.ccpt_create.argtypes = [POINTER(c_void_p), c_int, POINTER(Options)]
+        L.ccpt_create.restype = c_int
+        L.ccpt_destroy.argtypes = [c_void_p]
+        L.ccpt_destroy.restype = None
+        L.ccpt_set_reference.argtypes = [c_void_p, POINTER(Image), c_int, c_void_p]
+        L.ccpt_set_reference.restype = c_int
+        L.ccpt_track_batch.argtypes = [c_void_p, POINTER(Roi), c_int, c_void_p, c_void_p]
+        L.ccpt_track_batch.restype = c_int
+        L.ccpt_track_grad.argtypes = [c_void_p, POINTER(Roi), c_int, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p]
+        L.ccpt_track_grad.restype = c_int
+        L.ccpt_fisher.argtypes = [c_void_p, POINTER(Image), c_void_p, c_void_p]
+        L.ccpt_fisher.restype = c_int
+        L.ccpt_autotune.argtypes = [c_void_p, c_int, c_int, c_void_p]
+        L.ccpt_autotune.restype = c_int
+        L.ccpt_status_string.argtypes = [c_int]
+        L.ccpt_status_string.restype = ctypes.c_char_p
+        L.ccpt_last_error.argtypes = [c_void_p, ctypes.c_char_p, c_size_t]
+        L.ccpt_last_error.restype = c_int
+        _lib = L
+    return _lib
+
+
+EXPORTS = ["ccpt_default_options", "ccpt_create", "ccpt_destroy", "ccpt_set_reference",
+           "ccpt_track_batch", "ccpt_track_grad", "ccpt_fisher", "ccpt_autotune",
+           "ccpt_status_string", "ccpt_last_error"]
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype in (torch.uint16, torch.int16):
+        return U16
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"frames must be uint16 (or int16 bits) or float32, got {t.dtype}")
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def decode(results: torch.Tensor) -> np.ndarray:
+    """Device result buffer -> numpy structured array (RESULT_DTYPE)."""
+    raw = results.detach().reshape(-1).to("cpu", torch.uint8).numpy()
+    return raw.view(RESULT_DTYPE)
+
+
+class Tracker:
+    """A library context: options, references and workspaces on one GPU."""
+
+    def __init__(self, mode="ccu", eps=200.0, upsample=100, window=1.5, precision="fp32",
+                 newton_iters=3, graph=False, device=None):
+        L = lib()
+        o = Options()
+        L.ccpt_default_options(ctypes.byref(o))
+        o.mode = MODES[mode]
+        o.eps = float(eps)
+        o.upsample = int(upsample)
+        o.window = float(window)
+        o.precision = PRECISIONS[precision]
+        o.newton_iters = int(newton_iters)
+        o.flags = FLAG_GRAPH if graph else 0
+        self.options = o
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        h = c_void_p()
+        rc = L.ccpt_create(ctypes.byref(h), self.device.index, ctypes.byref(o))
+        if rc != OK:
+            raise CcptError(rc, L.ccpt_status_string(rc).decode())
+        self._h = h
+        self._refs = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ccpt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            buf = ctypes.create_string_buffer(512)
+            lib().ccpt_last_error(self._h, buf, 512)
+            raise CcptError(rc, buf.value.decode())
+
+    # ------------------------------------------------------------------
+    def set_reference(self, refs, stream=None):
+        """refs: one [N, N] tensor or a list of them (device, uint16/float32)."""
+        if isinstance(refs, torch.Tensor) and refs.dim() == 2:
+            refs = [refs]
+        refs = [r.contiguous() for r in refs]
+        arr = (Image * len(refs))()
+        for i, r in enumerate(refs):
+            if r.device != self.device:
+                raise ValueError("reference must live on the tracker's device")
+            arr[i] = Image(r.data_ptr(), r.shape[0], r.shape[1], r.stride(0), _dtype_code(r))
+        self._check(lib().ccpt_set_reference(self._h, arr, len(refs), c_void_p(_stream_handle(stream))))
+        self._refs = refs
+
+    def rois(self, frames, ref_ids=None):
+        """Roi array for a [n, N, N] tensor or a list of 2-D tensors."""
+        if isinstance(frames, torch.Tensor):
+            if frames.dim() == 2:
+                frames = frames[None]
+            seq = [frames[i] for i in range(frames.shape[0])]
+        else:
+            seq = list(frames)
+        n = len(seq)
+        if ref_ids is None:
+            ref_ids = [0] * n
+        arr = (Roi * n)()
+        for i, f in enumerate(seq):
+            if f.device != self.device:
+                raise ValueError("frames must live on the tracker's device")
+            if f.stride(1) != 1:
+                raise ValueError("frame rows must be contiguous")
+            arr[i] = Roi(f.data_ptr(), f.shape[0], f.shape[1], f.stride(0), _dtype_code(f), int(ref_ids[i]))
+        return arr, n
+
+    def track(self, frames, ref_ids=None, out=None, stream=None, rois=None):
+        """Tracks frames; returns the device result buffer (uint8 [n, 72]).
+        Use decode() for a numpy view.  `rois` reuses a prepared roi array."""
+        if rois is None:
+            rois = self.rois(frames, ref_ids)
+        arr, n = rois
+        if out is None:
+            out = torch.empty((n, RESULT_BYTES), dtype=torch.uint8, device=self.device)
+        self._check(lib().ccpt_track_batch(self._h, arr, n, c_void_p(out.data_ptr()),
+                                           c_void_p(_stream_handle(stream))))
+        return out
+
+    def track_grad(self, frames, fwd, g_d, g_peak=None, want_frames=True, want_ref=True,
+                   ref_ids=None, stream=None):
+        """Backward of track() for L = sum g_d . d + g_peak * C(d)."""
+        arr, n = self.rois(frames, ref_ids)
+        g_d = g_d.to(self.device, torch.float64).contiguous()
+        gp = g_peak.to(self.device, torch.float64).contiguous() if g_peak is not None else None
+        gf = gr = None
+        if want_frames:
+            total = sum(arr[i].ny * arr[i].nx for i in range(n))
+            gf = torch.empty(total, dtype=torch.float32, device=self.device)
+        if want_ref:
+            total = sum(r.shape[0] * r.shape[1] for r in self._refs)
+            gr = torch.empty(total, dtype=torch.float32, device=self.device)
+        self._check(lib().ccpt_track_grad(
+            self._h, arr, n, c_void_p(fwd.data_ptr()), c_void_p(g_d.data_ptr()),
+            c_void_p(gp.data_ptr() if gp is not None else 0),
+            c_void_p(gf.data_ptr() if gf is not None else 0),
+            c_void_p(gr.data_ptr() if gr is not None else 0),
+            c_void_p(_stream_handle(stream))))
+        return gf, gr
+
+    def fisher(self, mu, stream=None):
+        """Fisher matrix (2x2, float64 device tensor) of the displacement for
+        an expected image mu under Poisson noise."""
+        mu = mu.contiguous()
+        img = Image(mu.data_ptr(), mu.shape[0], mu.shape[1], mu.stride(0), _dtype_code(mu))
+        out = torch.empty(3, dtype=torch.float64, device=self.device)
+        self._check(lib().ccpt_fisher(self._h, ctypes.byref(img), c_void_p(out.data_ptr()),
+                                      c_void_p(_stream_handle(stream))))
+        f = out
+        return torch.stack([torch.stack([f[0], f[1]]), torch.stack([f[1], f[2]])])
+
+    def autotune(self, n, batch, stream=None):
+        self._check(lib().ccpt_autotune(self._h, int(n), int(batch), c_void_p(_stream_handle(stream))))

@@ -1,0 +1,161 @@
+// Batched complex FFTs of length L = 2^a 3^b held in LDS, in Stockham
+// (self-sorting) form: each stage reads its inputs with unit stride across
+// butterflies and writes them back already in order, so no bit reversal
+// pass is needed.  Radix 3 for the factors of 3, then radix 8, closing with
+// radix 4 or 2.  Twiddles come from an LDS table of exp(-2 pi i m / N) for
+// the transform size N of the kernel (L divides N).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ccpt {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by i * SIGN
+template <int SIGN>
+__device__ __forceinline__ float2 mul_i(float2 a) {
+  return SIGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+constexpr int fft_radix(int L, int stage) {
+  int i = 0;
+  while (L % 3 == 0) {
+    if (i == stage) return 3;
+    L /= 3;
+    ++i;
+  }
+  while (L % 8 == 0) {
+    if (i == stage) return 8;
+    L /= 8;
+    ++i;
+  }
+  if (L % 4 == 0) {
+    if (i == stage) return 4;
+    L /= 4;
+    ++i;
+  }
+  if (L % 2 == 0) {
+    if (i == stage) return 2;
+    L /= 2;
+    ++i;
+  }
+  return 1;
+}
+
+constexpr int fft_stages(int L) {
+  int s = 0;
+  while (fft_radix(L, s) > 1) ++s;
+  return s;
+}
+
+// In-register DFT of size R with exponent sign SIGN (-1 forward, +1 inverse).
+template <int R, int SIGN>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 2) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 3) {
+    const float c = -0.5f;
+    const float s = SIGN * 0.86602540378443864676f;
+    float2 a = v[0], b = v[1], d = v[2];
+    float2 t = cadd(b, d);
+    float2 u = csub(b, d);
+    v[0] = cadd(a, t);
+    float2 m = make_float2(a.x + c * t.x, a.y + c * t.y);
+    // i * s * u
+    float2 r = make_float2(-s * u.y, s * u.x);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  } else if constexpr (R == 4) {
+    float2 a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    float2 s13 = cadd(a1, a3), d13 = mul_i<SIGN>(csub(a1, a3));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  } else if constexpr (R == 8) {
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4, SIGN>(e);
+    dft<4, SIGN>(o);
+    const float h = 0.70710678118654752440f;
+    // w8^k = exp(SIGN * 2 pi i k / 8)
+    float2 o1 = make_float2(h * (o[1].x - SIGN * o[1].y), h * (o[1].y + SIGN * o[1].x));
+    float2 o2 = mul_i<SIGN>(o[2]);
+    float2 o3 = make_float2(h * (-o[3].x - SIGN * o[3].y), h * (-o[3].y + SIGN * o[3].x));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+}
+
+// One Stockham stage of radix R on `nseq` sequences of length L (sequence
+// q at src/dst + q*stride).  NS = product of the radices already applied.
+// tw: exp(-2 pi i m / NTW), m < NTW, with L | NTW.
+template <int L, int R, int SIGN, int NTW>
+__device__ __forceinline__ void fft_stage(const float2* __restrict__ src, float2* __restrict__ dst,
+                                          int nseq, int stride, int NS, const float2* tw,
+                                          int tid, int nthr) {
+  constexpr int B = L / R;
+  const int total = nseq * B;
+  for (int b = tid; b < total; b += nthr) {
+    const int q = b / B;
+    const int j = b - q * B;
+    const float2* in = src + q * stride;
+    float2* out = dst + q * stride;
+    float2 v[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) v[t] = in[j + t * B];
+    const int k = j % NS;
+    if (NS > 1) {
+      // twiddle exp(SIGN * 2 pi i t k / (NS R)) = tw[t k NTW / (NS R)] (conj for SIGN > 0)
+      const int step = NTW / (NS * R);
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        float2 w = tw[t * k * step];
+        if (SIGN > 0) w.y = -w.y;
+        v[t] = cmul(v[t], w);
+      }
+    }
+    dft<R, SIGN>(v);
+    const int base = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int t = 0; t < R; ++t) out[base + t * NS] = v[t];
+  }
+}
+
+template <int L, int SIGN, int NTW, int ST>
+__device__ __forceinline__ float2* fft_run(float2* a, float2* b, int nseq, int stride, int NS,
+                                           const float2* tw, int tid, int nthr) {
+  if constexpr (ST == fft_stages(L)) {
+    return a;
+  } else {
+    constexpr int R = fft_radix(L, ST);
+    fft_stage<L, R, SIGN, NTW>(a, b, nseq, stride, NS, tw, tid, nthr);
+    __syncthreads();
+    return fft_run<L, SIGN, NTW, ST + 1>(b, a, nseq, stride, NS * R, tw, tid, nthr);
+  }
+}
+
+// Transforms nseq sequences in `a` (b is scratch of the same size); returns
+// the buffer holding the result.  Callers must __syncthreads() before.
+template <int L, int SIGN, int NTW>
+__device__ __forceinline__ float2* fft_lds(float2* a, float2* b, int nseq, int stride,
+                                           const float2* tw) {
+  return fft_run<L, SIGN, NTW, 0>(a, b, nseq, stride, 1, tw, threadIdx.x, blockDim.x);
+}
+
+}  // namespace ccpt

@@ -1,0 +1,127 @@
+// DFT tables of the upsampled matrix DFT, built on the host in FP64 and
+// rounded (or split) to the matrix-core operand type.
+//
+//   K[m][ky] = phi_ky((m - c)/u)                       Stage A, Mp x N complex
+//   W[j][mx] = w_kx Re phi_kx((mx - c)/u) / N^2         j = kx <= N/2
+//            = -2 Im phi_kx((mx - c)/u) / N^2           j = N/2 + kx, 0 < kx < N/2
+//
+// phi_k(s) = exp(2 pi i k~ s / N) for the signed frequency k~, and
+// cos(pi s) for the Nyquist bin; w = 1 at kx = 0 and N/2, else 2.  Rows
+// m >= M and columns mx >= M are zero padding up to Mp (a multiple of 32);
+// W rows j >= N are zero padding up to Kb = N rounded up to 32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/ccpt.h"
+
+namespace ccpt {
+
+// Newton step bound when the grid was computed in split precision (px).
+constexpr double kSplitStepLimit = 0.05;
+
+// Stage B contraction length, padded for the matrix-core K step.
+constexpr int stage_b_k(int n) { return (n + 31) / 32 * 32; }
+
+struct HostTables {
+  std::vector<float2> tw;  // exp(-2 pi i m / N)
+  std::vector<char> ky;
+  std::vector<char> wb;
+  int Mp = 0;
+};
+
+inline void phi_host(int k, int n, double s, double& re, double& im) {
+  if (2 * k == n) {
+    re = std::cos(M_PI * s);
+    im = 0.0;
+    return;
+  }
+  const int kt = 2 * k < n ? k : k - n;
+  const double a = 2.0 * M_PI * (double)kt * s / (double)n;
+  re = std::cos(a);
+  im = std::sin(a);
+}
+
+// bf16 with round-to-nearest-even, and the hi/lo split x ~ hi + lo
+inline uint16_t bf16_rne(float f) {
+  uint32_t b;
+  memcpy(&b, &f, 4);
+  const uint32_t r = 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)((b + r) >> 16);
+}
+inline float bf16_to_f(uint16_t h) {
+  uint32_t b = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &b, 4);
+  return f;
+}
+inline void split_bf16(double x, uint16_t& hi, uint16_t& lo) {
+  hi = bf16_rne((float)x);
+  lo = bf16_rne((float)(x - (double)bf16_to_f(hi)));
+}
+
+inline HostTables build_tables(int n, int u, int M, int c, int precision) {
+  HostTables t;
+  t.Mp = (M + 31) / 32 * 32;
+  const int Mp = t.Mp;
+  t.tw.resize(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = 2.0 * M_PI * (double)m / (double)n;
+    t.tw[m] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  std::vector<double> kr((size_t)Mp * n, 0.0), ki((size_t)Mp * n, 0.0);
+  for (int m = 0; m < M; ++m)
+    for (int ky = 0; ky < n; ++ky)
+      phi_host(ky, n, (double)(m - c) / u, kr[(size_t)m * n + ky], ki[(size_t)m * n + ky]);
+  const int Kb = stage_b_k(n);
+  std::vector<double> w((size_t)Kb * Mp, 0.0);
+  const double inv = 1.0 / ((double)n * (double)n);
+  for (int mx = 0; mx < M; ++mx) {
+    const double s = (double)(mx - c) / u;
+    for (int kx = 0; kx <= n / 2; ++kx) {
+      double re, im;
+      phi_host(kx, n, s, re, im);
+      const double wt = (kx == 0 || 2 * kx == n) ? 1.0 : 2.0;
+      w[(size_t)kx * Mp + mx] = wt * re * inv;
+      if (kx > 0 && 2 * kx < n) w[(size_t)(n / 2 + kx) * Mp + mx] = -2.0 * im * inv;
+    }
+  }
+  if (precision == CCPT_PREC_FP32) {
+    t.ky.resize((size_t)Mp * n * sizeof(float2));
+    float2* K = (float2*)t.ky.data();
+    for (size_t i = 0; i < (size_t)Mp * n; ++i) K[i] = make_float2((float)kr[i], (float)ki[i]);
+    t.wb.resize((size_t)Kb * Mp * sizeof(float));
+    float* W = (float*)t.wb.data();
+    for (size_t i = 0; i < (size_t)Kb * Mp; ++i) W[i] = (float)w[i];
+  } else {
+    // Stage A: per (m, ky) one 32-bit word of (re, im) bf16 for hi, then lo:
+    //   ky table = [2][Mp][n] uint32  (plane 0 hi, plane 1 lo)
+    // Stage B: transposed, W^T[mx][j] bf16, planes hi and lo: [2][Mp][Kb] uint16
+    t.ky.resize((size_t)2 * Mp * n * 4);
+    uint32_t* K = (uint32_t*)t.ky.data();
+    for (size_t i = 0; i < (size_t)Mp * n; ++i) {
+      uint16_t rh, rl, ih, il;
+      split_bf16(kr[i], rh, rl);
+      split_bf16(ki[i], ih, il);
+      K[i] = (uint32_t)rh | ((uint32_t)ih << 16);
+      K[(size_t)Mp * n + i] = (uint32_t)rl | ((uint32_t)il << 16);
+    }
+    t.wb.resize((size_t)2 * Mp * Kb * 2);
+    uint16_t* W = (uint16_t*)t.wb.data();
+    for (int mx = 0; mx < Mp; ++mx)
+      for (int j = 0; j < Kb; ++j) {
+        uint16_t h, l;
+        split_bf16(w[(size_t)j * Mp + mx], h, l);
+        W[(size_t)mx * Kb + j] = h;
+        W[(size_t)Mp * Kb + (size_t)mx * Kb + j] = l;
+      }
+  }
+  return t;
+}
+
+}  // namespace ccpt

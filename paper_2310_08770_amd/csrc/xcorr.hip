@@ -1,0 +1,407 @@
+// Correlation stage of the tracker (Sec. II Eq. 4 / Eq. 7, Sec. III first
+// paragraph): prologue A = I or (I+eps)^2, forward 2-D r2c FFT, product with
+// the resident conj F[B], inverse 2-D c2r FFT and the integer-lag maximum.
+//
+// The 2-D transforms are split into a row pass (each row of N reals is
+// packed as N/2 complex values, transformed, and unpacked into N/2+1 bins)
+// and a column pass over the N/2+1 columns.  Both passes keep their data in
+// LDS and exchange it through a per-frame workspace that stays in the
+// L2/Infinity-Cache for the chunk sizes used.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "fft.h"
+
+namespace ccpt {
+
+constexpr int kThreads = 256;
+
+// largest divisor of N whose block of rows holds at most `budget` complex values
+constexpr int rows_per_block(int N, int budget) {
+  int best = 1;
+  for (int r = 1; r <= N; ++r)
+    if (N % r == 0 && r * (N / 2) <= budget) best = r;
+  return best;
+}
+
+// columns per block of the column pass: at most 2048 complex values per
+// LDS buffer, no wider than the N/2+1 columns need
+constexpr int cols_per_block(int N) {
+  int cb = 1;
+  while (cb * 2 * N <= 2048 && cb < N / 2 + 1) cb *= 2;
+  return cb;
+}
+
+__device__ __forceinline__ float load_px(const void* p, int dtype, long idx) {
+  return dtype == CCPT_U16 ? (float)((const unsigned short*)p)[idx] : ((const float*)p)[idx];
+}
+
+// Where a row pass reads its images from.
+struct ImgSrc {
+  const FrameDesc* desc;  // frames (desc[first + f]) or null
+  int first;
+  const void* data;  // when desc is null: image f at data + f * img_stride elements
+  int dtype;
+  int pitch;
+  long img_stride;
+};
+
+__device__ __forceinline__ void img_of(const ImgSrc& s, int f, const void*& data, int& dtype,
+                                       int& pitch) {
+  if (s.desc) {
+    const FrameDesc d = s.desc[s.first + f];
+    data = d.data;
+    dtype = d.dtype;
+    pitch = d.pitch;
+  } else {
+    dtype = s.dtype;
+    pitch = s.pitch;
+    data = (const char*)s.data + (size_t)f * s.img_stride * (dtype == CCPT_U16 ? 2 : 4);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max_u64(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (unsigned)__shfl_xor((int)v, o, 64));
+  return v;
+}
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o, 64));
+  return v;
+}
+
+__global__ void k_init_state(FrameState* st, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    FrameState s;
+    s.peak_key = 0;
+    s.grid_key = 0;
+    s.amin = 0xFFFFFFFFu;
+    s.amax = 0;
+    s.flags = 0;
+    s.pad = 0;
+    st[i] = s;
+  }
+}
+
+// Row pass, forward.  weight: 0 A = I, 1 B = -1/(E+eps), 2 A = (I+eps)^2.
+// Writes T[f][y][k], k < N/2+1.  With st != null records min/max of A and
+// non-finite pixels per frame.
+template <int N, int RPB>
+__global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, float eps,
+                                                       float2* __restrict__ T, FrameState* st,
+                                                       const float2* __restrict__ gtw) {
+  constexpr int L = N / 2, H = N / 2 + 1;
+  __shared__ float2 tw[N];
+  __shared__ float2 bufA[RPB * L];
+  __shared__ float2 bufB[RPB * L];
+  __shared__ unsigned red[3][kThreads / 64];
+  const int tid = threadIdx.x;
+  const int f = blockIdx.y;
+  const int y0 = blockIdx.x * RPB;
+  for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
+  const void* data;
+  int dtype, pitch;
+  img_of(src, f, data, dtype, pitch);
+  unsigned kmin = 0xFFFFFFFFu, kmax = 0, bad = 0;
+  for (int i = tid; i < RPB * L; i += kThreads) {
+    const int r = i / L, c = i - r * L;
+    const long idx = (long)(y0 + r) * pitch + 2 * c;
+    float a0 = load_px(data, dtype, idx);
+    float a1 = load_px(data, dtype, idx + 1);
+    if (weight == 1) {
+      a0 = -1.0f / (a0 + eps);
+      a1 = -1.0f / (a1 + eps);
+    } else if (weight == 2) {
+      a0 = (a0 + eps) * (a0 + eps);
+      a1 = (a1 + eps) * (a1 + eps);
+    }
+    if (!isfinite(a0) || !isfinite(a1)) bad = 1;
+    kmin = min(kmin, min(f2key(a0), f2key(a1)));
+    kmax = max(kmax, max(f2key(a0), f2key(a1)));
+    bufA[i] = make_float2(a0, a1);
+  }
+  if (st) {
+    kmin = wave_min_u32(kmin);
+    kmax = wave_max_u32(kmax);
+    bad = wave_max_u32(bad);
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = kmin;
+      red[1][tid >> 6] = kmax;
+      red[2][tid >> 6] = bad;
+    }
+  }
+  __syncthreads();
+  if (st && tid == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) {
+      kmin = min(kmin, red[0][w]);
+      kmax = max(kmax, red[1][w]);
+      bad |= red[2][w];
+    }
+    atomicMin(&st[f].amin, kmin);
+    atomicMax(&st[f].amax, kmax);
+    if (bad) atomicOr(&st[f].flags, (unsigned)CCPT_ST_NONFINITE);
+  }
+  float2* z = fft_lds<L, -1, N>(bufA, bufB, RPB, L, tw);
+  // unpack: X[k] = E[k] + W^k O[k], E = (Z[k] + conj Z[L-k]) / 2,
+  // O = (Z[k] - conj Z[L-k]) / (2i), W = exp(-2 pi i / N)
+  float2* Tf = T + (size_t)f * N * H;
+  for (int i = tid; i < RPB * H; i += kThreads) {
+    const int r = i / H, k = i - r * H;
+    const float2 zk = z[r * L + (k == L ? 0 : k)];
+    const float2 zc = cconj(z[r * L + (k == 0 ? 0 : L - k)]);
+    const float2 e = cscale(cadd(zk, zc), 0.5f);
+    const float2 d = csub(zk, zc);
+    const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // d / (2i)
+    Tf[(size_t)(y0 + r) * H + k] = cadd(e, cmul(tw[k], o));
+  }
+}
+
+enum ColKind { COL_XCORR = 0, COL_FWD = 1, COL_FWD_CONJ = 2, COL_INV = 3 };
+
+// Column pass over CB of the N/2+1 columns.
+//  COL_XCORR:    forward FFT, X = F[A] * rspec (stored to X), inverse FFT back into T
+//  COL_FWD:      forward FFT stored to `spec`
+//  COL_FWD_CONJ: conjugate of the forward FFT stored to `spec`
+//  COL_INV:      inverse FFT of `spec` stored to T
+template <int N, int CB, int KIND>
+__global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__ desc, int first,
+                                                   float2* __restrict__ T, float2* __restrict__ X,
+                                                   float2* __restrict__ spec, long spec_stride,
+                                                   const float2* __restrict__ gtw) {
+  constexpr int H = N / 2 + 1, S = N + 1;
+  __shared__ float2 tw[N];
+  __shared__ float2 bufA[CB * S];
+  __shared__ float2 bufB[CB * S];
+  const int tid = threadIdx.x;
+  const int f = blockIdx.y;
+  const int c0 = blockIdx.x * CB;
+  const int ncol = min(CB, H - c0);
+  for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
+  float2* Tf = T + (size_t)f * N * H;
+  const float2* inp = (KIND == COL_INV) ? spec + (size_t)f * spec_stride : Tf;
+  for (int i = tid; i < N * CB; i += kThreads) {
+    const int y = i / CB, c = i - y * CB;
+    bufA[c * S + y] = c < ncol ? inp[(size_t)y * H + c0 + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  if constexpr (KIND == COL_INV) {
+    float2* r = fft_lds<N, +1, N>(bufA, bufB, CB, S, tw);
+    for (int i = tid; i < N * CB; i += kThreads) {
+      const int y = i / CB, c = i - y * CB;
+      if (c < ncol) Tf[(size_t)y * H + c0 + c] = r[c * S + y];
+    }
+  } else {
+    float2* r = fft_lds<N, -1, N>(bufA, bufB, CB, S, tw);
+    if constexpr (KIND == COL_FWD || KIND == COL_FWD_CONJ) {
+      float2* out = spec + (size_t)f * spec_stride;
+      for (int i = tid; i < N * CB; i += kThreads) {
+        const int y = i / CB, c = i - y * CB;
+        if (c < ncol) {
+          float2 v = r[c * S + y];
+          if (KIND == COL_FWD_CONJ) v.y = -v.y;
+          out[(size_t)y * H + c0 + c] = v;
+        }
+      }
+    } else {
+      const float2* R = desc[first + f].rspec;
+      float2* Xf = X + (size_t)f * N * H;
+      for (int i = tid; i < N * CB; i += kThreads) {
+        const int y = i / CB, c = i - y * CB;
+        if (c < ncol) {
+          const float2 v = cmul(r[c * S + y], R[(size_t)y * H + c0 + c]);
+          Xf[(size_t)y * H + c0 + c] = v;
+          r[c * S + y] = v;
+        } else {
+          r[c * S + y] = make_float2(0.f, 0.f);
+        }
+      }
+      __syncthreads();
+      float2* o = (r == bufA) ? bufB : bufA;
+      float2* q = fft_lds<N, +1, N>(r, o, CB, S, tw);
+      for (int i = tid; i < N * CB; i += kThreads) {
+        const int y = i / CB, c = i - y * CB;
+        if (c < ncol) Tf[(size_t)y * H + c0 + c] = q[c * S + y];
+      }
+    }
+  }
+}
+
+// Row pass, inverse (c2r).  Each row's N/2+1 bins are packed into N/2
+// complex values Z = E + i O with E = (X[k] + conj X[L-k]) / 2 and
+// O = (X[k] - conj X[L-k]) W^-k / 2, transformed, and read out as the N reals
+// z[n] = a[2n] + i a[2n+1].
+// ARGMAX: per-frame maximum with ties to the lowest row-major index.
+// Otherwise the real row is scaled and stored to img (N x N per frame).
+template <int N, int RPB, bool ARGMAX>
+__global__ void __launch_bounds__(kThreads) k_rows_inv(const float2* __restrict__ T,
+                                                       FrameState* st, float* img, float scale,
+                                                       const float2* __restrict__ gtw) {
+  constexpr int L = N / 2, H = N / 2 + 1;
+  __shared__ float2 tw[N];
+  __shared__ float2 raw[RPB * H];
+  __shared__ float2 bufA[RPB * L];
+  __shared__ float2 bufB[RPB * L];
+  __shared__ unsigned long long red[kThreads / 64];
+  const int tid = threadIdx.x;
+  const int f = blockIdx.y;
+  const int y0 = blockIdx.x * RPB;
+  for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
+  const float2* Tf = T + (size_t)f * N * H + (size_t)y0 * H;
+  for (int i = tid; i < RPB * H; i += kThreads) raw[i] = Tf[i];
+  __syncthreads();
+  for (int i = tid; i < RPB * L; i += kThreads) {
+    const int r = i / L, k = i - r * L;
+    const float2 xk = raw[r * H + k];
+    const float2 xc = cconj(raw[r * H + L - k]);
+    const float2 e = cscale(cadd(xk, xc), 0.5f);
+    const float2 o = cmul(cscale(csub(xk, xc), 0.5f), cconj(tw[k]));
+    bufA[i] = make_float2(e.x - o.y, e.y + o.x);  // e + i o
+  }
+  __syncthreads();
+  float2* z = fft_lds<L, +1, N>(bufA, bufB, RPB, L, tw);
+  if constexpr (ARGMAX) {
+    unsigned long long best = 0;
+    for (int i = tid; i < RPB * L; i += kThreads) {
+      const int r = i / L, n = i - r * L;
+      const float2 v = z[i];
+      const unsigned flat = (unsigned)((y0 + r) * N + 2 * n);
+      unsigned long long k0 = peak_key(v.x, flat);
+      unsigned long long k1 = peak_key(v.y, flat + 1);
+      best = k0 > best ? k0 : best;
+      best = k1 > best ? k1 : best;
+    }
+    best = wave_max_u64(best);
+    if ((tid & 63) == 0) red[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < kThreads / 64; ++w) best = red[w] > best ? red[w] : best;
+      atomicMax(&st[f].peak_key, best);
+    }
+  } else {
+    float* out = img + (size_t)f * N * N + (size_t)y0 * N;
+    for (int i = tid; i < RPB * L; i += kThreads) {
+      const int r = i / L, n = i - r * L;
+      const float2 v = z[i];
+      out[r * N + 2 * n] = v.x * scale;
+      out[r * N + 2 * n + 1] = v.y * scale;
+    }
+  }
+}
+
+template <int N>
+static int xcorr_n(const GroupParams& g, hipStream_t s) {
+  constexpr int RPB = rows_per_block(N, 2048);
+  constexpr int CB = cols_per_block(N);
+  constexpr int H = N / 2 + 1;
+  hipLaunchKernelGGL(k_init_state, dim3((g.count + 255) / 256), dim3(256), 0, s, g.st, g.count);
+  ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0};
+  hipLaunchKernelGGL((k_rows_fwd<N, RPB>), dim3(N / RPB, g.count), dim3(kThreads), 0, s, src,
+                     g.mode == CCPT_MODE_CCSN ? 2 : 0, g.eps, g.T, g.st, g.tw);
+  hipLaunchKernelGGL((k_cols<N, CB, COL_XCORR>), dim3((H + CB - 1) / CB, g.count), dim3(kThreads),
+                     0, s, g.desc, g.first, g.T, g.X, (float2*)nullptr, 0L, g.tw);
+  hipLaunchKernelGGL((k_rows_inv<N, RPB, true>), dim3(N / RPB, g.count), dim3(kThreads), 0, s,
+                     g.T, g.st, (float*)nullptr, 1.0f, g.tw);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N>
+static int spectrum_n(const void* data, int dtype, int pitch, long img_stride, int n, int weight,
+                      float eps, int conj_out, float2* T, float2* spec, const float2* tw,
+                      hipStream_t s) {
+  constexpr int RPB = rows_per_block(N, 2048);
+  constexpr int CB = cols_per_block(N);
+  constexpr int H = N / 2 + 1;
+  ImgSrc src{nullptr, 0, data, dtype, pitch, img_stride};
+  hipLaunchKernelGGL((k_rows_fwd<N, RPB>), dim3(N / RPB, n), dim3(kThreads), 0, s, src, weight,
+                     eps, T, (FrameState*)nullptr, tw);
+  if (conj_out)
+    hipLaunchKernelGGL((k_cols<N, CB, COL_FWD_CONJ>), dim3((H + CB - 1) / CB, n), dim3(kThreads),
+                       0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, spec,
+                       (long)N * H, tw);
+  else
+    hipLaunchKernelGGL((k_cols<N, CB, COL_FWD>), dim3((H + CB - 1) / CB, n), dim3(kThreads), 0, s,
+                       (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, spec, (long)N * H, tw);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N>
+static int inverse_n(const float2* spec, int n, float scale, float2* T, float* img,
+                     const float2* tw, hipStream_t s) {
+  constexpr int RPB = rows_per_block(N, 2048);
+  constexpr int CB = cols_per_block(N);
+  constexpr int H = N / 2 + 1;
+  hipLaunchKernelGGL((k_cols<N, CB, COL_INV>), dim3((H + CB - 1) / CB, n), dim3(kThreads), 0, s,
+                     (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (float2*)spec,
+                     (long)N * H, tw);
+  hipLaunchKernelGGL((k_rows_inv<N, RPB, false>), dim3(N / RPB, n), dim3(kThreads), 0, s, T,
+                     (FrameState*)nullptr, img, scale, tw);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+#define CCPT_FOR_SIZES(X) \
+  X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
+  X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
+
+int launch_xcorr(int N, const GroupParams& g, hipStream_t s, int) {
+  switch (N) {
+#define CASE(n) \
+  case n:       \
+    return xcorr_n<n>(g, s);
+    CCPT_FOR_SIZES(CASE)
+#undef CASE
+  }
+  return -2;
+}
+
+int launch_spectrum(int N, const void* data, int dtype, int pitch, long img_stride, int n,
+                    int weight, float eps, int conj_out, float2* T, float2* spec,
+                    const float2* tw, hipStream_t s) {
+  switch (N) {
+#define CASE(nn) \
+  case nn:       \
+    return spectrum_n<nn>(data, dtype, pitch, img_stride, n, weight, eps, conj_out, T, spec, tw, s);
+    CCPT_FOR_SIZES(CASE)
+#undef CASE
+  }
+  return -2;
+}
+
+int launch_inverse(int N, const float2* spec, int n, float scale, float2* T, float* img,
+                   const float2* tw, hipStream_t s) {
+  switch (N) {
+#define CASE(nn) \
+  case nn:       \
+    return inverse_n<nn>(spec, n, scale, T, img, tw, s);
+    CCPT_FOR_SIZES(CASE)
+#undef CASE
+  }
+  return -2;
+}
+
+__global__ void k_zero(unsigned* p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+int launch_zero(void* p, size_t bytes, hipStream_t s) {
+  size_t n = bytes / 4;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (unsigned*)p, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace ccpt
