@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Throughput and latency of the tracking hot path on one MI355X.
+
+Workload (the 256x256 streaming case): 10,000 frames of 256x256 12-bit
+pixels (uint16) holding an Airy ring pattern (first zero at 8 px, peak 4000
+photons, background 50) with Poisson noise, displaced by a random walk with
+N(0, 0.3 px) steps; upsampling factor u = 100 on the 1.5-px window.
+
+A "step" is one batched call of the whole path (correlation FFTs, integer
+peak, upsampled matrix DFT, FP64 Newton) over all frames, inputs already
+resident in HBM.  Also reported: the plain per-frame path (one call and one
+synchronisation per frame), the same with a captured hipGraph, the
+roofline of the dominant kernel from HIP events, and the FP64 CPU oracle
+timed on a bounded sample of the same frames (also used to check the GPU
+results to the 1e-3 px bar).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/sec + p50/p99 per-frame latency at 256×256, batched vs plain, at ≤1e-3 px"
+
+# MI355X datasheet peaks (dense)
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x2": 2500.0, "fp16x2": 2500.0}
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def updft_flops_per_frame(n, M, precision):
+    """Algorithmic flops of the upsampled matrix DFT per frame: the complex
+    Stage A product (M x N by N x H) and the real-part Stage B product
+    (M x 2H by 2H x M); split precision runs three products per term."""
+    H = n // 2 + 1
+    f = 8.0 * M * n * H + 4.0 * M * M * H
+    return f * (3 if precision in ("bf16x2", "fp16x2") else 1)
+
+
+# ---------------------------------------------------------------- CPU baseline
+def _oracle_worker(args):
+    from threadpoolctl import threadpool_limits
+
+    frames, ref, u = args
+    from oracle import ccpt_oracle as O
+
+    out = []
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        for f in frames:
+            r = O.track(f, ref, u)
+            out.append((r["d"], r["p"], r["status"]))
+        dt = time.perf_counter() - t0
+    return out, dt
+
+
+def cpu_baseline(frames, ref, u, sample, cores):
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+
+    ref64 = np.asarray(ref, np.float32).astype(np.float64)
+    sub = frames[:sample]
+    parts = np.array_split(np.arange(len(sub)), cores)
+    jobs = [([sub[i] for i in p], ref64, u) for p in parts if len(p)]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(len(jobs), mp_context=mp.get_context("fork")) as ex:
+        res = list(ex.map(_oracle_worker, jobs))
+    wall = time.perf_counter() - t0
+    d = np.concatenate([np.array([r[0] for r in part]) for part, _ in res])
+    p = np.concatenate([np.array([r[1] for r in part]) for part, _ in res])
+    st = np.concatenate([np.array([r[2] for r in part]) for part, _ in res])
+    cpu_s = sum(dt for _, dt in res)
+    return dict(d=d, p=p, status=st, wall=wall, cpu_s=cpu_s, cores=len(jobs))
+
+
+# ---------------------------------------------------------------- GPU legs
+def time_batched(tr, frames_t, rois, out, steps, warmup, torch):
+    for _ in range(warmup):
+        tr.track(None, out=out, rois=rois)
+    torch.cuda.synchronize()
+    tr.stage_times(reset=True) if tr.options.flags & 2 else None
+    lat = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        tr.track(None, out=out, rois=rois)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    return total, np.array(lat)
+
+
+def time_plain(tr, frames_t, count, torch):
+    out = torch.empty((1, 72), dtype=torch.uint8, device=frames_t.device)
+    lat = []
+    for i in range(min(count, frames_t.shape[0])):
+        rois = tr.rois(frames_t[i:i + 1])
+        t0 = time.perf_counter()
+        tr.track(None, out=out, rois=rois)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    return np.array(lat)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=10000)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x2"])
+    ap.add_argument("--plain-frames", type=int, default=2000)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-frame legs")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain copy of this many MiB first (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every box here has one GPU "
+              "and the multi-GPU path is not built", file=sys.stderr)
+        sys.exit(2)
+
+    from synth import frames as S
+
+    t0 = time.perf_counter()
+    w = S.config2(args.frames)
+    frames = np.stack(w.frames)
+    ref = w.refs[0].astype(np.float32)
+    n, N = frames.shape[0], frames.shape[1]
+    log(f"[bench] generated {n} frames {N}x{N} in {time.perf_counter() - t0:.1f}s")
+
+    cpu = None
+    if not args.no_cpu:
+        cores = max(1, min(16, os.cpu_count() or 1))
+        sample = min(args.cpu_sample, n)
+        cpu = cpu_baseline(frames, ref, w.u, sample, cores)
+        log(f"[bench] oracle: {sample} frames in {cpu['wall']:.1f}s wall on {cpu['cores']} cores "
+            f"({cpu['cpu_s']:.1f}s CPU)")
+
+    import torch
+
+    from paper_2310_08770_amd import Tracker, decode
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    if args.copy_calib_mib:
+        a = torch.ones(args.copy_calib_mib * (1 << 18), dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"[bench] copy calibration: {args.copy_calib_mib} MiB read + written")
+    frames_t = torch.from_numpy(frames).to(dev)
+    ref_t = torch.from_numpy(ref).to(dev)
+    M = int(np.ceil(1.5 * w.u - 1e-9))
+
+    # ---- batched, headline precision, profiled for the roofline
+    tr = Tracker(upsample=w.u, precision=args.precision, profile=True)
+    tr.set_reference(ref_t)
+    rois = tr.rois(frames_t)
+    out = torch.empty((n, 72), dtype=torch.uint8, device=dev)
+    total, lat = time_batched(tr, frames_t, rois, out, args.steps, args.warmup, torch)
+    stages = tr.stage_times(reset=True)
+    res = decode(out)
+    value = n * args.steps / total
+    log(f"[bench] batched {args.precision}: {value:,.0f} frames/s, step p50 {np.median(lat)*1e3:.2f} ms")
+    stage_ms = {k: v[0] / args.steps for k, v in stages.items() if v[1]}
+    upd_ms, upd_launches = stages["updft"]
+    per_launch_ms = upd_ms / max(1, upd_launches)
+    frames_per_launch = n * args.steps / max(1, upd_launches)
+    flops_launch = updft_flops_per_frame(N, M, args.precision) * frames_per_launch
+    achieved = flops_launch / (per_launch_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    roofline = {
+        "kernel": f"k_updft_{'f32' if args.precision == 'fp32' else 'bf16x2'}<{N}>",
+        "bound": "mfma",
+        "achieved": round(achieved, 2),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": None,
+        "launch_ms": round(per_launch_ms, 4),
+        "frames_per_launch": round(frames_per_launch, 1),
+        "flops_per_frame": updft_flops_per_frame(N, M, args.precision),
+    }
+    tr.close()
+
+    # ---- other legs
+    legs = {}
+    other = "bf16x2" if args.precision == "fp32" else "fp32"
+    try:
+        tr2 = Tracker(upsample=w.u, precision=other)
+        tr2.set_reference(ref_t)
+        out2 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
+        tot2, lat2 = time_batched(tr2, frames_t, tr2.rois(frames_t), out2, max(3, args.steps // 3), 2, torch)
+        r2 = decode(out2)
+        legs[f"batched_{other}"] = dict(frames_per_s=round(n * max(3, args.steps // 3) / tot2, 1),
+                                        p50_ms=round(float(np.median(lat2)) * 1e3, 3),
+                                        p99_ms=round(float(np.percentile(lat2, 99)) * 1e3, 3))
+        tr2.close()
+    except Exception as e:  # the other precision may not be available
+        r2 = None
+        legs[f"batched_{other}"] = dict(error=str(e)[:200])
+
+    if not args.no_plain:
+        for name, graph in (("plain", False), ("graph_stream", True)):
+            trp = Tracker(upsample=w.u, precision="fp32", graph=graph)
+            trp.set_reference(ref_t)
+            time_plain(trp, frames_t, 50, torch)  # warm-up (captures the graph)
+            lp = time_plain(trp, frames_t, args.plain_frames, torch)
+            legs[name] = dict(frames_per_s=round(len(lp) / lp.sum(), 1),
+                              p50_ms=round(float(np.median(lp)) * 1e3, 4),
+                              p99_ms=round(float(np.percentile(lp, 99)) * 1e3, 4),
+                              frames=len(lp))
+            log(f"[bench] {name}: p50 {legs[name]['p50_ms']:.3f} ms p99 {legs[name]['p99_ms']:.3f} ms")
+            trp.close()
+
+    # ---- accuracy against the oracle sample
+    accuracy = None
+    cpu_json = None
+    if cpu is not None:
+        k = len(cpu["d"])
+        ok = (cpu["status"] & (4 | 8 | 16)) == 0
+        err = np.max(np.abs(res["d"][:k] - cpu["d"]), axis=1)
+        peaks_equal = np.all(res["p"][:k] == cpu["p"], axis=1)
+        accuracy = dict(frames_checked=int(k), max_err_px=float(err[ok].max()),
+                        mean_err_px=float(err[ok].mean()), integer_peak_agreement=float(peaks_equal.mean()),
+                        oracle_fallbacks=int((~ok).sum()))
+        if r2 is not None:
+            e2 = np.max(np.abs(r2["d"][:k] - cpu["d"]), axis=1)
+            accuracy[f"max_err_px_{other}"] = float(e2[ok].max())
+        cpu_json = {
+            "value": round(k / cpu["wall"], 2),
+            "unit": "frames/s",
+            "cores": cpu["cores"],
+            "kind": "oracle",
+            "sample": f"first {k} of the {n} frames (256x256, u=100), FP64 numpy oracle, "
+                      f"one single-threaded process per core; {cpu['cpu_s']:.1f} s of CPU work",
+            "p50_ms_per_frame_per_core": round(1e3 * cpu["cpu_s"] / k, 3),
+            "cpu": platform.processor() or platform.machine(),
+        }
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {
+            "workload": f"airy256_u100: {n} frames of {N}x{N} uint16 (12-bit) Airy spots, random walk, "
+                        f"u=100, 1.5-px window (M={M}), CC-U, {args.precision} upsampled DFT, FP64 Newton x3",
+            "frames_per_step": n,
+            "upsample": w.u,
+        },
+        "batched_latency": {"p50_ms": round(float(np.median(lat)) * 1e3, 4),
+                            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4)},
+        "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
+        "legs": legs,
+        "roofline": roofline,
+        "cpu_baseline": cpu_json,
+        "accuracy": accuracy,
+        "hbm_bytes_per_frame": int(N * N * 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,8 +85,22 @@ enum ccpt_precision {
 
 enum ccpt_dtype { CCPT_U16 = 0, CCPT_F32 = 1 };
 
-#define CCPT_FLAG_GRAPH 1 /* capture each batch shape once in a hipGraph and
-                             replay it on later calls */
+#define CCPT_FLAG_GRAPH 1   /* capture each batch shape once in a hipGraph and
+                               replay it on later calls */
+#define CCPT_FLAG_PROFILE 2 /* bracket every kernel launch with HIP events on the
+                               call's stream (measurement; disables graphs) */
+
+/* stage ids of ccpt_stage_times */
+enum ccpt_stage {
+  CCPT_STAGE_INIT = 0,     /* per-frame state reset */
+  CCPT_STAGE_ROWS_FWD = 1, /* prologue + row r2c FFTs */
+  CCPT_STAGE_COLS = 2,     /* column FFTs, cross-power spectrum, inverse column FFTs */
+  CCPT_STAGE_ROWS_INV = 3, /* row c2r FFTs + integer peak */
+  CCPT_STAGE_UPDFT = 4,    /* upsampled matrix DFT + grid maximum */
+  CCPT_STAGE_NEWTON = 5,   /* FP64 Newton refinement + result */
+  CCPT_STAGE_GRAD = 6,     /* all kernels of ccpt_track_grad */
+  CCPT_NUM_STAGES = 7
+};
 
 typedef struct ccpt_options {
   int mode;         /* ccpt_mode */
@@ -187,6 +201,12 @@ int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* strea
    of `batch` and keeps the fastest for later calls.  Needs a reference
    of that size.  Synchronises the stream. */
 int ccpt_autotune(ccpt_ctx* ctx, int n, int batch, void* stream);
+
+/* With CCPT_FLAG_PROFILE: total GPU time (ms) and number of launches of
+   each stage recorded since the last reset, summed over chunks and calls.
+   ms and launches are host arrays of n_stages entries.  Waits for the
+   recorded events.  reset != 0 clears the record afterwards. */
+int ccpt_stage_times(ccpt_ctx* ctx, double* ms, int* launches, int n_stages, int reset);
 
 /* Static text of a return code. */
 const char* ccpt_status_string(int code);

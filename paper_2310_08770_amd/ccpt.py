@@ -36,6 +36,8 @@ MODES = {"ccu": 0, "ccsn": 1}
 PRECISIONS = {"fp32": 0, "bf16x2": 1, "fp16x2": 2}
 U16, F32 = 0, 1
 FLAG_GRAPH = 1
+FLAG_PROFILE = 2
+STAGES = ["init", "rows_fwd", "cols", "rows_inv", "updft", "newton", "grad"]
 
 RESULT_DTYPE = np.dtype([
     ("d", "<f8", (2,)),
@@ -96,6 +98,8 @@ def lib():
         L.ccpt_fisher.restype = c_int
         L.ccpt_autotune.argtypes = [c_void_p, c_int, c_int, c_void_p]
         L.ccpt_autotune.restype = c_int
+        L.ccpt_stage_times.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int), c_int, c_int]
+        L.ccpt_stage_times.restype = c_int
         L.ccpt_status_string.argtypes = [c_int]
         L.ccpt_status_string.restype = ctypes.c_char_p
         L.ccpt_last_error.argtypes = [c_void_p, ctypes.c_char_p, c_size_t]
@@ -105,7 +109,7 @@ def lib():
 
 
 EXPORTS = ["ccpt_default_options", "ccpt_create", "ccpt_destroy", "ccpt_set_reference",
-           "ccpt_track_batch", "ccpt_track_grad", "ccpt_fisher", "ccpt_autotune",
+           "ccpt_track_batch", "ccpt_track_grad", "ccpt_fisher", "ccpt_autotune", "ccpt_stage_times",
            "ccpt_status_string", "ccpt_last_error"]
 
 
@@ -133,7 +137,7 @@ class Tracker:
     """A library context: options, references and workspaces on one GPU."""
 
     def __init__(self, mode="ccu", eps=200.0, upsample=100, window=1.5, precision="fp32",
-                 newton_iters=3, graph=False, device=None):
+                 newton_iters=3, graph=False, profile=False, device=None):
         L = lib()
         o = Options()
         L.ccpt_default_options(ctypes.byref(o))
@@ -143,7 +147,7 @@ class Tracker:
         o.window = float(window)
         o.precision = PRECISIONS[precision]
         o.newton_iters = int(newton_iters)
-        o.flags = FLAG_GRAPH if graph else 0
+        o.flags = (FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0)
         self.options = o
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         h = c_void_p()
@@ -189,7 +193,18 @@ class Tracker:
         if isinstance(frames, torch.Tensor):
             if frames.dim() == 2:
                 frames = frames[None]
-            seq = [frames[i] for i in range(frames.shape[0])]
+            if frames.device != self.device:
+                raise ValueError("frames must live on the tracker's device")
+            if frames.stride(2) != 1:
+                raise ValueError("frame rows must be contiguous")
+            n, ny, nx = frames.shape
+            ids = [0] * n if ref_ids is None else ref_ids
+            base, step, es = frames.data_ptr(), frames.stride(0), frames.element_size()
+            pitch, code = frames.stride(1), _dtype_code(frames)
+            arr = (Roi * n)()
+            for i in range(n):
+                arr[i] = Roi(base + i * step * es, ny, nx, pitch, code, int(ids[i]))
+            return arr, n
         else:
             seq = list(frames)
         n = len(seq)
@@ -247,6 +262,14 @@ class Tracker:
                                       c_void_p(_stream_handle(stream))))
         f = out
         return torch.stack([torch.stack([f[0], f[1]]), torch.stack([f[1], f[2]])])
+
+    def stage_times(self, reset=True):
+        """{stage: (total ms, launches)} recorded with profile=True."""
+        k = len(STAGES)
+        ms = (c_double * k)()
+        cnt = (c_int * k)()
+        self._check(lib().ccpt_stage_times(self._h, ms, cnt, k, 1 if reset else 0))
+        return {STAGES[i]: (ms[i], cnt[i]) for i in range(k)}
 
     def autotune(self, n, batch, stream=None):
         self._check(lib().ccpt_autotune(self._h, int(n), int(batch), c_void_p(_stream_handle(stream))))

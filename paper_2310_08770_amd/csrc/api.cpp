@@ -73,6 +73,23 @@ struct ccpt_ctx {
   hipEvent_t desc_evt = nullptr;
   // captured graphs
   std::map<GraphKey, hipGraphExec_t> graphs;
+  // profiling: events bracketing each launch
+  struct Span {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Span> spans;
+  std::vector<hipEvent_t> ev_pool;
+  hipStream_t cur_stream = nullptr;
+  hipEvent_t open_ev = nullptr;
+  // adjoint: packed-gradient offsets + accumulator pointers, accumulators
+  void* gsmall = nullptr;
+  size_t gsmall_cap = 0;
+  char* h_small = nullptr;
+  size_t h_small_cap = 0;
+  hipEvent_t small_evt = nullptr;
+  void* acc_buf = nullptr;
+  size_t acc_cap = 0;
   // errors
   int last_code = CCPT_OK;
   std::string last_msg;
@@ -151,30 +168,42 @@ int ensure_ws(ccpt_ctx* ctx, size_t bytes) {
   return CCPT_OK;
 }
 
-size_t frame_ws_bytes(int n) {
-  const size_t spec = (size_t)n * (n / 2 + 1) * sizeof(float2);
-  return 2 * spec + sizeof(FrameState);
+size_t spec_elems(int n) { return (size_t)n * (n / 2 + 1); }
+
+size_t split_words(int n) { return (size_t)2 * (n / 2) * xb_pitch(n); }
+
+size_t frame_ws_bytes(int n, int precision) {
+  size_t b = 2 * spec_elems(n) * sizeof(float2) + sizeof(FrameState);
+  if (precision != CCPT_PREC_FP32) b += split_words(n) * sizeof(unsigned);
+  return b;
 }
 
-int default_chunk(int n) {
-  // keep the chunk's two spectra well inside the 256 MB Infinity Cache
+int default_chunk(int n, int precision) {
+  // keep the chunk's spectra well inside the 256 MB Infinity Cache
   const size_t budget = (size_t)192 << 20;
-  int c = (int)(budget / frame_ws_bytes(n));
+  int c = (int)(budget / frame_ws_bytes(n, precision));
   return std::max(1, std::min(c, 4096));
 }
 
 int chunk_for(const ccpt_ctx* ctx, int n) {
   auto it = ctx->sched.find(n);
   if (it != ctx->sched.end() && it->second.chunk > 0) return it->second.chunk;
-  return default_chunk(n);
+  return default_chunk(n, ctx->o.precision);
 }
 
-// Carves the workspace for a chunk of `chunk` frames of size n.
-void carve(ccpt_ctx* ctx, int n, int chunk, float2*& T, float2*& X, FrameState*& st) {
-  const size_t spec = (size_t)n * (n / 2 + 1);
-  T = (float2*)ctx->ws;
-  X = T + spec * chunk;
-  st = (FrameState*)(X + spec * chunk);
+// Carves the workspace for a chunk of `chunk` frames of size n (every part
+// 16-byte aligned: spectra rows hold an even number of float2).
+void carve(ccpt_ctx* ctx, int n, int chunk, GroupParams& g) {
+  const size_t spec = spec_elems(n);
+  g.T = (float2*)ctx->ws;
+  g.X = g.T + spec * chunk;
+  char* p = (char*)(g.X + spec * chunk);
+  g.Xb = nullptr;
+  if (ctx->o.precision != CCPT_PREC_FP32) {
+    g.Xb = (unsigned*)p;
+    p += split_words(n) * sizeof(unsigned) * chunk;
+  }
+  g.st = (FrameState*)p;
 }
 
 int check_image(ccpt_ctx* ctx, const void* data, int ny, int nx, int pitch, int dtype,
@@ -206,24 +235,158 @@ GroupParams base_params(ccpt_ctx* ctx, int n) {
   return g;
 }
 
+hipEvent_t pool_event(ccpt_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void mark_cb(void* user, int stage, int begin) {
+  ccpt_ctx* ctx = (ccpt_ctx*)user;
+  hipEvent_t e = pool_event(ctx);
+  if (!e) return;
+  (void)hipEventRecord(e, ctx->cur_stream);
+  if (begin) {
+    ctx->open_ev = e;
+  } else if (ctx->open_ev) {
+    ctx->spans.push_back({stage, ctx->open_ev, e});
+    ctx->open_ev = nullptr;
+  }
+}
+
+Marker marker_of(ccpt_ctx* ctx, hipStream_t s) {
+  Marker m;
+  if (ctx->o.flags & CCPT_FLAG_PROFILE) {
+    ctx->cur_stream = s;
+    m.fn = mark_cb;
+    m.user = ctx;
+  }
+  return m;
+}
+
 // Launches the whole tracking sequence for one size group, chunk by chunk.
 int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int count,
               ccpt_result* out, hipStream_t s) {
   const int chunk = std::min(count, chunk_for(ctx, n));
   SizeTables& t = ctx->tables[n];
   UpdftTables ut{t.ky, t.wb, t.Mp, ctx->o.precision};
+  const Marker mark = marker_of(ctx, s);
   for (int c0 = 0; c0 < count; c0 += chunk) {
     GroupParams g = base_params(ctx, n);
     g.desc = d_desc;
     g.first = first + c0;
     g.count = std::min(chunk, count - c0);
     g.out = out;
-    carve(ctx, n, chunk, g.T, g.X, g.st);
-    if (launch_xcorr(n, g, s, 0)) return fail(ctx, CCPT_E_HIP, "correlation launch failed");
+    carve(ctx, n, chunk, g);
+    if (launch_xcorr(n, g, s, mark)) return fail(ctx, CCPT_E_HIP, "correlation launch failed");
+    mark(CCPT_STAGE_UPDFT, 1);
     if (launch_updft(n, g, ut, s)) return fail(ctx, CCPT_E_HIP, "upsampled DFT launch failed");
+    mark(CCPT_STAGE_UPDFT, 0);
+    mark(CCPT_STAGE_NEWTON, 1);
     if (launch_newton(n, g, step_limit(ctx), s))
       return fail(ctx, CCPT_E_HIP, "Newton launch failed");
+    mark(CCPT_STAGE_NEWTON, 0);
   }
+  return CCPT_OK;
+}
+
+
+// Validated, size-grouped descriptors of a roi array.
+struct Plan {
+  std::vector<FrameDesc> desc;  // grouped by size, largest first
+  std::vector<int> sig;         // (size, count) pairs of the groups
+};
+
+int plan_rois(ccpt_ctx* ctx, const ccpt_roi* rois, int n, Plan& plan) {
+  if (ctx->refs.empty()) return fail(ctx, CCPT_E_NOREF, "no reference set");
+  for (int i = 0; i < n; ++i) {
+    const ccpt_roi& r = rois[i];
+    int rc = check_image(ctx, r.data, r.ny, r.nx, r.pitch, r.dtype, "roi", i);
+    if (rc) return rc;
+    if (r.ref_id < 0 || r.ref_id >= (int)ctx->refs.size())
+      return fail(ctx, CCPT_E_NOREF, "roi %d: reference id %d not set", i, r.ref_id);
+    if (ctx->refs[r.ref_id].n != r.nx)
+      return fail(ctx, CCPT_E_INVALID, "roi %d: size %d differs from reference %d (%d)", i, r.nx,
+                  r.ref_id, ctx->refs[r.ref_id].n);
+  }
+  // group by size, largest first (they take longest); stable within a size
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return rois[a].nx > rois[b].nx; });
+  plan.desc.resize(n);
+  plan.sig.clear();
+  for (int k = 0; k < n; ++k) {
+    const ccpt_roi& r = rois[order[k]];
+    FrameDesc d;
+    d.data = r.data;
+    d.rspec = ctx->refs[r.ref_id].spec;
+    d.pitch = r.pitch;
+    d.dtype = r.dtype;
+    d.out_idx = order[k];
+    d.ref_id = r.ref_id;
+    plan.desc[k] = d;
+    if (plan.sig.empty() || plan.sig[plan.sig.size() - 2] != r.nx) {
+      plan.sig.push_back(r.nx);
+      plan.sig.push_back(0);
+    }
+    plan.sig.back()++;
+  }
+  return CCPT_OK;
+}
+
+// Copies the descriptors to the context's device table through a pinned
+// staging buffer; skipped when identical to the previous upload.
+int upload_desc(ccpt_ctx* ctx, const std::vector<FrameDesc>& desc, hipStream_t s) {
+  const size_t n = desc.size();
+  const size_t bytes = n * sizeof(FrameDesc);
+  if (n > ctx->desc_cap) {
+    HIP_CHECK(ctx, hipDeviceSynchronize());
+    drop_graphs(ctx);
+    if (ctx->d_desc) (void)hipFree(ctx->d_desc);
+    if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
+    ctx->d_desc = nullptr;
+    ctx->h_desc = nullptr;
+    size_t cap = std::max<size_t>(n, 64);
+    if (hipMalloc(&ctx->d_desc, cap * sizeof(FrameDesc)) != hipSuccess ||
+        hipHostMalloc(&ctx->h_desc, cap * sizeof(FrameDesc), hipHostMallocDefault) != hipSuccess) {
+      ctx->desc_cap = 0;
+      return fail(ctx, CCPT_E_NOMEM, "descriptor table");
+    }
+    ctx->desc_cap = cap;
+    ctx->last_desc.clear();
+  }
+  const bool same = ctx->last_desc.size() == n &&
+                    memcmp(ctx->last_desc.data(), desc.data(), bytes) == 0;
+  if (!same) {
+    HIP_CHECK(ctx, hipEventSynchronize(ctx->desc_evt));
+    memcpy(ctx->h_desc, desc.data(), bytes);
+    HIP_CHECK(ctx, hipMemcpyAsync(ctx->d_desc, ctx->h_desc, bytes, hipMemcpyHostToDevice, s));
+    HIP_CHECK(ctx, hipEventRecord(ctx->desc_evt, s));
+    ctx->last_desc = desc;
+  }
+  return CCPT_OK;
+}
+
+// Device buffer owned by the context, grown on demand.
+int ensure_buf(ccpt_ctx* ctx, void*& p, size_t& cap, size_t bytes) {
+  if (bytes <= cap) return CCPT_OK;
+  if (p) {
+    HIP_CHECK(ctx, hipDeviceSynchronize());
+    (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+    return fail(ctx, CCPT_E_NOMEM, "buffer of %zu bytes", bytes);
+  }
+  cap = bytes;
   return CCPT_OK;
 }
 
@@ -292,7 +455,8 @@ int ccpt_create(ccpt_ctx** out, int device, const ccpt_options* opts) {
   ctx->M = M;
   ctx->c = M / 2;
   if (hipSetDevice(device) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->desc_evt, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->desc_evt, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->small_evt, hipEventDisableTiming) != hipSuccess) {
     delete ctx;
     return CCPT_E_HIP;
   }
@@ -305,6 +469,11 @@ void ccpt_destroy(ccpt_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& sp : ctx->spans) {
+    (void)hipEventDestroy(sp.a);
+    (void)hipEventDestroy(sp.b);
+  }
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (auto& kv : ctx->tables) {
     (void)hipFree(kv.second.tw);
     (void)hipFree(kv.second.ky);
@@ -318,6 +487,10 @@ void ccpt_destroy(ccpt_ctx* ctx) {
   if (ctx->d_desc) (void)hipFree(ctx->d_desc);
   if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
   if (ctx->desc_evt) (void)hipEventDestroy(ctx->desc_evt);
+  if (ctx->small_evt) (void)hipEventDestroy(ctx->small_evt);
+  if (ctx->gsmall) (void)hipFree(ctx->gsmall);
+  if (ctx->acc_buf) (void)hipFree(ctx->acc_buf);
+  if (ctx->h_small) (void)hipHostFree(ctx->h_small);
   delete ctx;
 }
 
@@ -400,78 +573,23 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
   if (!ctx) return CCPT_E_INVALID;
   if (n < 0 || (n > 0 && (!rois || !out))) return fail(ctx, CCPT_E_INVALID, "bad roi array");
   if (n == 0) return CCPT_OK;
-  if (ctx->refs.empty()) return fail(ctx, CCPT_E_NOREF, "no reference set");
   int rc = set_device(ctx);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
-  for (int i = 0; i < n; ++i) {
-    const ccpt_roi& r = rois[i];
-    rc = check_image(ctx, r.data, r.ny, r.nx, r.pitch, r.dtype, "roi", i);
-    if (rc) return rc;
-    if (r.ref_id < 0 || r.ref_id >= (int)ctx->refs.size())
-      return fail(ctx, CCPT_E_NOREF, "roi %d: reference id %d not set", i, r.ref_id);
-    if (ctx->refs[r.ref_id].n != r.nx)
-      return fail(ctx, CCPT_E_INVALID, "roi %d: size %d differs from reference %d (%d)", i, r.nx,
-                  r.ref_id, ctx->refs[r.ref_id].n);
-  }
-  // group by size, largest first (they take longest)
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return rois[a].nx > rois[b].nx; });
-  std::vector<FrameDesc> desc(n);
-  std::vector<int> sig;
+  Plan plan;
+  rc = plan_rois(ctx, rois, n, plan);
+  if (rc) return rc;
+  const std::vector<int>& sig = plan.sig;
   size_t ws_need = 0;
-  for (int k = 0; k < n; ++k) {
-    const ccpt_roi& r = rois[order[k]];
-    FrameDesc d;
-    d.data = r.data;
-    d.rspec = ctx->refs[r.ref_id].spec;
-    d.pitch = r.pitch;
-    d.dtype = r.dtype;
-    d.out_idx = order[k];
-    d.pad = 0;
-    desc[k] = d;
-    if (sig.empty() || sig[sig.size() - 2] != r.nx) {
-      sig.push_back(r.nx);
-      sig.push_back(0);
-    }
-    sig.back()++;
-  }
   for (size_t gi = 0; gi < sig.size(); gi += 2) {
     const int nn = sig[gi], cnt = sig[gi + 1];
     const int chunk = std::min(cnt, chunk_for(ctx, nn));
-    ws_need = std::max(ws_need, frame_ws_bytes(nn) * (size_t)chunk + 256);
+    ws_need = std::max(ws_need, frame_ws_bytes(nn, ctx->o.precision) * (size_t)chunk + 256);
   }
   rc = ensure_ws(ctx, ws_need);
   if (rc) return rc;
-  // descriptor upload (skipped when identical to the previous call)
-  const size_t bytes = (size_t)n * sizeof(FrameDesc);
-  if ((size_t)n > ctx->desc_cap) {
-    HIP_CHECK(ctx, hipDeviceSynchronize());
-    drop_graphs(ctx);
-    if (ctx->d_desc) (void)hipFree(ctx->d_desc);
-    if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
-    ctx->d_desc = nullptr;
-    ctx->h_desc = nullptr;
-    size_t cap = std::max<size_t>(n, 64);
-    if (hipMalloc(&ctx->d_desc, cap * sizeof(FrameDesc)) != hipSuccess ||
-        hipHostMalloc(&ctx->h_desc, cap * sizeof(FrameDesc), hipHostMallocDefault) != hipSuccess) {
-      ctx->desc_cap = 0;
-      return fail(ctx, CCPT_E_NOMEM, "descriptor table");
-    }
-    ctx->desc_cap = cap;
-    ctx->last_desc.clear();
-  }
-  const bool same = ctx->last_desc.size() == (size_t)n &&
-                    memcmp(ctx->last_desc.data(), desc.data(), bytes) == 0;
-  if (!same) {
-    HIP_CHECK(ctx, hipEventSynchronize(ctx->desc_evt));
-    memcpy(ctx->h_desc, desc.data(), bytes);
-    HIP_CHECK(ctx, hipMemcpyAsync(ctx->d_desc, ctx->h_desc, bytes, hipMemcpyHostToDevice, s));
-    HIP_CHECK(ctx, hipEventRecord(ctx->desc_evt, s));
-    ctx->last_desc = desc;
-  }
+  rc = upload_desc(ctx, plan.desc, s);
+  if (rc) return rc;
 
   auto launch_all = [&]() -> int {
     int first = 0;
@@ -484,7 +602,8 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
     return CCPT_OK;
   };
 
-  const bool use_graph = (ctx->o.flags & CCPT_FLAG_GRAPH) && s != nullptr;
+  const bool use_graph = (ctx->o.flags & CCPT_FLAG_GRAPH) && !(ctx->o.flags & CCPT_FLAG_PROFILE) &&
+                         s != nullptr;
   if (!use_graph) return launch_all();
   GraphKey key{sig, out, s};
   auto it = ctx->graphs.find(key);
@@ -505,15 +624,198 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
   return CCPT_OK;
 }
 
-int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi*, int, const ccpt_result*, const double*,
-                    const double*, float*, float*, void*) {
+int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_result* fwd,
+                    const double* g_d, const double* g_peak, float* g_frames, float* g_ref,
+                    void* stream) {
   if (!ctx) return CCPT_E_INVALID;
-  return fail(ctx, CCPT_E_UNSUPPORTED, "gradient not built yet");
+  if (n < 0 || (n > 0 && (!rois || !fwd || !g_d)))
+    return fail(ctx, CCPT_E_INVALID, "bad gradient arguments");
+  if (n == 0 || (!g_frames && !g_ref)) return CCPT_OK;
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Plan plan;
+  rc = plan_rois(ctx, rois, n, plan);
+  if (rc) return rc;
+  const int nrefs = (int)ctx->refs.size();
+  // packed offsets of the frame gradients (roi order) and of the reference gradients
+  std::vector<long> goff(n);
+  long acc_el = 0;
+  for (int i = 0; i < n; ++i) {
+    goff[i] = acc_el;
+    acc_el += (long)rois[i].ny * rois[i].nx;
+  }
+  std::vector<long> roff(nrefs), aoff(nrefs);
+  long ro = 0, ao = 0;
+  for (int r = 0; r < nrefs; ++r) {
+    const int nn = ctx->refs[r].n;
+    roff[r] = ro;
+    ro += (long)nn * nn;
+    aoff[r] = ao;
+    ao += (long)spec_elems(nn);
+  }
+  // workspace per frame: F[A], QA, QB, T spectra and one image
+  auto per_frame = [](int nn) { return 4 * spec_elems(nn) * sizeof(float2) + (size_t)nn * nn * 4; };
+  const size_t budget = (size_t)256 << 20;
+  size_t ws_need = 0, img_need = 0;
+  for (size_t gi = 0; gi < plan.sig.size(); gi += 2) {
+    const int nn = plan.sig[gi], cnt = plan.sig[gi + 1];
+    const int chunk = std::max(1, std::min<int>(cnt, (int)(budget / per_frame(nn))));
+    ws_need = std::max(ws_need, per_frame(nn) * chunk + 256);
+  }
+  for (int r = 0; r < nrefs; ++r)
+    img_need = std::max(img_need, per_frame(ctx->refs[r].n) + 256);
+  rc = ensure_ws(ctx, std::max(ws_need, img_need));
+  if (rc) return rc;
+  const size_t small_bytes = (size_t)n * sizeof(long) + (size_t)nrefs * sizeof(void*);
+  rc = ensure_buf(ctx, ctx->gsmall, ctx->gsmall_cap, small_bytes);
+  if (rc) return rc;
+  if (g_ref) {
+    rc = ensure_buf(ctx, ctx->acc_buf, ctx->acc_cap, (size_t)ao * sizeof(float2));
+    if (rc) return rc;
+  }
+  rc = upload_desc(ctx, plan.desc, s);
+  if (rc) return rc;
+  // small table upload through pinned staging
+  HIP_CHECK(ctx, hipEventSynchronize(ctx->small_evt));
+  if (small_bytes > ctx->h_small_cap) {
+    if (ctx->h_small) (void)hipHostFree(ctx->h_small);
+    ctx->h_small = nullptr;
+    ctx->h_small_cap = 0;
+    if (hipHostMalloc(&ctx->h_small, small_bytes, hipHostMallocDefault) != hipSuccess)
+      return fail(ctx, CCPT_E_NOMEM, "pinned staging");
+    ctx->h_small_cap = small_bytes;
+  }
+  memcpy(ctx->h_small, goff.data(), (size_t)n * sizeof(long));
+  float2** accp = (float2**)(ctx->h_small + (size_t)n * sizeof(long));
+  for (int r = 0; r < nrefs; ++r)
+    accp[r] = g_ref ? (float2*)ctx->acc_buf + aoff[r] : nullptr;
+  HIP_CHECK(ctx, hipMemcpyAsync(ctx->gsmall, ctx->h_small, small_bytes, hipMemcpyHostToDevice, s));
+  HIP_CHECK(ctx, hipEventRecord(ctx->small_evt, s));
+  const long* d_goff = (const long*)ctx->gsmall;
+  float2* const* d_acc = (float2* const*)((char*)ctx->gsmall + (size_t)n * sizeof(long));
+  if (g_ref && launch_zero(ctx->acc_buf, (size_t)ao * sizeof(float2), s))
+    return fail(ctx, CCPT_E_HIP, "zero launch failed");
+
+  const Marker mark = marker_of(ctx, s);
+  const int mode = ctx->o.mode;
+  const float eps = (float)ctx->o.eps;
+  int first = 0;
+  mark(CCPT_STAGE_GRAD, 1);
+  for (size_t gi = 0; gi < plan.sig.size(); gi += 2) {
+    const int nn = plan.sig[gi], cnt = plan.sig[gi + 1];
+    const int chunk = std::max(1, std::min<int>(cnt, (int)(budget / per_frame(nn))));
+    const float2* tw = ctx->tables[nn].tw;
+    const size_t spec = spec_elems(nn);
+    for (int c0 = 0; c0 < cnt; c0 += chunk) {
+      const int count = std::min(chunk, cnt - c0);
+      float2* T = (float2*)ctx->ws;
+      float2* FA = T + spec * chunk;
+      float2* QA = FA + spec * chunk;
+      float2* QB = QA + spec * chunk;
+      float* img = (float*)(QB + spec * chunk);
+      const int f0 = first + c0;
+      if (launch_frame_spectra(nn, ctx->d_desc, f0, count, mode, eps, T, FA, tw, s) ||
+          launch_grad_psi(nn, ctx->d_desc, f0, count, fwd, g_d, g_peak, FA, QA,
+                          g_ref ? QB : nullptr, s))
+        return fail(ctx, CCPT_E_HIP, "gradient launch failed");
+      if (g_frames && (launch_inverse(nn, QA, count, 2.0f, T, img, tw, s) ||
+                       launch_grad_frames(nn, ctx->d_desc, f0, count, img, d_goff, g_frames, mode,
+                                          eps, s)))
+        return fail(ctx, CCPT_E_HIP, "frame gradient launch failed");
+      if (g_ref && launch_ref_accum(nn, ctx->d_desc, f0, count, QB, d_acc, s))
+        return fail(ctx, CCPT_E_HIP, "reference gradient launch failed");
+    }
+    first += cnt;
+  }
+  if (g_ref) {
+    for (int r = 0; r < nrefs; ++r) {
+      const int nn = ctx->refs[r].n;
+      float2* T = (float2*)ctx->ws;
+      float* img = (float*)(T + spec_elems(nn));
+      if (launch_inverse(nn, (float2*)ctx->acc_buf + aoff[r], 1, 2.0f, T, img, ctx->tables[nn].tw,
+                         s) ||
+          launch_grad_ref_chain(img, ctx->refs[r].img, nn * nn, mode, eps, g_ref + roff[r], s))
+        return fail(ctx, CCPT_E_HIP, "reference gradient launch failed");
+    }
+  }
+  mark(CCPT_STAGE_GRAD, 0);
+  return CCPT_OK;
 }
 
-int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image*, double*, void*) {
+int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* stream) {
   if (!ctx) return CCPT_E_INVALID;
-  return fail(ctx, CCPT_E_UNSUPPORTED, "fisher not built yet");
+  if (!mu || !fisher) return fail(ctx, CCPT_E_INVALID, "null argument");
+  int rc = check_image(ctx, mu->data, mu->ny, mu->nx, mu->pitch, mu->dtype, "mean image", 0);
+  if (rc) return rc;
+  rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int n = mu->nx;
+  HIP_CHECK(ctx, hipStreamSynchronize(s));
+  {
+    const size_t esz = mu->dtype == CCPT_U16 ? 2 : 4;
+    std::vector<char> raw((size_t)mu->ny * mu->pitch * esz);
+    HIP_CHECK(ctx, hipMemcpy(raw.data(), mu->data, raw.size(), hipMemcpyDeviceToHost));
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        const size_t k = (size_t)y * mu->pitch + x;
+        const float v = mu->dtype == CCPT_U16 ? (float)((const uint16_t*)raw.data())[k]
+                                              : ((const float*)raw.data())[k];
+        if (!(v > 0.f) || !std::isfinite(v))
+          return fail(ctx, CCPT_E_INVALID, "mean image must be > 0 and finite (%d, %d)", y, x);
+      }
+  }
+  rc = ensure_tables(ctx, n);
+  if (rc) return rc;
+  const size_t spec = spec_elems(n);
+  const int nblocks = 64;
+  const size_t bytes = 4 * spec * sizeof(float2) + 2 * (size_t)n * n * sizeof(float) +
+                       (size_t)nblocks * 3 * sizeof(double) + 256;
+  char* tmp = nullptr;
+  HIP_CHECK(ctx, hipMalloc(&tmp, bytes));
+  float2* F = (float2*)tmp;
+  float2* Dy = F + spec;
+  float2* Dx = Dy + spec;
+  float2* T = Dx + spec;
+  float* iy = (float*)(T + spec);
+  float* ix = iy + (size_t)n * n;
+  double* part = (double*)(((uintptr_t)(ix + (size_t)n * n) + 15) & ~(uintptr_t)15);
+  const float2* tw = ctx->tables[n].tw;
+  int bad = launch_spectrum(n, mu->data, mu->dtype, mu->pitch, 0, 1, 0, 0.f, 0, T, F, tw, s) ||
+            launch_fisher_deriv(n, F, Dy, Dx, s) || launch_inverse(n, Dy, 1, 2.0f, T, iy, tw, s) ||
+            launch_inverse(n, Dx, 1, 2.0f, T, ix, tw, s) ||
+            launch_fisher_reduce(iy, ix, mu->data, mu->dtype, mu->pitch, n, part, nblocks, fisher, s);
+  hipError_t e = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  if (bad) return fail(ctx, CCPT_E_HIP, "fisher launch failed");
+  if (e != hipSuccess) return fail(ctx, CCPT_E_HIP, "fisher: %s", hipGetErrorString(e));
+  return CCPT_OK;
+}
+
+int ccpt_stage_times(ccpt_ctx* ctx, double* ms, int* launches, int n_stages, int reset) {
+  if (!ctx || n_stages < 0 || (n_stages > 0 && (!ms || !launches))) return CCPT_E_INVALID;
+  for (int i = 0; i < n_stages; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  for (auto& sp : ctx->spans) {
+    HIP_CHECK(ctx, hipEventSynchronize(sp.b));
+    float t = 0.f;
+    HIP_CHECK(ctx, hipEventElapsedTime(&t, sp.a, sp.b));
+    if (sp.stage >= 0 && sp.stage < n_stages) {
+      ms[sp.stage] += t;
+      launches[sp.stage] += 1;
+    }
+  }
+  if (reset) {
+    for (auto& sp : ctx->spans) {
+      ctx->ev_pool.push_back(sp.a);
+      ctx->ev_pool.push_back(sp.b);
+    }
+    ctx->spans.clear();
+  }
+  return CCPT_OK;
 }
 
 int ccpt_autotune(ccpt_ctx* ctx, int, int, void*) {

@@ -16,7 +16,7 @@ struct FrameDesc {
   int pitch;            // elements between row starts
   int dtype;            // CCPT_U16 / CCPT_F32
   int out_idx;          // index into the caller's result array
-  int pad;
+  int ref_id;           // reference index
 };
 
 // Per-frame scratch kept in the workspace between the kernels of one chunk.
@@ -35,6 +35,9 @@ struct GroupParams {
   int count;              // frames in the current chunk
   float2* T;              // workspace [count][N][N/2+1] (FFT intermediate)
   float2* X;              // workspace [count][N][N/2+1] (cross-power spectrum)
+  unsigned* Xb;           // split-precision copy of X for the matrix cores, or null:
+                          // [count][2 (hi, lo)][N/2][xb_pitch(N)] words, one word =
+                          // bf16 re | bf16 im << 16, ky contiguous, DC zeroed
   FrameState* st;         // [count]
   ccpt_result* out;       // caller's results
   const float2* tw;       // exp(-2 pi i m / N), m < N
@@ -46,6 +49,9 @@ struct GroupParams {
   int newton_iters;
   double half_window;     // Newton results farther than this from p fall back
 };
+
+// Row length (in words) of the split-precision spectrum rows: N rounded up to 32.
+__host__ __device__ constexpr int xb_pitch(int n) { return (n + 31) / 32 * 32; }
 
 // Order-preserving map float -> uint32 (a < b  <=>  key(a) < key(b)).
 __host__ __device__ inline unsigned f2key(float v) {
@@ -62,11 +68,21 @@ __host__ __device__ inline unsigned key_index(unsigned long long k) {
   return 0xFFFFFFFFu - (unsigned)(k & 0xFFFFFFFFull);
 }
 
+// Optional callback around each kernel launch (stage id, begin/end), used
+// to bracket launches with timing events.
+struct Marker {
+  void (*fn)(void* user, int stage, int begin) = nullptr;
+  void* user = nullptr;
+  void operator()(int stage, int begin) const {
+    if (fn) fn(user, stage, begin);
+  }
+};
+
 // ---- launchers (defined in the .hip files) -------------------------------
 
 // Stage 0-3: state reset, forward 2-D r2c FFT with the prologue, cross-power
 // spectrum, inverse 2-D c2r FFT and the integer-peak search.
-int launch_xcorr(int N, const GroupParams& g, hipStream_t s, int col_block);
+int launch_xcorr(int N, const GroupParams& g, hipStream_t s, const Marker& mark);
 
 // Forward 2-D r2c FFT of n images (pitch in elements) into spec
 // [n][N][N/2+1]; weight: 0 = identity, 1 = CC-SN reference (-1/(E+eps)),
@@ -91,6 +107,25 @@ int launch_newton(int N, const GroupParams& g, double step_limit, hipStream_t s)
 // scaled by `scale` (T is scratch of the same size as the spectra).
 int launch_inverse(int N, const float2* spec, int n, float scale, float2* T, float* img,
                    const float2* tw, hipStream_t s);
+
+// Forward 2-D r2c spectra (with the frame prologue of `mode`) of the frames of
+// a descriptor chunk into spec [count][N][N/2+1].
+int launch_frame_spectra(int N, const FrameDesc* desc, int first, int count, int mode, float eps,
+                         float2* T, float2* spec, const float2* tw, hipStream_t s);
+
+// Adjoint pieces (grad.hip).
+int launch_grad_psi(int N, const FrameDesc* desc, int first, int count, const ccpt_result* fwd,
+                    const double* g_d, const double* g_peak, const float2* FA, float2* QA,
+                    float2* QB, hipStream_t s);
+int launch_grad_frames(int N, const FrameDesc* desc, int first, int count, const float* img,
+                       const long* goff, float* g_frames, int mode, float eps, hipStream_t s);
+int launch_ref_accum(int N, const FrameDesc* desc, int first, int count, const float2* QB,
+                     float2* const* acc, hipStream_t s);
+int launch_grad_ref_chain(const float* img, const float* E, int nn, int mode, float eps,
+                          float* out, hipStream_t s);
+int launch_fisher_deriv(int N, const float2* F, float2* Dy, float2* Dx, hipStream_t s);
+int launch_fisher_reduce(const float* dy, const float* dx, const void* mu, int dtype, int pitch,
+                         int n, double* part, int nblocks, double* out, hipStream_t s);
 
 // Fills bytes of device memory with zero using a kernel (graph-safe).
 int launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -23,6 +23,23 @@ __device__ __forceinline__ float2 mul_i(float2 a) {
   return SIGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
+// bf16 (round to nearest even) of a float, as the high 16 bits of its pattern
+__device__ __forceinline__ unsigned bf16_bits(float f) {
+  unsigned b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return b >> 16;
+}
+__device__ __forceinline__ float bf16_float(unsigned h) { return __uint_as_float(h << 16); }
+
+// Splits a complex value into bf16 hi + lo words (re in the low half, im in
+// the high half of each word): v ~ hi + lo to about 16 significant bits.
+__device__ __forceinline__ void split_pair(float2 v, unsigned& hi, unsigned& lo) {
+  const unsigned hr = bf16_bits(v.x), hm = bf16_bits(v.y);
+  const unsigned lr = bf16_bits(v.x - bf16_float(hr)), lm = bf16_bits(v.y - bf16_float(hm));
+  hi = hr | (hm << 16);
+  lo = lr | (lm << 16);
+}
+
 constexpr int fft_radix(int L, int stage) {
   int i = 0;
   while (L % 3 == 0) {

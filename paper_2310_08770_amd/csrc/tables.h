@@ -91,26 +91,18 @@ inline HostTables build_tables(int n, int u, int M, int c, int precision) {
       if (kx > 0 && 2 * kx < n) w[(size_t)(n / 2 + kx) * Mp + mx] = -2.0 * im * inv;
     }
   }
+  // Stage A operand: FP32 complex [Mp][n] in every precision (the split
+  // kernels fold the integer-peak phase into it and split it on the fly)
+  t.ky.resize((size_t)Mp * n * sizeof(float2));
+  float2* K = (float2*)t.ky.data();
+  for (size_t i = 0; i < (size_t)Mp * n; ++i) K[i] = make_float2((float)kr[i], (float)ki[i]);
   if (precision == CCPT_PREC_FP32) {
-    t.ky.resize((size_t)Mp * n * sizeof(float2));
-    float2* K = (float2*)t.ky.data();
-    for (size_t i = 0; i < (size_t)Mp * n; ++i) K[i] = make_float2((float)kr[i], (float)ki[i]);
     t.wb.resize((size_t)Kb * Mp * sizeof(float));
     float* W = (float*)t.wb.data();
     for (size_t i = 0; i < (size_t)Kb * Mp; ++i) W[i] = (float)w[i];
   } else {
-    // Stage A: per (m, ky) one 32-bit word of (re, im) bf16 for hi, then lo:
-    //   ky table = [2][Mp][n] uint32  (plane 0 hi, plane 1 lo)
-    // Stage B: transposed, W^T[mx][j] bf16, planes hi and lo: [2][Mp][Kb] uint16
-    t.ky.resize((size_t)2 * Mp * n * 4);
-    uint32_t* K = (uint32_t*)t.ky.data();
-    for (size_t i = 0; i < (size_t)Mp * n; ++i) {
-      uint16_t rh, rl, ih, il;
-      split_bf16(kr[i], rh, rl);
-      split_bf16(ki[i], ih, il);
-      K[i] = (uint32_t)rh | ((uint32_t)ih << 16);
-      K[(size_t)Mp * n + i] = (uint32_t)rl | ((uint32_t)il << 16);
-    }
+    // Stage B operand, transposed W^T[mx][j] as bf16, hi plane then lo plane:
+    // [2][Mp][Kb] uint16
     t.wb.resize((size_t)2 * Mp * Kb * 2);
     uint16_t* W = (uint16_t*)t.wb.data();
     for (int mx = 0; mx < Mp; ++mx)

@@ -201,12 +201,234 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
   }
 }
 
+
+// ---------------------------------------------------------------- BF16 x 2
+// Split precision: every operand x is carried as bf16 hi + lo (x ~ hi + lo to
+// ~16 significant bits) and each product as hi*hi + hi*lo + lo*hi, accumulated
+// in FP32 on the matrix cores (the lo*lo term is below the FP32 rounding of
+// the sum).  The frame's X arrives already split (unfolded, DC dropped) from
+// the column FFT; the integer-peak phase is folded into the shared K table
+// instead: K'[m, ky] = K[m, ky] exp(2 pi i ky p_y / N) (split per block), and
+// the kx phase exp(2 pi i kx p_x / N) multiplies Y after Stage A.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+// (re, im) word pairs -> (re, -im)
+__device__ __forceinline__ u32x4 neg_im(u32x4 w) { return w ^ 0x80000000u; }
+// (re, im) word pairs -> (im, re)
+__device__ __forceinline__ u32x4 swap_ri(u32x4 w) { return (w >> 16) | (w << 16); }
+
+// Stage B operand: W^T as bf16 planes [2][Mp][KB] (hi, lo)
+template <int N>
+__global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const float2* __restrict__ Ktab,
+                                                            const unsigned short* __restrict__ WbT, int Mp) {
+  constexpr int H = N / 2 + 1;
+  constexpr int NC = N / 2;
+  constexpr int NT = (NC + 31) / 32;
+  constexpr int TPW = (NT + 3) / 4;
+  constexpr int P = xb_pitch(N);
+  constexpr int KC = N >= 384 ? 16 : 32;   // ky per LDS chunk (multiple of 8)
+  constexpr int KCS = KC + 4;              // LDS row stride, words
+  constexpr int XROWS = NT * 32;
+  constexpr int KB = (N + 31) / 32 * 32;
+  constexpr int YST = KB + 8;              // Ymat row stride, bf16 elements
+  constexpr int XW = 2 * XROWS * KCS;
+  constexpr int KW = 2 * 32 * KCS;
+  constexpr int YW = 32 * YST;             // two bf16 planes of 32 x YST
+  constexpr int RAWW = (XW + KW) > YW ? (XW + KW) : YW;
+  __shared__ __attribute__((aligned(16))) unsigned raw[RAWW];
+  __shared__ float2 kf[32][KC + 1];
+  __shared__ float2 twf[N];
+  __shared__ float nyq[8][32];
+  __shared__ unsigned long long red[kUThreads / 64];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = blockIdx.y;
+  const int m0 = blockIdx.x * 32;
+  const FrameState st = g.st[f];
+  if (frame_skipped(st)) return;
+  unsigned pk = key_index(st.peak_key);
+  if (pk >= (unsigned)(N * N)) pk = 0;
+  const int iy = pk / N, ix = pk % N;
+  for (int i = tid; i < N; i += kUThreads) twf[i] = cconj(g.tw[i]);
+
+  unsigned* xs_hi = raw;
+  unsigned* xs_lo = raw + XROWS * KCS;
+  unsigned* ks_hi = raw + XW;
+  unsigned* ks_lo = ks_hi + 32 * KCS;
+  const unsigned* Xbh = g.Xb + (size_t)f * 2 * NC * P;
+  const unsigned* Xbl = Xbh + (size_t)NC * P;
+  const float2* Xf = g.X + (size_t)f * N * H;
+
+  f32x16 accr[TPW], acci[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) accr[t][v] = acci[t][v] = 0.f;
+  float nacc = 0.f;
+  const int h = lane >> 5, j = lane & 31;
+  __syncthreads();
+
+  for (int k0 = 0; k0 < P; k0 += KC) {
+    for (int i = tid; i < XROWS * (KC / 4); i += kUThreads) {
+      const int r = i / (KC / 4), q = i - r * (KC / 4);
+      u32x4 vh = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
+      if (r < NC) {
+        vh = *(const u32x4*)(Xbh + (size_t)r * P + k0 + 4 * q);
+        vl = *(const u32x4*)(Xbl + (size_t)r * P + k0 + 4 * q);
+      }
+      *(u32x4*)(xs_hi + r * KCS + 4 * q) = vh;
+      *(u32x4*)(xs_lo + r * KCS + 4 * q) = vl;
+    }
+    for (int i = tid; i < 32 * KC; i += kUThreads) {
+      const int m = i / KC, kk = i - m * KC;
+      const int ky = k0 + kk;
+      float2 kv = make_float2(0.f, 0.f);
+      if (ky < N) kv = cmul(Ktab[(size_t)(m0 + m) * N + ky], twf[(ky * iy) % N]);
+      kf[m][kk] = kv;
+      unsigned wh, wl;
+      split_pair(kv, wh, wl);
+      ks_hi[m * KCS + kk] = wh;
+      ks_lo[m * KCS + kk] = wl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s8 = 0; s8 < KC / 8; ++s8) {
+      const int col = s8 * 8 + 4 * h;
+      const u32x4 ah = *(const u32x4*)(ks_hi + j * KCS + col);
+      const u32x4 al = *(const u32x4*)(ks_lo + j * KCS + col);
+      const bf16x8 arh = as_bf(neg_im(ah)), aih = as_bf(swap_ri(ah));
+      const bf16x8 arl = as_bf(neg_im(al)), ail = as_bf(swap_ri(al));
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        if (wave + 4 * t < NT) {
+          const int row = (wave + 4 * t) * 32 + j;
+          const bf16x8 bh = as_bf(*(const u32x4*)(xs_hi + row * KCS + col));
+          const bf16x8 bl = as_bf(*(const u32x4*)(xs_lo + row * KCS + col));
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bh, accr[t], 0, 0, 0);
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bl, accr[t], 0, 0, 0);
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bh, accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, bh, acci[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, bl, acci[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, bh, acci[t], 0, 0, 0);
+        }
+      }
+    }
+    {  // Nyquist column kx = N/2 in FP32 on the VALU
+      const int m = tid & 31, grp = tid >> 5;
+      for (int kk = grp; kk < KC; kk += 8) {
+        const int ky = k0 + kk;
+        if (ky < N) {
+          const float2 kv = kf[m][kk];
+          const float2 xv = Xf[(size_t)ky * H + NC];
+          nacc += kv.x * xv.x - kv.y * xv.y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  nyq[tid >> 5][tid & 31] = nacc;
+  // kx phase of the fold
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    if (wave + 4 * t < NT) {
+      const int kx = (wave + 4 * t) * 32 + j;
+      const float2 ph = twf[(kx * ix) % N];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float yr = accr[t][v], yi = acci[t][v];
+        accr[t][v] = yr * ph.x - yi * ph.y;
+        acci[t][v] = yr * ph.y + yi * ph.x;
+      }
+    }
+  }
+  unsigned short* ymh = (unsigned short*)raw;
+  unsigned short* yml = ymh + 32 * YST;
+  for (int i = tid; i < 32 * (KB - N); i += kUThreads) {
+    const int r = i / (KB - N), c = N + i % (KB - N);
+    ymh[r * YST + c] = 0;
+    yml[r * YST + c] = 0;
+  }
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int kx = (wave + 4 * t) * 32 + j;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = (v >> 2) * 8 + h * 4 + (v & 3);
+      if (kx < NC) {
+        const unsigned a = bf16_bits(accr[t][v]);
+        ymh[i * YST + kx] = (unsigned short)a;
+        yml[i * YST + kx] = (unsigned short)bf16_bits(accr[t][v] - bf16_float(a));
+      }
+      if (kx >= 1 && kx < NC) {
+        const unsigned b = bf16_bits(acci[t][v]);
+        ymh[i * YST + NC + kx] = (unsigned short)b;
+        yml[i * YST + NC + kx] = (unsigned short)bf16_bits(acci[t][v] - bf16_float(b));
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < 32) {
+    float sacc = 0.f;
+    for (int q = 0; q < 8; ++q) sacc += nyq[q][tid];
+    if (ix & 1) sacc = -sacc;  // exp(i pi p_x)
+    const unsigned a = bf16_bits(sacc);
+    ymh[tid * YST + NC] = (unsigned short)a;
+    yml[tid * YST + NC] = (unsigned short)bf16_bits(sacc - bf16_float(a));
+  }
+  __syncthreads();
+
+  // Stage B: U[32][Mp] = Ymat[32][KB] x W[KB][Mp] on 16x16x32 bf16 tiles
+  const int ntb = 2 * (Mp / 16);
+  unsigned long long best = 0;
+  const int l16 = lane & 15, q4 = lane >> 4;
+  const unsigned short* WbL = WbT + (size_t)Mp * KB;
+  for (int T = wave; T < ntb; T += 4) {
+    const int mt = T & 1, nt = T >> 1;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const unsigned short* ah_p = ymh + (mt * 16 + l16) * YST + 8 * q4;
+    const unsigned short* al_p = yml + (mt * 16 + l16) * YST + 8 * q4;
+    const unsigned short* bh_p = WbT + (size_t)(nt * 16 + l16) * KB + 8 * q4;
+    const unsigned short* bl_p = WbL + (size_t)(nt * 16 + l16) * KB + 8 * q4;
+#pragma unroll 4
+    for (int k = 0; k < KB; k += 32) {
+      const bf16x8 ah = as_bf(*(const u32x4*)(ah_p + k));
+      const bf16x8 al = as_bf(*(const u32x4*)(al_p + k));
+      const bf16x8 bh = as_bf(*(const u32x4*)(bh_p + k));
+      const bf16x8 bl = as_bf(*(const u32x4*)(bl_p + k));
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int my = m0 + mt * 16 + q4 * 4 + v;
+      const int mx = nt * 16 + l16;
+      if (my < g.M && mx < g.M) {
+        const unsigned long long key = peak_key(acc[v], (unsigned)(my * g.M + mx));
+        best = key > best ? key : best;
+      }
+    }
+  }
+  best = wmax64(best);
+  if (lane == 0) red[wave] = best;
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < kUThreads / 64; ++w) best = red[w] > best ? red[w] : best;
+    atomicMax(&g.st[f].grid_key, best);
+  }
+}
+
 template <int N>
 static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
   const int mtiles = t.Mp / 32;
   if (t.precision == CCPT_PREC_FP32) {
     hipLaunchKernelGGL((k_updft_f32<N>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
                        (const float2*)t.ky, (const float*)t.wb, t.Mp);
+  } else if (t.precision == CCPT_PREC_BF16X2) {
+    if (!g.Xb) return -1;
+    hipLaunchKernelGGL((k_updft_bf16x2<N>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
+                       (const float2*)t.ky, (const unsigned short*)t.wb, t.Mp);
   } else {
     return -2;
   }

@@ -178,6 +178,7 @@ enum ColKind { COL_XCORR = 0, COL_FWD = 1, COL_FWD_CONJ = 2, COL_INV = 3 };
 template <int N, int CB, int KIND>
 __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__ desc, int first,
                                                    float2* __restrict__ T, float2* __restrict__ X,
+                                                   unsigned* __restrict__ Xb,
                                                    float2* __restrict__ spec, long spec_stride,
                                                    const float2* __restrict__ gtw) {
   constexpr int H = N / 2 + 1, S = N + 1;
@@ -228,6 +229,25 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
         }
       }
       __syncthreads();
+      if (Xb) {
+        // bf16 hi/lo split of X for the matrix cores, one row per column kx < N/2,
+        // ky contiguous, rows padded to xb_pitch(N) with zeros; DC dropped
+        constexpr int NC = N / 2, P = xb_pitch(N);
+        unsigned* hi = Xb + (size_t)f * 2 * NC * P;
+        unsigned* lo = hi + (size_t)NC * P;
+        for (int i = tid; i < CB * P; i += kThreads) {
+          const int c = i / P, y = i - c * P;
+          const int kx = c0 + c;
+          if (c < ncol && kx < NC) {
+            float2 v = y < N ? r[c * S + y] : make_float2(0.f, 0.f);
+            if (kx == 0 && y == 0) v = make_float2(0.f, 0.f);
+            unsigned wh, wl;
+            split_pair(v, wh, wl);
+            hi[(size_t)kx * P + y] = wh;
+            lo[(size_t)kx * P + y] = wl;
+          }
+        }
+      }
       float2* o = (r == bufA) ? bufB : bufA;
       float2* q = fft_lds<N, +1, N>(r, o, CB, S, tw);
       for (int i = tid; i < N * CB; i += kThreads) {
@@ -301,18 +321,26 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const float2* __restrict_
 }
 
 template <int N>
-static int xcorr_n(const GroupParams& g, hipStream_t s) {
+static int xcorr_n(const GroupParams& g, hipStream_t s, const Marker& mark) {
   constexpr int RPB = rows_per_block(N, 2048);
   constexpr int CB = cols_per_block(N);
   constexpr int H = N / 2 + 1;
+  mark(CCPT_STAGE_INIT, 1);
   hipLaunchKernelGGL(k_init_state, dim3((g.count + 255) / 256), dim3(256), 0, s, g.st, g.count);
+  mark(CCPT_STAGE_INIT, 0);
   ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0};
+  mark(CCPT_STAGE_ROWS_FWD, 1);
   hipLaunchKernelGGL((k_rows_fwd<N, RPB>), dim3(N / RPB, g.count), dim3(kThreads), 0, s, src,
                      g.mode == CCPT_MODE_CCSN ? 2 : 0, g.eps, g.T, g.st, g.tw);
+  mark(CCPT_STAGE_ROWS_FWD, 0);
+  mark(CCPT_STAGE_COLS, 1);
   hipLaunchKernelGGL((k_cols<N, CB, COL_XCORR>), dim3((H + CB - 1) / CB, g.count), dim3(kThreads),
-                     0, s, g.desc, g.first, g.T, g.X, (float2*)nullptr, 0L, g.tw);
+                     0, s, g.desc, g.first, g.T, g.X, g.Xb, (float2*)nullptr, 0L, g.tw);
+  mark(CCPT_STAGE_COLS, 0);
+  mark(CCPT_STAGE_ROWS_INV, 1);
   hipLaunchKernelGGL((k_rows_inv<N, RPB, true>), dim3(N / RPB, g.count), dim3(kThreads), 0, s,
                      g.T, g.st, (float*)nullptr, 1.0f, g.tw);
+  mark(CCPT_STAGE_ROWS_INV, 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -328,11 +356,27 @@ static int spectrum_n(const void* data, int dtype, int pitch, long img_stride, i
                      eps, T, (FrameState*)nullptr, tw);
   if (conj_out)
     hipLaunchKernelGGL((k_cols<N, CB, COL_FWD_CONJ>), dim3((H + CB - 1) / CB, n), dim3(kThreads),
-                       0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, spec,
-                       (long)N * H, tw);
+                       0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (unsigned*)nullptr,
+                       spec, (long)N * H, tw);
   else
     hipLaunchKernelGGL((k_cols<N, CB, COL_FWD>), dim3((H + CB - 1) / CB, n), dim3(kThreads), 0, s,
-                       (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, spec, (long)N * H, tw);
+                       (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (unsigned*)nullptr, spec,
+                       (long)N * H, tw);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N>
+static int frame_spectra_n(const FrameDesc* desc, int first, int count, int mode, float eps,
+                           float2* T, float2* spec, const float2* tw, hipStream_t s) {
+  constexpr int RPB = rows_per_block(N, 2048);
+  constexpr int CB = cols_per_block(N);
+  constexpr int H = N / 2 + 1;
+  ImgSrc src{desc, first, nullptr, 0, 0, 0};
+  hipLaunchKernelGGL((k_rows_fwd<N, RPB>), dim3(N / RPB, count), dim3(kThreads), 0, s, src,
+                     mode == CCPT_MODE_CCSN ? 2 : 0, eps, T, (FrameState*)nullptr, tw);
+  hipLaunchKernelGGL((k_cols<N, CB, COL_FWD>), dim3((H + CB - 1) / CB, count), dim3(kThreads), 0,
+                     s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (unsigned*)nullptr,
+                     spec, (long)N * H, tw);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -343,8 +387,8 @@ static int inverse_n(const float2* spec, int n, float scale, float2* T, float* i
   constexpr int CB = cols_per_block(N);
   constexpr int H = N / 2 + 1;
   hipLaunchKernelGGL((k_cols<N, CB, COL_INV>), dim3((H + CB - 1) / CB, n), dim3(kThreads), 0, s,
-                     (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (float2*)spec,
-                     (long)N * H, tw);
+                     (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (unsigned*)nullptr,
+                     (float2*)spec, (long)N * H, tw);
   hipLaunchKernelGGL((k_rows_inv<N, RPB, false>), dim3(N / RPB, n), dim3(kThreads), 0, s, T,
                      (FrameState*)nullptr, img, scale, tw);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -354,11 +398,11 @@ static int inverse_n(const float2* spec, int n, float scale, float2* T, float* i
   X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
   X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
 
-int launch_xcorr(int N, const GroupParams& g, hipStream_t s, int) {
+int launch_xcorr(int N, const GroupParams& g, hipStream_t s, const Marker& mark) {
   switch (N) {
 #define CASE(n) \
   case n:       \
-    return xcorr_n<n>(g, s);
+    return xcorr_n<n>(g, s, mark);
     CCPT_FOR_SIZES(CASE)
 #undef CASE
   }
@@ -372,6 +416,18 @@ int launch_spectrum(int N, const void* data, int dtype, int pitch, long img_stri
 #define CASE(nn) \
   case nn:       \
     return spectrum_n<nn>(data, dtype, pitch, img_stride, n, weight, eps, conj_out, T, spec, tw, s);
+    CCPT_FOR_SIZES(CASE)
+#undef CASE
+  }
+  return -2;
+}
+
+int launch_frame_spectra(int N, const FrameDesc* desc, int first, int count, int mode, float eps,
+                         float2* T, float2* spec, const float2* tw, hipStream_t s) {
+  switch (N) {
+#define CASE(nn) \
+  case nn:       \
+    return frame_spectra_n<nn>(desc, first, count, mode, eps, T, spec, tw, s);
     CCPT_FOR_SIZES(CASE)
 #undef CASE
   }

@@ -19,6 +19,8 @@ frame(r) ~ ref(r - d).
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -31,8 +33,20 @@ J1_ZERO = 3.8317059702075125
 
 
 def rng_for(config_index: int, salt: int = 0) -> np.random.Generator:
-    """Generator for one workload: PCG64 seeded with SEED_BASE + index (+ salt)."""
+    """Generator for one workload's parameters (shifts, sizes, ...):
+    PCG64 seeded with SEED_BASE + index (+ salt)."""
     return np.random.Generator(np.random.PCG64(SEED_BASE + config_index + salt))
+
+
+def noise_rng(config_index: int, frame_index: int) -> np.random.Generator:
+    """Independent Poisson-noise stream of one frame, so frames can be made
+    in parallel and any subset regenerated exactly."""
+    ss = np.random.SeedSequence([SEED_BASE + config_index, frame_index])
+    return np.random.Generator(np.random.PCG64(ss))
+
+
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 def gaussian_spot(n: int, sigma: float, peak: float, center=None) -> np.ndarray:
@@ -122,12 +136,32 @@ class Workload:
         return np.stack(self.frames)
 
 
-def _shifted_frames(spot_nz, bg, shifts, rng, clip_max, as_dtype):
-    frames = []
-    for d in shifts:
-        mu = phase_ramp_shift(spot_nz, d) + bg
-        frames.append(noisy(mu, rng, clip_max).astype(as_dtype))
-    return frames
+def _make_frames(spot_nz, bg, shifts, config_index, clip_max, as_dtype, chunk=32):
+    """Frames mu_i = shift(spot, d_i) + bg with Poisson noise from each
+    frame's own stream.  The spot spectrum is computed once; chunks of
+    frames go through one irfft2 each, in a thread pool (numpy releases the
+    GIL in the FFT and the Poisson draws)."""
+    ny, nx = spot_nz.shape
+    f = np.fft.rfft2(spot_nz)
+    ky = np.fft.fftfreq(ny)
+    kx = np.fft.rfftfreq(nx)
+    n = len(shifts)
+
+    def work(s0):
+        d = shifts[s0:s0 + chunk]
+        ry = np.exp(-2j * np.pi * ky[None, :] * d[:, 0:1])
+        rx = np.exp(-2j * np.pi * kx[None, :] * d[:, 1:2])
+        mu = np.fft.irfft2(f[None] * ry[:, :, None] * rx[:, None, :], s=(ny, nx)) + bg
+        return [noisy(m, noise_rng(config_index, s0 + j), clip_max).astype(as_dtype)
+                for j, m in enumerate(mu)]
+
+    starts = list(range(0, n, chunk))
+    if len(starts) > 1:
+        with ThreadPoolExecutor(_workers()) as ex:
+            parts = list(ex.map(work, starts))
+    else:
+        parts = [work(s0) for s0 in starts]
+    return [fr for part in parts for fr in part]
 
 
 def config1(n_frames: int = 100) -> Workload:
@@ -137,7 +171,7 @@ def config1(n_frames: int = 100) -> Workload:
     n = 64
     shifts = rng.uniform(-2.0, 2.0, size=(n_frames, 2))
     spot = zero_nyquist(gaussian_spot(n, 3.0, 1000.0))
-    frames = _shifted_frames(spot, 10.0, shifts, rng, 65535.0, np.uint16)
+    frames = _make_frames(spot, 10.0, shifts, 0, 65535.0, np.uint16)
     ref = spot + 10.0
     return Workload("gauss64_u20", frames, [ref], np.zeros(n_frames, np.int32),
                     shifts, "u16", 20, dict(sigma=3.0, peak=1000.0, bg=10.0))
@@ -152,30 +186,10 @@ def config2(n_frames: int = 10000) -> Workload:
     steps[0] = 0.0
     shifts = np.cumsum(steps, axis=0)
     spot = zero_nyquist(airy_spot(n, 8.0, 4000.0))
-    frames = _fast_shifted_frames(spot, 50.0, shifts, rng, 4095.0, np.uint16)
+    frames = _make_frames(spot, 50.0, shifts, 1, 4095.0, np.uint16)
     ref = spot + 50.0
     return Workload("airy256_u100", frames, [ref], np.zeros(n_frames, np.int32),
                     shifts, "u16", 100, dict(peak=4000.0, bg=50.0, first_zero=8.0))
-
-
-def _fast_shifted_frames(spot_nz, bg, shifts, rng, clip_max, as_dtype, chunk=64):
-    """Same as _shifted_frames but batched through rfft2 for speed: the
-    spectrum of the spot is computed once and each frame needs one irfft2.
-    Poisson draws happen frame by frame in order, so the stream of random
-    numbers is identical to the unbatched version."""
-    ny, nx = spot_nz.shape
-    f = np.fft.rfft2(spot_nz)
-    ky = np.fft.fftfreq(ny)
-    kx = np.fft.rfftfreq(nx)
-    out = []
-    for s0 in range(0, len(shifts), chunk):
-        d = shifts[s0:s0 + chunk]
-        ry = np.exp(-2j * np.pi * ky[None, :] * d[:, 0:1])
-        rx = np.exp(-2j * np.pi * kx[None, :] * d[:, 1:2])
-        mu = np.fft.irfft2(f[None] * ry[:, :, None] * rx[:, None, :], s=(ny, nx)) + bg
-        for m in mu:
-            out.append(noisy(m, rng, clip_max).astype(as_dtype))
-    return out
 
 
 def config3(n_rois: int = 4096) -> Workload:
@@ -194,7 +208,7 @@ def config3(n_rois: int = 4096) -> Workload:
         n = int(sizes[i])
         spot = zero_nyquist(gaussian_spot(n, sig[i], pk[i]))
         mu = phase_ramp_shift(spot, shifts[i]) + bg[i]
-        frames.append(noisy(mu, rng, 65535.0).astype(np.uint16))
+        frames.append(noisy(mu, noise_rng(2, i), 65535.0).astype(np.uint16))
         refs.append(spot + bg[i])
     return Workload("uneven_rois_u100", frames, refs, np.arange(n_rois, dtype=np.int32),
                     shifts, "u16", 100, dict(sizes=sizes, sigma=sig, peak=pk, bg=bg))
@@ -207,7 +221,7 @@ def config4(n_frames: int = 2048) -> Workload:
     n = 512
     shifts = rng.uniform(-3.0, 3.0, size=(n_frames, 2))
     spot = zero_nyquist(gaussian_spot(n, 4.0, 500.0))
-    frames = _fast_shifted_frames(spot, 20.0, shifts, rng, 65535.0, np.uint16, chunk=16)
+    frames = _make_frames(spot, 20.0, shifts, 3, 65535.0, np.uint16, chunk=8)
     ref = spot + 20.0
     return Workload("gauss512_u200", frames, [ref], np.zeros(n_frames, np.int32),
                     shifts, "u16", 200, dict(sigma=4.0, peak=500.0, bg=20.0))
@@ -220,7 +234,7 @@ def config5(n_frames: int = 1024) -> Workload:
     n = 128
     shifts = rng.uniform(-2.0, 2.0, size=(n_frames, 2))
     spot = zero_nyquist(gaussian_spot(n, 3.0, 2000.0))
-    frames = _fast_shifted_frames(spot, 0.0, shifts, rng, None, np.float32)
+    frames = _make_frames(spot, 0.0, shifts, 4, None, np.float32)
     return Workload("gauss128_grad", frames, [spot.copy()], np.zeros(n_frames, np.int32),
                     shifts, "f32", 100, dict(sigma=3.0, peak=2000.0, bg=0.0))
 

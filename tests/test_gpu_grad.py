@@ -1,0 +1,231 @@
+"""GPU adjoint, Fisher information, split precision, CC-SN and graph replay,
+each checked against the FP64 oracle (or the eager path for graphs)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ccpt_oracle as O
+from synth import frames as S
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def tracker(**kw):
+    from paper_2310_08770_amd import Tracker
+    return Tracker(**kw)
+
+
+def t(x, dtype=None):
+    a = np.ascontiguousarray(x if dtype is None else np.asarray(x, dtype=dtype))
+    return torch.from_numpy(a).to(DEV)
+
+
+@pytest.mark.parametrize("mode", ["ccu", "ccsn"])
+def test_adjoint_vs_fp64_oracle(mode):
+    say(f"case: adjoint vs oracle, config5 128x128 f32, 6 frames, {mode}")
+    from paper_2310_08770_amd import decode
+    w = S.config5(6)
+    u, eps = 100, 200.0
+    m = O.MODE_CCU if mode == "ccu" else O.MODE_CCSN
+    ref32 = w.refs[0].astype(np.float32)
+    tr = tracker(upsample=u, mode=mode, eps=eps)
+    tr.set_reference(t(ref32))
+    fr = t(np.stack(w.frames))
+    res = tr.track(fr)
+    rng = np.random.Generator(np.random.PCG64(5))
+    g_d = rng.standard_normal((6, 2))
+    g_peak = rng.standard_normal(6) * 1e-6
+    gf, gr = tr.track_grad(fr, res, t(g_d), t(g_peak))
+    torch.cuda.synchronize()
+    gf = gf.cpu().numpy().reshape(6, 128, 128)
+    gr = gr.cpu().numpy().reshape(128, 128)
+    r = decode(res)
+    ref64 = ref32.astype(np.float64)
+    tot_gE = np.zeros((128, 128))
+    for i in range(6):
+        o = O.track(w.frames[i], ref64, u, mode=m, eps=eps)
+        assert np.max(np.abs(r["d"][i] - o["d"])) < 1e-3
+        gI, gE = O.adjoint(w.frames[i], ref64, o, g_d[i], g_peak[i], mode=m, eps=eps)
+        tot_gE += gE
+        rel = np.max(np.abs(gf[i] - gI)) / np.max(np.abs(gI))
+        say(f"  frame {i}: frame-gradient rel err {rel:.2e}")
+        assert rel <= 1e-3
+    rel = np.max(np.abs(gr - tot_gE)) / np.max(np.abs(tot_gE))
+    say(f"  reference-gradient rel err {rel:.2e}")
+    assert rel <= 1e-3
+    tr.close()
+
+
+def test_adjoint_directional_fd_on_gpu():
+    say("case: directional finite differences of the GPU forward, config5")
+    from paper_2310_08770_amd import decode
+    w = S.config5(4)
+    ref32 = w.refs[0].astype(np.float32)
+    tr = tracker(upsample=100)
+    tr.set_reference(t(ref32))
+    fr = t(np.stack(w.frames))
+    res = tr.track(fr)
+    g_d = np.array([[1.0, 0.0], [0.0, 1.0], [0.6, -0.8], [1.0, 1.0]])
+    gf, _ = tr.track_grad(fr, res, t(g_d), None, want_ref=False)
+    gf = gf.cpu().numpy().reshape(4, 128, 128).astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(8))
+    v = rng.standard_normal((4, 128, 128)).astype(np.float32)
+    h = 4.0  # photons: large enough for the FP32 forward to resolve the change
+
+    def L(x):
+        r = decode(tr.track(t(x)))
+        return np.sum(r["d"] * g_d, axis=1)
+
+    base = np.stack(w.frames).astype(np.float32)
+    fd = (L(base + h * v) - L(base - h * v)) / (2 * h)
+    an = np.sum(gf * v, axis=(1, 2))
+    rel = np.abs(fd - an) / np.abs(an)
+    say(f"  directional FD rel err {rel}")
+    assert np.all(rel <= 1e-2)
+    tr.close()
+
+
+def test_fisher_vs_oracle():
+    say("case: Fisher information 128x128 and 512x512")
+    for n, sigma in [(128, 3.0), (512, 4.0)]:
+        mu = (S.gaussian_spot(n, sigma, 500.0) + 20.0).astype(np.float32)
+        tr = tracker(upsample=100)
+        F = tr.fisher(t(mu)).cpu().numpy()
+        Fo = O.fisher(mu.astype(np.float64))
+        rel = np.max(np.abs(F - Fo)) / np.max(np.abs(Fo))
+        say(f"  N={n}: fisher rel err {rel:.2e}")
+        assert rel <= 1e-4
+        tr.close()
+
+
+def test_bf16x2_parity_config2_sample():
+    say("case: bf16x2 split precision, config2 first 32 frames")
+    from paper_2310_08770_amd import decode
+    w = S.config2(32)
+    ref32 = w.refs[0].astype(np.float32)
+    tr = tracker(upsample=100, precision="bf16x2")
+    tr.set_reference(t(ref32))
+    r = decode(tr.track(t(np.stack(w.frames))))
+    ref64 = ref32.astype(np.float64)
+    errs, gerrs = [], []
+    for i in range(32):
+        o = O.track(w.frames[i], ref64, 100)
+        assert tuple(r["p"][i]) == tuple(o["p"])
+        errs.append(np.max(np.abs(r["d"][i] - o["d"])))
+        gerrs.append(np.max(np.abs(r["d_grid"][i] - o["d_grid"])))
+    say(f"  max |d - d_oracle| = {max(errs):.2e}, max |d_grid - oracle grid| = {max(gerrs):.2e}, "
+        f"status {np.unique(r['status'])}")
+    assert max(errs) <= 1e-3
+    # the split-precision grid may pick a neighbouring grid point on a flat top
+    assert max(gerrs) <= 1e-2 + 1e-6
+    tr.close()
+
+
+@pytest.mark.parametrize("n", [16, 18, 48, 96, 192, 512])
+def test_bf16x2_sizes(n):
+    say(f"case: bf16x2 size {n}")
+    from paper_2310_08770_amd import decode
+    r = np.random.Generator(np.random.PCG64(300 + n))
+    spot = S.zero_nyquist(S.gaussian_spot(n, max(1.5, n / 24), 3000.0))
+    frames = [S.noisy(S.phase_ramp_shift(spot, r.uniform(-3, 3, 2)) + 20.0, r).astype(np.uint16)
+              for _ in range(4)]
+    ref32 = (spot + 20.0).astype(np.float32)
+    tr = tracker(upsample=20, precision="bf16x2")
+    tr.set_reference(t(ref32))
+    res = decode(tr.track([t(f) for f in frames]))
+    for i, f in enumerate(frames):
+        o = O.track(f, ref32.astype(np.float64), 20)
+        assert tuple(res["p"][i]) == tuple(o["p"])
+        assert np.max(np.abs(res["d"][i] - o["d"])) <= 1e-3
+    tr.close()
+
+
+def test_ccsn_parity():
+    say("case: CC-SN forward parity, config1 (eps 200)")
+    from paper_2310_08770_amd import decode
+    w = S.config1(30)
+    ref32 = w.refs[0].astype(np.float32)
+    tr = tracker(upsample=20, mode="ccsn", eps=200.0)
+    tr.set_reference(t(ref32))
+    r = decode(tr.track(t(np.stack(w.frames))))
+    errs = []
+    for i in range(30):
+        o = O.track(w.frames[i], ref32.astype(np.float64), 20, mode=O.MODE_CCSN, eps=200.0)
+        assert tuple(r["p"][i]) == tuple(o["p"])
+        errs.append(np.max(np.abs(r["d"][i] - o["d"])))
+    say(f"  CC-SN max err {max(errs):.2e}")
+    assert max(errs) <= 1e-3
+    tr.close()
+
+
+def test_ccsn_rejects_nonpositive_reference():
+    say("case: CC-SN reference with E + eps <= 0")
+    from paper_2310_08770_amd.ccpt import CcptError, E_NONPOSITIVE_REF
+    tr = tracker(upsample=10, mode="ccsn", eps=1.0)
+    bad = np.full((32, 32), -5.0, np.float32)
+    with pytest.raises(CcptError) as e:
+        tr.set_reference(t(bad))
+    assert e.value.code == E_NONPOSITIVE_REF
+    tr.close()
+
+
+def test_graph_replay_matches_eager():
+    say("case: hipGraph replay vs eager, 3 replays with eager work between")
+    from paper_2310_08770_amd import decode
+    w = S.config2(40)
+    ref = t(w.refs[0].astype(np.float32))
+    fr = t(np.stack(w.frames))
+    eager = tracker(upsample=100)
+    eager.set_reference(ref)
+    want = decode(eager.track(fr))
+    g = tracker(upsample=100, graph=True)
+    g.set_reference(ref)
+    stream = torch.cuda.Stream()
+    out = torch.empty((40, 72), dtype=torch.uint8, device=DEV)
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            out.zero_()
+            g.track(fr, out=out, stream=stream)
+        stream.synchronize()
+        got = decode(out)
+        assert got.tobytes() == want.tobytes(), rep
+        # unrelated eager work between replays
+        _ = decode(eager.track(fr[:5]))
+    eager.close()
+    g.close()
+
+
+def test_error_codes():
+    say("case: argument errors")
+    from paper_2310_08770_amd.ccpt import CcptError, E_UNSUPPORTED, E_NOREF
+    tr = tracker(upsample=10)
+    with pytest.raises(CcptError) as e:
+        tr.track(t(np.zeros((2, 20, 20), np.float32)))
+    assert e.value.code == E_NOREF
+    tr.set_reference(t(np.ones((32, 32), np.float32)))
+    with pytest.raises(CcptError) as e:
+        tr.track(t(np.zeros((2, 30, 30), np.float32)))
+    assert e.value.code == E_UNSUPPORTED
+    tr.close()
+
+
+def test_template_optimisation_reduces_loss():
+    say("case: template optimisation, 20 Adam steps on config5 (256 frames)")
+    from paper_2310_08770_amd.autograd import optimise_template
+    w = S.config5(256)
+    tr = tracker(upsample=100)
+    fr = t(np.stack(w.frames))
+    # start from one noisy frame (shifted by its true displacement)
+    ref0 = t(np.maximum(w.frames[0], 1.0).astype(np.float32))
+    shifts = w.shifts - w.shifts[0]
+    _, losses = optimise_template(fr, t(shifts), ref0, tr, steps=20, log=say)
+    assert losses[-1] < losses[0]
+    tr.close()
