@@ -231,6 +231,15 @@ def main():
                               frames=len(lp))
             log(f"[bench] {name}: p50 {legs[name]['p50_ms']:.3f} ms p99 {legs[name]['p99_ms']:.3f} ms")
             trp.close()
+        # where a plain call spends its GPU time
+        trp = Tracker(upsample=w.u, precision="fp32", profile=True)
+        trp.set_reference(ref_t)
+        time_plain(trp, frames_t, 20, torch)
+        trp.stage_times(reset=True)
+        time_plain(trp, frames_t, 200, torch)
+        st = trp.stage_times(reset=True)
+        legs["plain"]["gpu_stage_us"] = {k: round(v[0] / max(1, v[1]) * 1e3, 2) for k, v in st.items() if v[1]}
+        trp.close()
 
     # ---- accuracy against the oracle sample
     accuracy = None

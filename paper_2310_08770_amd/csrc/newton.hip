@@ -1,19 +1,32 @@
 // FP64 refinement of the upsampled-grid maximum and the result record.
 //
 // The band-limited correlation (the function the paper's upsampled DFT
-// samples, Sec. III) is evaluated directly from the FP32 cross-power
-// spectrum in FP64 arithmetic, with its gradient and Hessian:
+// samples, Sec. III) around an expansion centre s0 is
 //
-//   C(s) = 1/N^2 sum_kx w_kx Re[ phi_kx(s_x) V_kx(s_y) ],
-//   V_kx(s_y) = sum_ky X[ky, kx] phi_ky(s_y),
-//   phi_k(s) = exp(2 pi i k~ s / N),  phi_{N/2}(s) = cos(pi s),
+//   C(s0 + e) = 1/N^2 sum_kx w_kx Re[ phi_kx(s0x + ex) V_kx(s0y + ey) ],
+//   V_kx(s0y + ey) = sum_ky X[ky, kx] phi_ky(s0y) exp(i a_ky ey),
+//   phi_k(s) = exp(i a_k s), a_k = 2 pi k~ / N, and for a Nyquist bin
+//   phi(s) = cos(pi s) = Re exp(i pi s),
 //
-// and Newton steps s <- s - H^-1 grad C start from the grid maximum.  The
-// same safeguards as the reference definition apply: a Hessian that is not
-// negative definite or a step beyond the step limit falls back to the grid
-// estimate, and a result more than 0.75 px from the integer peak is
-// flagged and replaced by the grid estimate (0.75 px for the paper's
-// 1.5-px window).
+// with w = 1 at kx = 0 and N/2, else 2.  Expanding both exponentials in
+// powers of e turns C into a polynomial
+//
+//   C(s0 + e) = sum_{n+m <= K} c_nm ey^n ex^m / (n! m!),
+//   c_nm = 1/N^2 sum_kx w Re[ P_m(kx) M_n(kx) ],
+//   M_n(kx) = sum_ky X[ky, kx] phi_ky(s0y) (i a_ky)^n,
+//   P_m(kx) = phi_kx(s0x) (i b_kx)^m       (real part only for a Nyquist bin)
+//
+// whose truncation error is below (pi |e|)^(K+1)/(K+1)! relative, i.e. at
+// FP64 rounding for |e| <= 0.02 px with K = 7.  One streaming pass over the
+// FP32 spectrum (FP64 arithmetic) therefore gives C, its gradient and Hessian
+// anywhere near the seed, and the Newton iterations run on the polynomial.
+// If an iterate moves farther than the model radius from the centre, the
+// model is rebuilt around it (at most three passes).
+//
+// Safeguards as in the reference definition: a Hessian that is not negative
+// definite or a step beyond the step limit falls back to the grid estimate,
+// and a result farther than half the window from the integer peak is
+// flagged and replaced by the grid estimate.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -23,122 +36,207 @@
 namespace ccpt {
 
 constexpr int kNThreads = 256;
+constexpr int kOrder = 7;                               // K
+constexpr int kCoef = (kOrder + 1) * (kOrder + 2) / 2;  // pairs with n + m <= K
+constexpr double kModelRadius = 0.02;                   // px
+constexpr int kMaxPasses = 3;
 
-struct CEval {
-  double c, gy, gx, hyy, hxx, hxy;
-};
-
-__device__ __forceinline__ void phi3(int k, int n, double s, double2& p0, double2& p1, double2& p2) {
-  if (2 * k == n) {
-    double sn, cs;
-    sincospi(s, &sn, &cs);
-    const double pi = 3.14159265358979323846;
-    p0 = make_double2(cs, 0.0);
-    p1 = make_double2(-pi * sn, 0.0);
-    p2 = make_double2(-pi * pi * cs, 0.0);
-    return;
-  }
-  const int kt = 2 * k < n ? k : k - n;
-  double sn, cs;
-  sincospi(2.0 * (double)kt * s / (double)n, &sn, &cs);
-  const double w = 2.0 * 3.14159265358979323846 * (double)kt / (double)n;
-  p0 = make_double2(cs, sn);
-  p1 = make_double2(-w * sn, w * cs);
-  p2 = make_double2(-w * w * cs, -w * w * sn);
+// pairs ordered by n, then m
+__host__ __device__ constexpr int coef_index(int n, int m) {
+  return n * (kOrder + 1) - n * (n - 1) / 2 + m;
 }
 
-__device__ __forceinline__ double re_mul(double2 a, double2 b) { return a.x * b.x - a.y * b.y; }
+struct Deriv {
+  double c, gy, gx, hyy, hxy, hxx;
+};
 
-template <int N>
-__device__ CEval eval_c(const float2* __restrict__ Xf, double sy, double sx, double2 (*ey)[3],
-                        double (*red)[kNThreads / 64]) {
-  constexpr int H = N / 2 + 1;
-  const int tid = threadIdx.x;
-  for (int ky = tid; ky < N; ky += kNThreads) phi3(ky, N, sy, ey[ky][0], ey[ky][1], ey[ky][2]);
-  __syncthreads();
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int kx = tid; kx < H; kx += kNThreads) {
-    double2 v0 = make_double2(0, 0), v1 = v0, v2 = v0;
-    const float2* col = Xf + kx;
-#pragma unroll 4
-    for (int ky = 0; ky < N; ++ky) {
-      const float2 xf = col[(size_t)ky * H];
-      const double xr = xf.x, xi = xf.y;
-      const double2 a = ey[ky][0], b = ey[ky][1], c = ey[ky][2];
-      v0.x += xr * a.x - xi * a.y;
-      v0.y += xr * a.y + xi * a.x;
-      v1.x += xr * b.x - xi * b.y;
-      v1.y += xr * b.y + xi * b.x;
-      v2.x += xr * c.x - xi * c.y;
-      v2.y += xr * c.y + xi * c.x;
-    }
-    double2 e0, e1, e2;
-    phi3(kx, N, sx, e0, e1, e2);
-    const double wt = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
-    acc[0] += wt * re_mul(e0, v0);
-    acc[1] += wt * re_mul(e0, v1);
-    acc[2] += wt * re_mul(e1, v0);
-    acc[3] += wt * re_mul(e0, v2);
-    acc[4] += wt * re_mul(e2, v0);
-    acc[5] += wt * re_mul(e1, v1);
-  }
-  // deterministic block reduction
+// C and its first and second derivatives of the polynomial model at e.
+__device__ Deriv model_eval(const double* coef, double ey, double ex) {
+  double py[kOrder + 1], px[kOrder + 1];  // e^j / j!
+  py[0] = px[0] = 1.0;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
+  for (int j = 1; j <= kOrder; ++j) {
+    py[j] = py[j - 1] * ey / j;
+    px[j] = px[j - 1] * ex / j;
+  }
+  Deriv d{0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int n = 0; n <= kOrder; ++n)
+#pragma unroll
+    for (int m = 0; n + m <= kOrder; ++m) {
+      const double c = coef[coef_index(n, m)];
+      d.c += c * py[n] * px[m];
+      if (n >= 1) d.gy += c * py[n - 1] * px[m];
+      if (m >= 1) d.gx += c * py[n] * px[m - 1];
+      if (n >= 2) d.hyy += c * py[n - 2] * px[m];
+      if (m >= 2) d.hxx += c * py[n] * px[m - 2];
+      if (n >= 1 && m >= 1) d.hxy += c * py[n - 1] * px[m - 1];
+    }
+  return d;
+}
+
+// acc[n, m] += w Re[P_m M_n] with P_m = phx (i b)^m (real part only if nyq_x).
+__device__ __forceinline__ void add_terms(double* acc, const double2* M, double2 phx, double b,
+                                          bool nyq_x, double w) {
+  double2 P = phx;
+#pragma unroll
+  for (int m = 0; m <= kOrder; ++m) {
+    const double pr = P.x, pim = nyq_x ? 0.0 : P.y;
+#pragma unroll
+    for (int n = 0; n + m <= kOrder; ++n) acc[coef_index(n, m)] += w * (pr * M[n].x - pim * M[n].y);
+    P = make_double2(-b * P.y, b * P.x);
+  }
+}
+
+// Accumulates t (i a)^n into M[n], n = 0..K.
+__device__ __forceinline__ void add_powers(double2* M, double2 t, double a) {
+#pragma unroll
+  for (int n = 0; n <= kOrder; ++n) {
+    M[n].x += t.x;
+    M[n].y += t.y;
+    t = make_double2(-a * t.y, a * t.x);
+  }
+}
+
+// One pass: the model coefficients around (sy, sx) into coef (LDS).
+template <int N>
+__device__ void build_model(const float2* __restrict__ Xf, double sy, double sx, double2* phy,
+                            double* ay, double (*red)[kNThreads / 64], double* coef) {
+  constexpr int H = N / 2 + 1;
+  constexpr int NC = N / 2;
+  constexpr int S = NC >= kNThreads ? 1 : kNThreads / NC;  // ky segments per column
+  constexpr int SEG = (N + S - 1) / S;
+  const double pi = 3.14159265358979323846;
+  const int tid = threadIdx.x;
+  for (int ky = tid; ky < N; ky += kNThreads) {
+    if (2 * ky == N) {
+      phy[ky] = make_double2(0.0, 0.0);  // the Nyquist row is added separately
+      ay[ky] = 0.0;
+    } else {
+      const int kt = 2 * ky < N ? ky : ky - N;
+      double sn, cs;
+      sincospi(2.0 * (double)kt * sy / (double)N, &sn, &cs);
+      phy[ky] = make_double2(cs, sn);
+      ay[ky] = 2.0 * pi * (double)kt / (double)N;
+    }
+  }
+  __syncthreads();
+  double acc[kCoef];
+#pragma unroll
+  for (int q = 0; q < kCoef; ++q) acc[q] = 0.0;
+  // Nyquist row: Re[exp(i pi sy) (i pi)^n]
+  double ry[kOrder + 1];
+  {
+    double sn, cs;
+    sincospi(sy, &sn, &cs);
+    double2 t = make_double2(cs, sn);
+#pragma unroll
+    for (int n = 0; n <= kOrder; ++n) {
+      ry[n] = t.x;
+      t = make_double2(-pi * t.y, pi * t.x);
+    }
+  }
+  // columns kx < N/2, split into S ky segments
+  for (int item = tid; item < NC * S; item += kNThreads) {
+    const int kx = item / S, seg = item - kx * S;
+    const int y0 = seg * SEG, y1 = min(N, y0 + SEG);
+    double2 M[kOrder + 1];
+#pragma unroll
+    for (int n = 0; n <= kOrder; ++n) M[n] = make_double2(0.0, 0.0);
+    const float2* col = Xf + kx;
+    for (int ky = y0; ky < y1; ++ky) {
+      const float2 xf = col[(size_t)ky * H];
+      const double2 ph = phy[ky];
+      const double2 t = make_double2((double)xf.x * ph.x - (double)xf.y * ph.y,
+                                     (double)xf.x * ph.y + (double)xf.y * ph.x);
+      add_powers(M, t, ay[ky]);
+    }
+    if (y0 <= N / 2 && N / 2 < y1) {
+      const float2 xf = col[(size_t)(N / 2) * H];
+#pragma unroll
+      for (int n = 0; n <= kOrder; ++n) {
+        M[n].x += (double)xf.x * ry[n];
+        M[n].y += (double)xf.y * ry[n];
+      }
+    }
+    double sn, cs;
+    sincospi(2.0 * (double)kx * sx / (double)N, &sn, &cs);
+    add_terms(acc, M, make_double2(cs, sn), 2.0 * pi * (double)kx / (double)N, false,
+              kx == 0 ? 1.0 : 2.0);
+  }
+  // Nyquist column kx = N/2: every thread takes a few rows
+  {
+    double2 M[kOrder + 1];
+#pragma unroll
+    for (int n = 0; n <= kOrder; ++n) M[n] = make_double2(0.0, 0.0);
+    for (int ky = tid; ky < N; ky += kNThreads) {
+      const float2 xf = Xf[(size_t)ky * H + NC];
+      if (2 * ky == N) {
+#pragma unroll
+        for (int n = 0; n <= kOrder; ++n) {
+          M[n].x += (double)xf.x * ry[n];
+          M[n].y += (double)xf.y * ry[n];
+        }
+      } else {
+        const double2 ph = phy[ky];
+        add_powers(M, make_double2((double)xf.x * ph.x - (double)xf.y * ph.y,
+                                   (double)xf.x * ph.y + (double)xf.y * ph.x),
+                   ay[ky]);
+      }
+    }
+    double sn, cs;
+    sincospi(sx, &sn, &cs);
+    add_terms(acc, M, make_double2(cs, sn), pi, true, 1.0);
+  }
+  // deterministic block reduction of the coefficients
+  const double inv = 1.0 / ((double)N * (double)N);
+#pragma unroll
+  for (int q = 0; q < kCoef; ++q) {
     double v = acc[q];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    acc[q] = v;
+    if ((tid & 63) == 0) red[q][tid >> 6] = v;
   }
   __syncthreads();
-  if ((tid & 63) == 0)
-    for (int q = 0; q < 6; ++q) red[q][tid >> 6] = acc[q];
-  __syncthreads();
-  double r[6];
-  for (int q = 0; q < 6; ++q) {
-    double v = 0;
-    for (int w = 0; w < kNThreads / 64; ++w) v += red[q][w];
-    r[q] = v / ((double)N * (double)N);
+  if (tid < kCoef) {
+    double v = 0.0;
+    for (int w = 0; w < kNThreads / 64; ++w) v += red[tid][w];
+    coef[tid] = v * inv;
   }
   __syncthreads();
-  return CEval{r[0], r[1], r[2], r[3], r[4], r[5]};
+}
+
+__device__ void write_special(ccpt_result* out, unsigned status) {
+  ccpt_result r;
+  r.reserved = 0;
+  const double v = status == CCPT_ST_NONFINITE ? __builtin_nan("") : 0.0;
+  r.d[0] = r.d[1] = v;
+  r.peak = v;
+  r.hess[0] = r.hess[1] = r.hess[2] = v;
+  r.d_grid[0] = r.d_grid[1] = (float)v;
+  r.p[0] = r.p[1] = 0;
+  r.status = status;
+  *out = r;
 }
 
 template <int N>
 __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step_limit) {
-  constexpr int H = N / 2 + 1;
-  __shared__ double2 ey[N][3];
-  __shared__ double red[6][kNThreads / 64];
+  __shared__ double2 phy[N];
+  __shared__ double ay[N];
+  __shared__ double red[kCoef][kNThreads / 64];
+  __shared__ double coef[kCoef];
+  __shared__ double ctl[3];  // next centre y, x; another pass?
   const int f = blockIdx.x;
   const int tid = threadIdx.x;
   const FrameState st = g.st[f];
   const FrameDesc d = g.desc[g.first + f];
   ccpt_result* out = g.out + d.out_idx;
-  ccpt_result r;
-  r.reserved = 0;
   if (st.flags & CCPT_ST_NONFINITE) {
-    if (tid == 0) {
-      const double nan = __builtin_nan("");
-      r.d[0] = r.d[1] = nan;
-      r.peak = nan;
-      r.hess[0] = r.hess[1] = r.hess[2] = nan;
-      r.d_grid[0] = r.d_grid[1] = __builtin_nanf("");
-      r.p[0] = r.p[1] = 0;
-      r.status = CCPT_ST_NONFINITE;
-      *out = r;
-    }
+    if (tid == 0) write_special(out, CCPT_ST_NONFINITE);
     return;
   }
   if (st.amin == st.amax) {
-    if (tid == 0) {
-      r.d[0] = r.d[1] = 0.0;
-      r.peak = 0.0;
-      r.hess[0] = r.hess[1] = r.hess[2] = 0.0;
-      r.d_grid[0] = r.d_grid[1] = 0.f;
-      r.p[0] = r.p[1] = 0;
-      r.status = CCPT_ST_FLAT;
-      *out = r;
-    }
+    if (tid == 0) write_special(out, CCPT_ST_FLAT);
     return;
   }
   unsigned pk = key_index(st.peak_key);
@@ -151,43 +249,71 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
   const int my = gk / g.M, mx = gk % g.M;
   const double dgy = py + (double)(my - g.c) / g.u;
   const double dgx = px + (double)(mx - g.c) / g.u;
-  const float2* Xf = g.X + (size_t)f * N * H;
+  const float2* Xf = g.X + (size_t)f * N * (N / 2 + 1);
 
+  // the iterate and the decisions live in thread 0; the centre is broadcast
   double sy = dgy, sx = dgx;
   unsigned status = 0;
-  for (int it = 0; it < g.newton_iters; ++it) {
-    const CEval e = eval_c<N>(Xf, sy, sx, ey, red);
-    const double det = e.hyy * e.hxx - e.hxy * e.hxy;
-    if (!(e.hyy < 0.0 && det > 0.0)) {
-      status |= CCPT_ST_NEWTON_FALLBACK;
-      sy = dgy;
-      sx = dgx;
-      break;
+  bool done = false;
+  int it_left = g.newton_iters;
+  double cy = dgy, cx = dgx;
+  Deriv fin{0, 0, 0, 0, 0, 0};
+  for (int pass = 0; pass < kMaxPasses; ++pass) {
+    build_model<N>(Xf, cy, cx, phy, ay, red, coef);
+    if (tid == 0) {
+      while (!done && it_left > 0) {
+        const Deriv e = model_eval(coef, sy - cy, sx - cx);
+        const double det = e.hyy * e.hxx - e.hxy * e.hxy;
+        if (!(e.hyy < 0.0 && det > 0.0)) {
+          status |= CCPT_ST_NEWTON_FALLBACK;
+          sy = dgy;
+          sx = dgx;
+          done = true;
+          break;
+        }
+        const double ty = -(e.hxx * e.gy - e.hxy * e.gx) / det;
+        const double tx = -(e.hyy * e.gx - e.hxy * e.gy) / det;
+        if (fmax(fabs(ty), fabs(tx)) > step_limit) {
+          status |= CCPT_ST_NEWTON_FALLBACK;
+          sy = dgy;
+          sx = dgx;
+          done = true;
+          break;
+        }
+        sy += ty;
+        sx += tx;
+        --it_left;
+        if (fmax(fabs(sy - cy), fabs(sx - cx)) > kModelRadius) break;  // rebuild around sy, sx
+      }
+      if (it_left == 0) done = true;
+      if (done && fmax(fabs(sy - py), fabs(sx - px)) > g.half_window) {
+        status |= CCPT_ST_WINDOW_EXIT;
+        sy = dgy;
+        sx = dgx;
+      }
+      bool again = !done || fmax(fabs(sy - cy), fabs(sx - cx)) > kModelRadius;
+      if (pass == kMaxPasses - 1) again = false;  // out of passes: use the last model
+      if (!again) fin = model_eval(coef, sy - cy, sx - cx);
+      ctl[0] = sy;
+      ctl[1] = sx;
+      ctl[2] = again ? 1.0 : 0.0;
     }
-    const double ty = -(e.hxx * e.gy - e.hxy * e.gx) / det;
-    const double tx = -(e.hyy * e.gx - e.hxy * e.gy) / det;
-    if (fmax(fabs(ty), fabs(tx)) > step_limit) {
-      status |= CCPT_ST_NEWTON_FALLBACK;
-      sy = dgy;
-      sx = dgx;
-      break;
-    }
-    sy += ty;
-    sx += tx;
+    __syncthreads();
+    const bool again = ctl[2] != 0.0;
+    cy = ctl[0];
+    cx = ctl[1];
+    __syncthreads();
+    if (!again) break;
   }
-  if (fmax(fabs(sy - py), fabs(sx - px)) > g.half_window) {
-    status |= CCPT_ST_WINDOW_EXIT;
-    sy = dgy;
-    sx = dgx;
-  }
-  const CEval e = eval_c<N>(Xf, sy, sx, ey, red);
   if (tid == 0) {
+    ccpt_result r;
+    r.reserved = 0;
     r.d[0] = sy;
     r.d[1] = sx;
-    r.peak = e.c;
-    r.hess[0] = e.hyy;
-    r.hess[1] = e.hxy;
-    r.hess[2] = e.hxx;
+    r.peak = fin.c;
+    r.hess[0] = fin.hyy;
+    r.hess[1] = fin.hxy;
+    r.hess[2] = fin.hxx;
     r.d_grid[0] = (float)dgy;
     r.d_grid[1] = (float)dgx;
     r.p[0] = py;
