@@ -419,6 +419,221 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
   }
 }
 
+
+// Wide variant for N >= 256: one block per frame and group of up to MT
+// 32-row m-tiles, one wave per 32-column kx tile.  Each frame's split
+// spectrum is streamed once from memory straight into the B operands (no
+// LDS staging, each fragment feeds 6 MT matrix instructions); the folded
+// K' rows of the block are built per 32-ky chunk in LDS and shared by all
+// waves.  The Nyquist column is accumulated in FP32 by the thread that
+// builds the row.  Stage B then runs m-tile by m-tile.
+template <int N, int MT>
+__global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
+    k_updft_bf16x2_wide(GroupParams g, const float2* __restrict__ Ktab,
+                        const unsigned short* __restrict__ WbT, int Mp) {
+  constexpr int H = N / 2 + 1;
+  constexpr int NC = N / 2;
+  constexpr int NW = (NC + 31) / 32;  // waves = kx tiles
+  constexpr int NTH = 64 * NW;
+  constexpr int P = xb_pitch(N);
+  constexpr int KC = 32;
+  constexpr int KCS = KC + 4;
+  constexpr int ROWS = MT * 32;
+  constexpr int KB = (N + 31) / 32 * 32;
+  constexpr int YST = KB + 8;
+  constexpr int KW = 2 * ROWS * KCS;
+  constexpr int YW = 32 * YST;
+  constexpr int RAWW = KW > YW ? KW : YW;
+  static_assert(ROWS <= NTH, "one thread per K' row");
+  __shared__ __attribute__((aligned(16))) unsigned raw[RAWW];
+  __shared__ float2 twf[N];
+  __shared__ float2 xnyq[N];  // Nyquist column X[ky, N/2] of the frame
+  __shared__ float nyq[ROWS];
+  __shared__ unsigned long long red[NW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = blockIdx.y;
+  const int m0 = blockIdx.x * ROWS;
+  const int mt_here = min(MT, (Mp - m0) / 32);
+  const FrameState st = g.st[f];
+  if (frame_skipped(st)) return;
+  unsigned pk = key_index(st.peak_key);
+  if (pk >= (unsigned)(N * N)) pk = 0;
+  const int iy = pk / N, ix = pk % N;
+  for (int i = tid; i < N; i += NTH) {
+    twf[i] = cconj(g.tw[i]);
+    xnyq[i] = g.X[(size_t)f * N * H + (size_t)i * H + NC];
+  }
+
+  unsigned* ks_hi = raw;
+  unsigned* ks_lo = raw + ROWS * KCS;
+  const unsigned* Xbh = g.Xb + (size_t)f * 2 * NC * P;
+  const unsigned* Xbl = Xbh + (size_t)NC * P;
+  const int h = lane >> 5, j = lane & 31;
+  const int kxrow = wave * 32 + j;
+  const bool bvalid = kxrow < NC;
+
+  f32x16 accr[MT], acci[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) accr[t][v] = acci[t][v] = 0.f;
+  float nacc = 0.f;
+  const bool krow = tid < mt_here * 32;
+  __syncthreads();
+
+  for (int k0 = 0; k0 < P; k0 += KC) {
+    u32x4 bh[KC / 8], bl[KC / 8];
+#pragma unroll
+    for (int s8 = 0; s8 < KC / 8; ++s8) {
+      const int col = k0 + s8 * 8 + 4 * h;
+      if (bvalid) {
+        bh[s8] = *(const u32x4*)(Xbh + (size_t)kxrow * P + col);
+        bl[s8] = *(const u32x4*)(Xbl + (size_t)kxrow * P + col);
+      } else {
+        bh[s8] = u32x4{0u, 0u, 0u, 0u};
+        bl[s8] = u32x4{0u, 0u, 0u, 0u};
+      }
+    }
+    if (krow) {
+      // this thread's K row segment, fetched with 16-byte loads before use
+      const int m = tid;
+      const float4* krow_p = (const float4*)(Ktab + (size_t)(m0 + m) * N + k0);
+      constexpr int Q = KC / 2;  // float4 = two complex values
+      float4 kq[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        kq[q] = (k0 + 2 * q < N) ? krow_p[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int kk = 2 * q + e;
+          const int ky = k0 + kk;
+          float2 kv = make_float2(0.f, 0.f);
+          if (ky < N) {
+            const float2 kr = e ? make_float2(kq[q].z, kq[q].w) : make_float2(kq[q].x, kq[q].y);
+            kv = cmul(kr, twf[(ky * iy) % N]);
+            const float2 xn = xnyq[ky];
+            nacc += kv.x * xn.x - kv.y * xn.y;
+          }
+          unsigned wh, wl;
+          split_pair(kv, wh, wl);
+          ks_hi[m * KCS + kk] = wh;
+          ks_lo[m * KCS + kk] = wl;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s8 = 0; s8 < KC / 8; ++s8) {
+      const int col = s8 * 8 + 4 * h;
+      const bf16x8 b_h = as_bf(bh[s8]), b_l = as_bf(bl[s8]);
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        if (t < mt_here) {
+          const u32x4 ah = *(const u32x4*)(ks_hi + (t * 32 + j) * KCS + col);
+          const u32x4 al = *(const u32x4*)(ks_lo + (t * 32 + j) * KCS + col);
+          const bf16x8 arh = as_bf(neg_im(ah)), aih = as_bf(swap_ri(ah));
+          const bf16x8 arl = as_bf(neg_im(al)), ail = as_bf(swap_ri(al));
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, b_h, accr[t], 0, 0, 0);
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, b_l, accr[t], 0, 0, 0);
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, b_h, accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, b_h, acci[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, b_l, acci[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, b_h, acci[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (krow) nyq[tid] = (ix & 1) ? -nacc : nacc;  // kx phase exp(i pi p_x) of the Nyquist column
+  // kx phase of the fold
+  if (bvalid) {
+    const float2 ph = twf[(kxrow * ix) % N];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float yr = accr[t][v], yi = acci[t][v];
+        accr[t][v] = yr * ph.x - yi * ph.y;
+        acci[t][v] = yr * ph.y + yi * ph.x;
+      }
+  }
+  unsigned short* ymh = (unsigned short*)raw;
+  unsigned short* yml = ymh + 32 * YST;
+  const int ntb = 2 * (Mp / 16);
+  unsigned long long best = 0;
+  const int l16 = lane & 15, q4 = lane >> 4;
+  const unsigned short* WbL = WbT + (size_t)Mp * KB;
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    if (t >= mt_here) break;
+    __syncthreads();
+    for (int i = tid; i < 32 * (KB - N); i += NTH) {
+      const int r = i / (KB - N), c = N + i % (KB - N);
+      ymh[r * YST + c] = 0;
+      yml[r * YST + c] = 0;
+    }
+    if (tid < 32) {
+      const float v = nyq[t * 32 + tid];
+      const unsigned a = bf16_bits(v);
+      ymh[tid * YST + NC] = (unsigned short)a;
+      yml[tid * YST + NC] = (unsigned short)bf16_bits(v - bf16_float(a));
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = (v >> 2) * 8 + h * 4 + (v & 3);
+      if (bvalid) {
+        const unsigned a = bf16_bits(accr[t][v]);
+        ymh[i * YST + kxrow] = (unsigned short)a;
+        yml[i * YST + kxrow] = (unsigned short)bf16_bits(accr[t][v] - bf16_float(a));
+        if (kxrow >= 1) {
+          const unsigned b = bf16_bits(acci[t][v]);
+          ymh[i * YST + NC + kxrow] = (unsigned short)b;
+          yml[i * YST + NC + kxrow] = (unsigned short)bf16_bits(acci[t][v] - bf16_float(b));
+        }
+      }
+    }
+    __syncthreads();
+    const int mrow0 = m0 + t * 32;
+    for (int T = wave; T < ntb; T += NW) {
+      const int mt = T & 1, nt = T >> 1;
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      const unsigned short* ah_p = ymh + (mt * 16 + l16) * YST + 8 * q4;
+      const unsigned short* al_p = yml + (mt * 16 + l16) * YST + 8 * q4;
+      const unsigned short* bh_p = WbT + (size_t)(nt * 16 + l16) * KB + 8 * q4;
+      const unsigned short* bl_p = WbL + (size_t)(nt * 16 + l16) * KB + 8 * q4;
+#pragma unroll 4
+      for (int k = 0; k < KB; k += 32) {
+        const bf16x8 a_h = as_bf(*(const u32x4*)(ah_p + k));
+        const bf16x8 a_l = as_bf(*(const u32x4*)(al_p + k));
+        const bf16x8 w_h = as_bf(*(const u32x4*)(bh_p + k));
+        const bf16x8 w_l = as_bf(*(const u32x4*)(bl_p + k));
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_h, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_l, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, w_h, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int my = mrow0 + mt * 16 + q4 * 4 + v;
+        const int mx = nt * 16 + l16;
+        if (my < g.M && mx < g.M) {
+          const unsigned long long key = peak_key(acc[v], (unsigned)(my * g.M + mx));
+          best = key > best ? key : best;
+        }
+      }
+    }
+  }
+  best = wmax64(best);
+  if (lane == 0) red[wave] = best;
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < NW; ++w) best = red[w] > best ? red[w] : best;
+    atomicMax(&g.st[f].grid_key, best);
+  }
+}
+
 template <int N>
 static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
   const int mtiles = t.Mp / 32;
@@ -427,8 +642,16 @@ static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
                        (const float2*)t.ky, (const float*)t.wb, t.Mp);
   } else if (t.precision == CCPT_PREC_BF16X2) {
     if (!g.Xb) return -1;
-    hipLaunchKernelGGL((k_updft_bf16x2<N>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
-                       (const float2*)t.ky, (const unsigned short*)t.wb, t.Mp);
+    if constexpr (N >= 256) {
+      constexpr int MT = 5;
+      constexpr int NW = (N / 2 + 31) / 32;
+      hipLaunchKernelGGL((k_updft_bf16x2_wide<N, MT>), dim3((mtiles + MT - 1) / MT, g.count),
+                         dim3(64 * NW), 0, s, g, (const float2*)t.ky, (const unsigned short*)t.wb,
+                         t.Mp);
+    } else {
+      hipLaunchKernelGGL((k_updft_bf16x2<N>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
+                         (const float2*)t.ky, (const unsigned short*)t.wb, t.Mp);
+    }
   } else {
     return -2;
   }
