@@ -24,12 +24,19 @@ constexpr int rows_per_block(int N, int budget) {
   return best;
 }
 
-// columns per block of the column pass: at most 2048 complex values per
-// LDS buffer, no wider than the N/2+1 columns need
+// columns per block of the column pass: at most 4096 complex values per
+// LDS buffer (16 columns of 256: the row-major X stores are 128-byte lines),
+// no wider than the N/2+1 columns need
 constexpr int cols_per_block(int N) {
   int cb = 1;
-  while (cb * 2 * N <= 2048 && cb < N / 2 + 1) cb *= 2;
+  while (cb * 2 * N <= 4096 && cb < N / 2 + 1) cb *= 2;
   return cb;
+}
+
+// rows per block of the row passes: 16 rows (128-byte runs of the
+// column-major intermediate) when they fit, else the largest divisor of N
+constexpr int row_block(int N) {
+  return (N % 16 == 0 && 16 * (N / 2 + 1) <= 4200) ? 16 : rows_per_block(N, 2048);
 }
 
 __device__ __forceinline__ float load_px(const void* p, int dtype, long idx) {
@@ -103,9 +110,10 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, f
                                                        float2* __restrict__ T, FrameState* st,
                                                        const float2* __restrict__ gtw) {
   constexpr int L = N / 2, H = N / 2 + 1;
+  constexpr int LS = L + 1;  // padded row stride in LDS
   __shared__ float2 tw[N];
-  __shared__ float2 bufA[RPB * L];
-  __shared__ float2 bufB[RPB * L];
+  __shared__ float2 bufA[RPB * LS];
+  __shared__ float2 bufB[RPB * LS];
   __shared__ unsigned red[3][kThreads / 64];
   const int tid = threadIdx.x;
   const int f = blockIdx.y;
@@ -115,22 +123,43 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, f
   int dtype, pitch;
   img_of(src, f, data, dtype, pitch);
   unsigned kmin = 0xFFFFFFFFu, kmax = 0, bad = 0;
-  for (int i = tid; i < RPB * L; i += kThreads) {
-    const int r = i / L, c = i - r * L;
-    const long idx = (long)(y0 + r) * pitch + 2 * c;
-    float a0 = load_px(data, dtype, idx);
-    float a1 = load_px(data, dtype, idx + 1);
-    if (weight == 1) {
-      a0 = -1.0f / (a0 + eps);
-      a1 = -1.0f / (a1 + eps);
-    } else if (weight == 2) {
-      a0 = (a0 + eps) * (a0 + eps);
-      a1 = (a1 + eps) * (a1 + eps);
+  auto pro = [&](float a) {
+    if (weight == 1) a = -1.0f / (a + eps);
+    else if (weight == 2) a = (a + eps) * (a + eps);
+    if (!isfinite(a)) bad = 1;
+    kmin = min(kmin, f2key(a));
+    kmax = max(kmax, f2key(a));
+    return a;
+  };
+  const bool vec16 = dtype == CCPT_U16 && N % 8 == 0 && pitch % 8 == 0 &&
+                     ((uintptr_t)data & 15) == 0;
+  const bool vec32 = dtype == CCPT_F32 && N % 4 == 0 && pitch % 4 == 0 &&
+                     ((uintptr_t)data & 15) == 0;
+  if (vec16) {
+    // 8 pixels (16 bytes) per load
+    for (int i = tid; i < RPB * (N / 8); i += kThreads) {
+      const int r = i / (N / 8), q = i - r * (N / 8);
+      const uint4 v = *(const uint4*)((const unsigned short*)data + (long)(y0 + r) * pitch + 8 * q);
+      const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        bufA[r * LS + 4 * q + e] = make_float2(pro((float)(w[e] & 0xFFFFu)), pro((float)(w[e] >> 16)));
     }
-    if (!isfinite(a0) || !isfinite(a1)) bad = 1;
-    kmin = min(kmin, min(f2key(a0), f2key(a1)));
-    kmax = max(kmax, max(f2key(a0), f2key(a1)));
-    bufA[i] = make_float2(a0, a1);
+  } else if (vec32) {
+    for (int i = tid; i < RPB * (N / 4); i += kThreads) {
+      const int r = i / (N / 4), q = i - r * (N / 4);
+      const float4 v = *(const float4*)((const float*)data + (long)(y0 + r) * pitch + 4 * q);
+      bufA[r * LS + 2 * q] = make_float2(pro(v.x), pro(v.y));
+      bufA[r * LS + 2 * q + 1] = make_float2(pro(v.z), pro(v.w));
+    }
+  } else {
+    for (int i = tid; i < RPB * L; i += kThreads) {
+      const int r = i / L, c = i - r * L;
+      const long idx = (long)(y0 + r) * pitch + 2 * c;
+      const float a0 = pro(load_px(data, dtype, idx));
+      const float a1 = pro(load_px(data, dtype, idx + 1));
+      bufA[r * LS + c] = make_float2(a0, a1);
+    }
   }
   if (st) {
     kmin = wave_min_u32(kmin);
@@ -153,18 +182,19 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, f
     atomicMax(&st[f].amax, kmax);
     if (bad) atomicOr(&st[f].flags, (unsigned)CCPT_ST_NONFINITE);
   }
-  float2* z = fft_lds<L, -1, N>(bufA, bufB, RPB, L, tw);
+  float2* z = fft_lds<L, -1, N>(bufA, bufB, RPB, LS, tw);
   // unpack: X[k] = E[k] + W^k O[k], E = (Z[k] + conj Z[L-k]) / 2,
-  // O = (Z[k] - conj Z[L-k]) / (2i), W = exp(-2 pi i / N)
+  // O = (Z[k] - conj Z[L-k]) / (2i), W = exp(-2 pi i / N); stored column-major
+  // T[k][y] so each column k receives RPB consecutive rows
   float2* Tf = T + (size_t)f * N * H;
   for (int i = tid; i < RPB * H; i += kThreads) {
-    const int r = i / H, k = i - r * H;
-    const float2 zk = z[r * L + (k == L ? 0 : k)];
-    const float2 zc = cconj(z[r * L + (k == 0 ? 0 : L - k)]);
+    const int k = i / RPB, r = i - k * RPB;
+    const float2 zk = z[r * LS + (k == L ? 0 : k)];
+    const float2 zc = cconj(z[r * LS + (k == 0 ? 0 : L - k)]);
     const float2 e = cscale(cadd(zk, zc), 0.5f);
     const float2 d = csub(zk, zc);
     const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // d / (2i)
-    Tf[(size_t)(y0 + r) * H + k] = cadd(e, cmul(tw[k], o));
+    Tf[(size_t)k * N + y0 + r] = cadd(e, cmul(tw[k], o));
   }
 }
 
@@ -190,18 +220,26 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
   const int c0 = blockIdx.x * CB;
   const int ncol = min(CB, H - c0);
   for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
+  // T is column-major: column kx holds N consecutive rows
   float2* Tf = T + (size_t)f * N * H;
-  const float2* inp = (KIND == COL_INV) ? spec + (size_t)f * spec_stride : Tf;
-  for (int i = tid; i < N * CB; i += kThreads) {
-    const int y = i / CB, c = i - y * CB;
-    bufA[c * S + y] = c < ncol ? inp[(size_t)y * H + c0 + c] : make_float2(0.f, 0.f);
+  if constexpr (KIND == COL_INV) {
+    const float2* inp = spec + (size_t)f * spec_stride;  // row-major spectrum
+    for (int i = tid; i < N * CB; i += kThreads) {
+      const int y = i / CB, c = i - y * CB;
+      bufA[c * S + y] = c < ncol ? inp[(size_t)y * H + c0 + c] : make_float2(0.f, 0.f);
+    }
+  } else {
+    for (int i = tid; i < N * CB; i += kThreads) {
+      const int c = i / N, y = i - c * N;
+      bufA[c * S + y] = c < ncol ? Tf[(size_t)(c0 + c) * N + y] : make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
   if constexpr (KIND == COL_INV) {
     float2* r = fft_lds<N, +1, N>(bufA, bufB, CB, S, tw);
     for (int i = tid; i < N * CB; i += kThreads) {
-      const int y = i / CB, c = i - y * CB;
-      if (c < ncol) Tf[(size_t)y * H + c0 + c] = r[c * S + y];
+      const int c = i / N, y = i - c * N;
+      if (c < ncol) Tf[(size_t)(c0 + c) * N + y] = r[c * S + y];
     }
   } else {
     float2* r = fft_lds<N, -1, N>(bufA, bufB, CB, S, tw);
@@ -251,8 +289,8 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
       float2* o = (r == bufA) ? bufB : bufA;
       float2* q = fft_lds<N, +1, N>(r, o, CB, S, tw);
       for (int i = tid; i < N * CB; i += kThreads) {
-        const int y = i / CB, c = i - y * CB;
-        if (c < ncol) Tf[(size_t)y * H + c0 + c] = q[c * S + y];
+        const int c = i / N, y = i - c * N;
+        if (c < ncol) Tf[(size_t)(c0 + c) * N + y] = q[c * S + y];
       }
     }
   }
@@ -269,17 +307,22 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const float2* __restrict_
                                                        FrameState* st, float* img, float scale,
                                                        const float2* __restrict__ gtw) {
   constexpr int L = N / 2, H = N / 2 + 1;
+  constexpr int LS = L + 1;
   __shared__ float2 tw[N];
   __shared__ float2 raw[RPB * H];
-  __shared__ float2 bufA[RPB * L];
-  __shared__ float2 bufB[RPB * L];
+  __shared__ float2 bufA[RPB * LS];
+  __shared__ float2 bufB[RPB * LS];
   __shared__ unsigned long long red[kThreads / 64];
   const int tid = threadIdx.x;
   const int f = blockIdx.y;
   const int y0 = blockIdx.x * RPB;
   for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
-  const float2* Tf = T + (size_t)f * N * H + (size_t)y0 * H;
-  for (int i = tid; i < RPB * H; i += kThreads) raw[i] = Tf[i];
+  // column-major T: column k holds rows y0..y0+RPB-1 consecutively
+  const float2* Tf = T + (size_t)f * N * H + y0;
+  for (int i = tid; i < RPB * H; i += kThreads) {
+    const int k = i / RPB, r = i - k * RPB;
+    raw[r * H + k] = Tf[(size_t)k * N + r];
+  }
   __syncthreads();
   for (int i = tid; i < RPB * L; i += kThreads) {
     const int r = i / L, k = i - r * L;
@@ -287,15 +330,15 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const float2* __restrict_
     const float2 xc = cconj(raw[r * H + L - k]);
     const float2 e = cscale(cadd(xk, xc), 0.5f);
     const float2 o = cmul(cscale(csub(xk, xc), 0.5f), cconj(tw[k]));
-    bufA[i] = make_float2(e.x - o.y, e.y + o.x);  // e + i o
+    bufA[r * LS + k] = make_float2(e.x - o.y, e.y + o.x);  // e + i o
   }
   __syncthreads();
-  float2* z = fft_lds<L, +1, N>(bufA, bufB, RPB, L, tw);
+  float2* z = fft_lds<L, +1, N>(bufA, bufB, RPB, LS, tw);
   if constexpr (ARGMAX) {
     unsigned long long best = 0;
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
-      const float2 v = z[i];
+      const float2 v = z[r * LS + n];
       const unsigned flat = (unsigned)((y0 + r) * N + 2 * n);
       unsigned long long k0 = peak_key(v.x, flat);
       unsigned long long k1 = peak_key(v.y, flat + 1);
@@ -313,7 +356,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const float2* __restrict_
     float* out = img + (size_t)f * N * N + (size_t)y0 * N;
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
-      const float2 v = z[i];
+      const float2 v = z[r * LS + n];
       out[r * N + 2 * n] = v.x * scale;
       out[r * N + 2 * n + 1] = v.y * scale;
     }
@@ -322,7 +365,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const float2* __restrict_
 
 template <int N>
 static int xcorr_n(const GroupParams& g, hipStream_t s, const Marker& mark) {
-  constexpr int RPB = rows_per_block(N, 2048);
+  constexpr int RPB = row_block(N);
   constexpr int CB = cols_per_block(N);
   constexpr int H = N / 2 + 1;
   mark(CCPT_STAGE_INIT, 1);
@@ -348,7 +391,7 @@ template <int N>
 static int spectrum_n(const void* data, int dtype, int pitch, long img_stride, int n, int weight,
                       float eps, int conj_out, float2* T, float2* spec, const float2* tw,
                       hipStream_t s) {
-  constexpr int RPB = rows_per_block(N, 2048);
+  constexpr int RPB = row_block(N);
   constexpr int CB = cols_per_block(N);
   constexpr int H = N / 2 + 1;
   ImgSrc src{nullptr, 0, data, dtype, pitch, img_stride};
@@ -368,7 +411,7 @@ static int spectrum_n(const void* data, int dtype, int pitch, long img_stride, i
 template <int N>
 static int frame_spectra_n(const FrameDesc* desc, int first, int count, int mode, float eps,
                            float2* T, float2* spec, const float2* tw, hipStream_t s) {
-  constexpr int RPB = rows_per_block(N, 2048);
+  constexpr int RPB = row_block(N);
   constexpr int CB = cols_per_block(N);
   constexpr int H = N / 2 + 1;
   ImgSrc src{desc, first, nullptr, 0, 0, 0};
@@ -383,7 +426,7 @@ static int frame_spectra_n(const FrameDesc* desc, int first, int count, int mode
 template <int N>
 static int inverse_n(const float2* spec, int n, float scale, float2* T, float* img,
                      const float2* tw, hipStream_t s) {
-  constexpr int RPB = rows_per_block(N, 2048);
+  constexpr int RPB = row_block(N);
   constexpr int CB = cols_per_block(N);
   constexpr int H = N / 2 + 1;
   hipLaunchKernelGGL((k_cols<N, CB, COL_INV>), dim3((H + CB - 1) / CB, n), dim3(kThreads), 0, s,
