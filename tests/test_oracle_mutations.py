@@ -1,0 +1,92 @@
+"""Plausible mistakes planted in the oracle (on the CPU) must each be caught by
+one of the pins in test_oracle_pins.py; this shows the pins constrain every
+part of the oracle and are not a restatement of it."""
+import numpy as np
+import pytest
+
+import tests.test_oracle_pins as P
+from oracle import ccpt_oracle as O
+
+
+def _fails(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_nyquist_as_plain_exponential_is_caught(monkeypatch):
+    good = O.phi
+
+    def bad(n, s, order=0):
+        k = O.signed_freq(n)
+        w = 2.0 * np.pi * k / n
+        return np.exp(1j * w * s) * (1j * w) ** order  # no cos(pi s) at N/2
+
+    monkeypatch.setattr(O, "phi", bad)
+    _fails(P.test_p5_upsampled_dft_equals_zero_padded_ifft)
+    monkeypatch.setattr(O, "phi", good)
+
+
+def test_swapped_cross_power_roles_are_caught(monkeypatch):
+    monkeypatch.setattr(O, "cross_power", lambda A, B: np.conj(np.fft.fft2(A)) * np.fft.fft2(B))
+    _fails(P.test_p3_exact_integer_shifts_all_lags_16)
+
+
+def test_transposed_grid_axes_are_caught(monkeypatch):
+    good = O.upsampled_grid
+
+    def bad(X, p, u):
+        return good(X, p, u).T
+
+    monkeypatch.setattr(O, "upsampled_grid", bad)
+    _fails(P.test_p4_on_grid_shift_gives_exact_grid_estimate)
+
+
+def test_ccsn_positive_weight_is_caught(monkeypatch):
+    def bad(frame, ref, mode=O.MODE_CCU, eps=200.0):
+        I = np.asarray(frame, float)
+        E = np.asarray(ref, float)
+        if mode == O.MODE_CCU:
+            return I, E
+        return (I + eps) ** 2, 1.0 / (E + eps)
+
+    monkeypatch.setattr(O, "weights", bad)
+    _fails(P.test_p2_ccsn_sign_is_a_minimum)
+
+
+def test_wrong_derivative_sign_is_caught(monkeypatch):
+    good = O.phi
+
+    def bad(n, s, order=0):
+        v = good(n, s, order)
+        return -v if order == 1 else v
+
+    monkeypatch.setattr(O, "phi", bad)
+    _fails(P.test_p4_phase_ramp_subpixel_recovery, 64, 20, 3.0)
+
+
+def test_dropped_normalisation_is_caught(monkeypatch):
+    def bad(X, s, dy=0, dx=0):
+        ny, nx = X.shape
+        return float((O.phi(ny, s[0], dy) @ X @ O.phi(nx, s[1], dx)).real)
+
+    monkeypatch.setattr(O, "bandlimited", bad)
+    _fails(P.test_band_limited_derivatives_match_finite_differences)
+
+
+def test_adjoint_without_implicit_term_is_caught(monkeypatch):
+    good = O._shift_kernel
+
+    def bad(shape, s, lam, cbar):
+        return good(shape, s, np.zeros(2), cbar)
+
+    monkeypatch.setattr(O, "_shift_kernel", bad)
+    _fails(P.test_p11_adjoint_matches_central_differences, O.MODE_CCU)
+
+
+def test_fisher_without_poisson_weight_is_caught(monkeypatch):
+    def bad(mu):
+        dy, dx = O.derivative_images(mu)
+        return np.array([[np.sum(dy * dy), np.sum(dy * dx)], [np.sum(dx * dy), np.sum(dx * dx)]])
+
+    monkeypatch.setattr(O, "fisher", bad)
+    _fails(P.test_p9_crb_closed_form_zero_background)
