@@ -41,6 +41,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_tag):
+    """Per-frame HBM bytes of a kernel from the committed rocprofv3 counter
+    summary, if the kernel source is unchanged since the counters were taken
+    (the summary records the source's sha256); else None."""
+    import glob
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2310_08770_amd", "csrc", "updft.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(path):
+            m = re.search(r"traffic kernel=(\S+) bytes_per_frame=(\d+) source_sha256=([0-9a-f]+)", line)
+            if m and m.group(1) == kernel_tag and m.group(3) == sha:
+                return int(m.group(2))
+    return None
+
+
 def updft_flops_per_frame(n, M, precision):
     """Algorithmic flops of the upsampled matrix DFT per frame: the complex
     Stage A product (M x N by N x H) and the real-part Stage B product
@@ -128,6 +145,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-frame legs")
+    ap.add_argument("--no-tune", action="store_true", help="skip the chunk autotuner")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -174,6 +192,8 @@ def main():
     # ---- batched, headline precision, profiled for the roofline
     tr = Tracker(upsample=w.u, precision=args.precision, profile=True)
     tr.set_reference(ref_t)
+    chunk = tr.chunk(N) if args.no_tune else tr.autotune(N, n)
+    log(f"[bench] chunk {chunk} frames per launch ({'default' if args.no_tune else 'autotuned'})")
     rois = tr.rois(frames_t)
     out = torch.empty((n, 72), dtype=torch.uint8, device=dev)
     total, lat = time_batched(tr, frames_t, rois, out, args.steps, args.warmup, torch)
@@ -188,14 +208,16 @@ def main():
     flops_launch = updft_flops_per_frame(N, M, args.precision) * frames_per_launch
     achieved = flops_launch / (per_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    kernel_tag = f"k_updft_{'f32' if args.precision == 'fp32' else 'bf16x2_wide'}<{N}>"
+    traffic_pf = measured_traffic(kernel_tag)
     roofline = {
-        "kernel": f"k_updft_{'f32' if args.precision == 'fp32' else 'bf16x2'}<{N}>",
+        "kernel": kernel_tag,
         "bound": "mfma",
         "achieved": round(achieved, 2),
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": None,
+        "traffic": None if traffic_pf is None else int(traffic_pf * frames_per_launch),
         "launch_ms": round(per_launch_ms, 4),
         "frames_per_launch": round(frames_per_launch, 1),
         "flops_per_frame": updft_flops_per_frame(N, M, args.precision),
@@ -208,6 +230,8 @@ def main():
     try:
         tr2 = Tracker(upsample=w.u, precision=other)
         tr2.set_reference(ref_t)
+        if not args.no_tune:
+            tr2.autotune(N, n)
         out2 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
         tot2, lat2 = time_batched(tr2, frames_t, tr2.rois(frames_t), out2, max(3, args.steps // 3), 2, torch)
         r2 = decode(out2)
@@ -284,6 +308,7 @@ def main():
                         f"u=100, 1.5-px window (M={M}), CC-U, {args.precision} upsampled DFT, FP64 Newton x3",
             "frames_per_step": n,
             "upsample": w.u,
+            "chunk": chunk,
         },
         "batched_latency": {"p50_ms": round(float(np.median(lat)) * 1e3, 4),
                             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4)},

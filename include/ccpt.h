@@ -74,16 +74,21 @@ extern "C" {
 /* ---- options ---------------------------------------------------------- */
 enum ccpt_mode { CCPT_MODE_CCU = 0, CCPT_MODE_CCSN = 1 };
 
-/* arithmetic of the upsampled matrix DFT (the FFTs are always FP32, the
-   Newton step always FP64) */
+/* arithmetic of the correlation and the upsampled matrix DFT (the Newton
+   refinement is FP64 in every mode) */
 enum ccpt_precision {
-  CCPT_PREC_FP32 = 0,   /* FP32 matrix cores */
-  CCPT_PREC_BF16X2 = 1, /* operands split into bf16 hi + lo, three bf16
-                           products accumulated in FP32 */
-  CCPT_PREC_FP16X2 = 2  /* same with fp16 hi + lo (scaled) */
+  CCPT_PREC_FP32 = 0,   /* FP32 FFTs, FP32 matrix cores */
+  CCPT_PREC_BF16X2 = 1, /* FP32 FFTs; DFT operands split into bf16 hi + lo,
+                           three bf16 products accumulated in FP32 */
+  CCPT_PREC_FP16X2 = 2, /* reserved (fp16 hi + lo); ccpt_create rejects it */
+  CCPT_PREC_FP64 = 3    /* FFTs, cross-power spectrum, integer peak and the
+                           upsampled DFT all in FP64 (vector units): the
+                           accuracy mode, for agreement with an FP64
+                           definition well below 1e-9 px */
 };
 
-enum ccpt_dtype { CCPT_U16 = 0, CCPT_F32 = 1 };
+/* pixel types: uint16 (12-bit cameras), float32, float64 */
+enum ccpt_dtype { CCPT_U16 = 0, CCPT_F32 = 1, CCPT_F64 = 2 };
 
 #define CCPT_FLAG_GRAPH 1   /* capture each batch shape once in a hipGraph and
                                replay it on later calls */
@@ -197,10 +202,19 @@ int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_resul
    (CCPT_E_INVALID otherwise, checked on the host after the copy). */
 int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* stream);
 
-/* Measures the candidate schedules for frames of size n x n in batches
-   of `batch` and keeps the fastest for later calls.  Needs a reference
-   of that size.  Synchronises the stream. */
+/* Launch scheduling of the batched path (a10): frames of one size are run in
+   chunks whose spectra workspace stays resident in the Infinity Cache; the
+   chunk size trades that residency against the number of launches.
+   ccpt_autotune times ccpt_track_batch on `batch` frames of size n x n (each
+   frame is the context's reference of that size; timing does not depend on
+   content) for a range of chunk sizes and keeps the fastest for later calls
+   on this context.  Needs a reference of size n (CCPT_E_NOREF otherwise).
+   Allocates and synchronises the stream. */
 int ccpt_autotune(ccpt_ctx* ctx, int n, int batch, void* stream);
+
+/* Reads (set = 0) or sets (set != 0) the chunk size used for frames of size
+   n x n; 0 restores the default.  Lets a caller persist tuning results. */
+int ccpt_schedule(ccpt_ctx* ctx, int n, int* chunk, int set);
 
 /* With CCPT_FLAG_PROFILE: total GPU time (ms) and number of launches of
    each stage recorded since the last reset, summed over chunks and calls.

@@ -33,8 +33,8 @@ ST_NEWTON_FALLBACK = 8
 ST_WINDOW_EXIT = 16
 
 MODES = {"ccu": 0, "ccsn": 1}
-PRECISIONS = {"fp32": 0, "bf16x2": 1, "fp16x2": 2}
-U16, F32 = 0, 1
+PRECISIONS = {"fp32": 0, "bf16x2": 1, "fp16x2": 2, "fp64": 3}
+U16, F32, F64 = 0, 1, 2
 FLAG_GRAPH = 1
 FLAG_PROFILE = 2
 STAGES = ["init", "rows_fwd", "cols", "rows_inv", "updft", "newton", "grad"]
@@ -98,6 +98,8 @@ def lib():
         L.ccpt_fisher.restype = c_int
         L.ccpt_autotune.argtypes = [c_void_p, c_int, c_int, c_void_p]
         L.ccpt_autotune.restype = c_int
+        L.ccpt_schedule.argtypes = [c_void_p, c_int, POINTER(c_int), c_int]
+        L.ccpt_schedule.restype = c_int
         L.ccpt_stage_times.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int), c_int, c_int]
         L.ccpt_stage_times.restype = c_int
         L.ccpt_status_string.argtypes = [c_int]
@@ -109,8 +111,8 @@ def lib():
 
 
 EXPORTS = ["ccpt_default_options", "ccpt_create", "ccpt_destroy", "ccpt_set_reference",
-           "ccpt_track_batch", "ccpt_track_grad", "ccpt_fisher", "ccpt_autotune", "ccpt_stage_times",
-           "ccpt_status_string", "ccpt_last_error"]
+           "ccpt_track_batch", "ccpt_track_grad", "ccpt_fisher", "ccpt_autotune", "ccpt_schedule",
+           "ccpt_stage_times", "ccpt_status_string", "ccpt_last_error"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -118,7 +120,9 @@ def _dtype_code(t: torch.Tensor) -> int:
         return U16
     if t.dtype == torch.float32:
         return F32
-    raise TypeError(f"frames must be uint16 (or int16 bits) or float32, got {t.dtype}")
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"frames must be uint16 (or int16 bits), float32 or float64, got {t.dtype}")
 
 
 def _stream_handle(stream) -> int:
@@ -271,5 +275,39 @@ class Tracker:
         self._check(lib().ccpt_stage_times(self._h, ms, cnt, k, 1 if reset else 0))
         return {STAGES[i]: (ms[i], cnt[i]) for i in range(k)}
 
-    def autotune(self, n, batch, stream=None):
+    def autotune(self, n, batch, stream=None, cache=None):
+        """Tunes the chunk size for n x n frames in batches of `batch` (needs a
+        reference of that size).  With `cache` (a JSON file path) the choice is
+        read from / written to it, keyed by GPU arch, size, u, precision, mode."""
+        key = None
+        if cache:
+            import json
+            props = torch.cuda.get_device_properties(self.device)
+            arch = getattr(props, "gcnArchName", props.name)
+            o = self.options
+            key = f"{arch}|N={n}|batch={batch}|u={o.upsample}|prec={o.precision}|mode={o.mode}"
+            try:
+                with open(cache) as fh:
+                    table = json.load(fh)
+            except (OSError, ValueError):
+                table = {}
+            if key in table:
+                self.set_chunk(n, int(table[key]))
+                return int(table[key])
         self._check(lib().ccpt_autotune(self._h, int(n), int(batch), c_void_p(_stream_handle(stream))))
+        chunk = self.chunk(n)
+        if cache:
+            table[key] = chunk
+            with open(cache, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+        return chunk
+
+    def chunk(self, n):
+        """Frames per launch chunk currently used for n x n frames."""
+        c = c_int(0)
+        self._check(lib().ccpt_schedule(self._h, int(n), ctypes.byref(c), 0))
+        return c.value
+
+    def set_chunk(self, n, chunk):
+        c = c_int(int(chunk))
+        self._check(lib().ccpt_schedule(self._h, int(n), ctypes.byref(c), 1))

@@ -31,13 +31,19 @@ struct SizeTables {
   float2* tw = nullptr;  // N
   void* ky = nullptr;
   void* wb = nullptr;
+  unsigned* kfold = nullptr;  // split precision, N >= kWideMinN
   int Mp = 0;
+  // FP64 mode
+  double2* tw64 = nullptr;  // N
+  double2* ky64 = nullptr;  // [Mp][N]
+  double2* wb64 = nullptr;  // [N/2+1][Mp]
 };
 
 struct Ref {
   int n = 0;
-  float2* spec = nullptr;  // conj F[B], N x (N/2+1)
-  float* img = nullptr;    // E as float (N x N), kept for the CC-SN chain rule
+  float2* spec = nullptr;     // conj F[B], N x (N/2+1) (the adjoint always uses it)
+  double2* spec64 = nullptr;  // the same in FP64 (FP64 mode)
+  float* img = nullptr;       // E as float (N x N), kept for the CC-SN chain rule
 };
 
 struct Schedule {
@@ -90,6 +96,9 @@ struct ccpt_ctx {
   hipEvent_t small_evt = nullptr;
   void* acc_buf = nullptr;
   size_t acc_cap = 0;
+  // FP32 split-K partials of small launches
+  void* ypart = nullptr;
+  size_t ypart_cap = 0;
   // errors
   int last_code = CCPT_OK;
   std::string last_msg;
@@ -123,16 +132,28 @@ int set_device(ccpt_ctx* ctx) {
   return CCPT_OK;
 }
 
+bool fp64(const ccpt_ctx* ctx) { return ctx->o.precision == CCPT_PREC_FP64; }
+bool split(const ccpt_ctx* ctx) { return ctx->o.precision == CCPT_PREC_BF16X2; }
+
 double step_limit(const ccpt_ctx* ctx) {
   const double grid = 1.0 / ctx->o.upsample;
   // split-precision grids locate the maximum less exactly than one grid step
-  return ctx->o.precision == CCPT_PREC_FP32 ? grid : std::max(grid, kSplitStepLimit);
+  return split(ctx) ? std::max(grid, kSplitStepLimit) : grid;
+}
+
+template <typename T>
+int upload(ccpt_ctx* ctx, T*& dst, const std::vector<T>& src) {
+  HIP_CHECK(ctx, hipMalloc(&dst, src.size() * sizeof(T)));
+  HIP_CHECK(ctx, hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return CCPT_OK;
 }
 
 int ensure_tables(ccpt_ctx* ctx, int n) {
   if (ctx->tables.count(n)) return CCPT_OK;
   SizeTables t;
-  HostTables h = build_tables(n, ctx->o.upsample, ctx->M, ctx->c, ctx->o.precision);
+  // the FP64 mode keeps the FP32 tables too (twiddles of the adjoint and Fisher paths)
+  HostTables h = build_tables(n, ctx->o.upsample, ctx->M, ctx->c,
+                              fp64(ctx) ? CCPT_PREC_FP32 : ctx->o.precision);
   t.Mp = h.Mp;
   HIP_CHECK(ctx, hipMalloc(&t.tw, h.tw.size() * sizeof(float2)));
   HIP_CHECK(ctx, hipMemcpy(t.tw, h.tw.data(), h.tw.size() * sizeof(float2), hipMemcpyHostToDevice));
@@ -140,6 +161,21 @@ int ensure_tables(ccpt_ctx* ctx, int n) {
   HIP_CHECK(ctx, hipMemcpy(t.ky, h.ky.data(), h.ky.size(), hipMemcpyHostToDevice));
   HIP_CHECK(ctx, hipMalloc(&t.wb, h.wb.size()));
   HIP_CHECK(ctx, hipMemcpy(t.wb, h.wb.data(), h.wb.size(), hipMemcpyHostToDevice));
+  if (fp64(ctx)) {
+    HostTables64 h64 = build_tables64(n, ctx->o.upsample, ctx->M, ctx->c, t.Mp);
+    int rc = upload(ctx, t.tw64, h64.tw);
+    if (!rc) rc = upload(ctx, t.ky64, h64.ky);
+    if (!rc) rc = upload(ctx, t.wb64, h64.wb);
+    if (rc) return rc;
+  }
+  if (split(ctx) && n >= kWideMinN) {
+    const size_t words = (size_t)n * 2 * t.Mp * xb_pitch(n);
+    if (hipMalloc(&t.kfold, words * sizeof(unsigned)) != hipSuccess)
+      return fail(ctx, CCPT_E_NOMEM, "folded table of %zu bytes", words * sizeof(unsigned));
+    if (launch_build_kfold(t.kfold, n, ctx->o.upsample, ctx->M, ctx->c, t.Mp, nullptr))
+      return fail(ctx, CCPT_E_HIP, "folded table launch failed");
+    HIP_CHECK(ctx, hipDeviceSynchronize());
+  }
   ctx->tables[n] = t;
   return CCPT_OK;
 }
@@ -173,8 +209,11 @@ size_t spec_elems(int n) { return (size_t)n * (n / 2 + 1); }
 size_t split_words(int n) { return (size_t)2 * (n / 2) * xb_pitch(n); }
 
 size_t frame_ws_bytes(int n, int precision) {
+  if (precision == CCPT_PREC_FP64)
+    return 2 * spec_elems(n) * sizeof(double2) + (size_t)(n / row_block64(n)) * sizeof(PeakCand) +
+           sizeof(FrameState);
   size_t b = 2 * spec_elems(n) * sizeof(float2) + sizeof(FrameState);
-  if (precision != CCPT_PREC_FP32) b += split_words(n) * sizeof(unsigned);
+  if (precision == CCPT_PREC_BF16X2) b += split_words(n) * sizeof(unsigned);
   return b;
 }
 
@@ -195,11 +234,20 @@ int chunk_for(const ccpt_ctx* ctx, int n) {
 // 16-byte aligned: spectra rows hold an even number of float2).
 void carve(ccpt_ctx* ctx, int n, int chunk, GroupParams& g) {
   const size_t spec = spec_elems(n);
+  if (fp64(ctx)) {
+    g.T = g.X = nullptr;
+    g.Xb = nullptr;
+    g.T64 = (double2*)ctx->ws;
+    g.X64 = g.T64 + spec * chunk;
+    g.cand = (PeakCand*)(g.X64 + spec * chunk);
+    g.st = (FrameState*)(g.cand + (size_t)(n / row_block64(n)) * chunk);
+    return;
+  }
   g.T = (float2*)ctx->ws;
   g.X = g.T + spec * chunk;
   char* p = (char*)(g.X + spec * chunk);
   g.Xb = nullptr;
-  if (ctx->o.precision != CCPT_PREC_FP32) {
+  if (split(ctx)) {
     g.Xb = (unsigned*)p;
     p += split_words(n) * sizeof(unsigned) * chunk;
   }
@@ -209,17 +257,24 @@ void carve(ccpt_ctx* ctx, int n, int chunk, GroupParams& g) {
 int check_image(ccpt_ctx* ctx, const void* data, int ny, int nx, int pitch, int dtype,
                 const char* what, int idx) {
   if (!data) return fail(ctx, CCPT_E_INVALID, "%s %d: null data", what, idx);
-  if (dtype != CCPT_U16 && dtype != CCPT_F32)
+  if (dtype != CCPT_U16 && dtype != CCPT_F32 && dtype != CCPT_F64)
     return fail(ctx, CCPT_E_INVALID, "%s %d: unknown dtype %d", what, idx, dtype);
   if (ny <= 0 || nx <= 0 || pitch < nx)
     return fail(ctx, CCPT_E_INVALID, "%s %d: bad shape %dx%d pitch %d", what, idx, ny, nx, pitch);
   if (ny != nx || !supported_size(nx))
     return fail(ctx, CCPT_E_UNSUPPORTED, "%s %d: %dx%d is not a supported square size", what,
                 idx, ny, nx);
-  const size_t align = dtype == CCPT_U16 ? 2 : 4;
+  const size_t align = dtype_bytes(dtype);
   if ((uintptr_t)data % align)
     return fail(ctx, CCPT_E_INVALID, "%s %d: misaligned data", what, idx);
   return CCPT_OK;
+}
+
+// One pixel of a host copy of an image.
+double pixel(const void* raw, int dtype, size_t k) {
+  if (dtype == CCPT_U16) return (double)((const uint16_t*)raw)[k];
+  if (dtype == CCPT_F64) return ((const double*)raw)[k];
+  return (double)((const float*)raw)[k];
 }
 
 GroupParams base_params(ccpt_ctx* ctx, int n) {
@@ -227,6 +282,8 @@ GroupParams base_params(ccpt_ctx* ctx, int n) {
   g.tw = ctx->tables[n].tw;
   g.mode = ctx->o.mode;
   g.eps = (float)ctx->o.eps;
+  g.eps64 = ctx->o.eps;
+  g.tw64 = ctx->tables[n].tw64;
   g.u = ctx->o.upsample;
   g.M = ctx->M;
   g.c = ctx->c;
@@ -269,12 +326,23 @@ Marker marker_of(ccpt_ctx* ctx, hipStream_t s) {
   return m;
 }
 
+// Bytes of FP32 split-K partials a launch of `count` frames of size n uses
+// (0 when the launch is large enough to fill the GPU without splitting).
+size_t split_partials_bytes(const ccpt_ctx* ctx, int n, int count) {
+  if (ctx->o.precision != CCPT_PREC_FP32) return 0;
+  auto it = ctx->tables.find(n);
+  if (it == ctx->tables.end()) return 0;
+  const int mtiles = it->second.Mp / 32;
+  if ((long)count * mtiles >= kSplitMaxBlocks) return 0;
+  return (size_t)count * mtiles * kSplitSlices * 32 * stage_b_k(n) * sizeof(float);
+}
+
 // Launches the whole tracking sequence for one size group, chunk by chunk.
 int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int count,
               ccpt_result* out, hipStream_t s) {
   const int chunk = std::min(count, chunk_for(ctx, n));
   SizeTables& t = ctx->tables[n];
-  UpdftTables ut{t.ky, t.wb, t.Mp, ctx->o.precision};
+  UpdftTables ut{t.ky, t.wb, t.Mp, ctx->o.precision, t.kfold};
   const Marker mark = marker_of(ctx, s);
   for (int c0 = 0; c0 < count; c0 += chunk) {
     GroupParams g = base_params(ctx, n);
@@ -283,9 +351,13 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
     g.count = std::min(chunk, count - c0);
     g.out = out;
     carve(ctx, n, chunk, g);
-    if (launch_xcorr(n, g, s, mark)) return fail(ctx, CCPT_E_HIP, "correlation launch failed");
+    const size_t yb = split_partials_bytes(ctx, n, g.count);
+    g.ypart = (yb && yb <= ctx->ypart_cap) ? (float*)ctx->ypart : nullptr;
+    if ((fp64(ctx) ? launch_xcorr64(n, g, s, mark) : launch_xcorr(n, g, s, mark)))
+      return fail(ctx, CCPT_E_HIP, "correlation launch failed");
     mark(CCPT_STAGE_UPDFT, 1);
-    if (launch_updft(n, g, ut, s)) return fail(ctx, CCPT_E_HIP, "upsampled DFT launch failed");
+    if ((fp64(ctx) ? launch_updft64(n, g, t.ky64, t.wb64, t.Mp, s) : launch_updft(n, g, ut, s)))
+      return fail(ctx, CCPT_E_HIP, "upsampled DFT launch failed");
     mark(CCPT_STAGE_UPDFT, 0);
     mark(CCPT_STAGE_NEWTON, 1);
     if (launch_newton(n, g, step_limit(ctx), s))
@@ -302,7 +374,9 @@ struct Plan {
   std::vector<int> sig;         // (size, count) pairs of the groups
 };
 
-int plan_rois(ccpt_ctx* ctx, const ccpt_roi* rois, int n, Plan& plan) {
+// fp32_spec: point the descriptors at the FP32 reference spectra whatever
+// the precision (the adjoint works in FP32).
+int plan_rois(ccpt_ctx* ctx, const ccpt_roi* rois, int n, Plan& plan, bool fp32_spec = false) {
   if (ctx->refs.empty()) return fail(ctx, CCPT_E_NOREF, "no reference set");
   for (int i = 0; i < n; ++i) {
     const ccpt_roi& r = rois[i];
@@ -325,7 +399,8 @@ int plan_rois(ccpt_ctx* ctx, const ccpt_roi* rois, int n, Plan& plan) {
     const ccpt_roi& r = rois[order[k]];
     FrameDesc d;
     d.data = r.data;
-    d.rspec = ctx->refs[r.ref_id].spec;
+    const Ref& ref = ctx->refs[r.ref_id];
+    d.rspec = (fp64(ctx) && !fp32_spec) ? (const void*)ref.spec64 : (const void*)ref.spec;
     d.pitch = r.pitch;
     d.dtype = r.dtype;
     d.out_idx = order[k];
@@ -441,7 +516,9 @@ int ccpt_create(ccpt_ctx** out, int device, const ccpt_options* opts) {
   if (o.mode != CCPT_MODE_CCU && o.mode != CCPT_MODE_CCSN) return CCPT_E_INVALID;
   if (o.upsample < 1 || o.upsample > 1024) return CCPT_E_INVALID;
   if (!(o.window > 0.0 && o.window <= 2.0)) return CCPT_E_INVALID;
-  if (o.precision != CCPT_PREC_FP32 && o.precision != CCPT_PREC_BF16X2) return CCPT_E_INVALID;
+  if (o.precision != CCPT_PREC_FP32 && o.precision != CCPT_PREC_BF16X2 &&
+      o.precision != CCPT_PREC_FP64)
+    return CCPT_E_INVALID;
   if (o.newton_iters < 0 || o.newton_iters > 8) return CCPT_E_INVALID;
   if (!std::isfinite(o.eps)) return CCPT_E_INVALID;
   const int M = (int)std::ceil(o.window * o.upsample - 1e-9);
@@ -478,9 +555,14 @@ void ccpt_destroy(ccpt_ctx* ctx) {
     (void)hipFree(kv.second.tw);
     (void)hipFree(kv.second.ky);
     (void)hipFree(kv.second.wb);
+    if (kv.second.kfold) (void)hipFree(kv.second.kfold);
+    if (kv.second.tw64) (void)hipFree(kv.second.tw64);
+    if (kv.second.ky64) (void)hipFree(kv.second.ky64);
+    if (kv.second.wb64) (void)hipFree(kv.second.wb64);
   }
   for (auto& r : ctx->refs) {
     (void)hipFree(r.spec);
+    if (r.spec64) (void)hipFree(r.spec64);
     (void)hipFree(r.img);
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
@@ -490,6 +572,7 @@ void ccpt_destroy(ccpt_ctx* ctx) {
   if (ctx->small_evt) (void)hipEventDestroy(ctx->small_evt);
   if (ctx->gsmall) (void)hipFree(ctx->gsmall);
   if (ctx->acc_buf) (void)hipFree(ctx->acc_buf);
+  if (ctx->ypart) (void)hipFree(ctx->ypart);
   if (ctx->h_small) (void)hipHostFree(ctx->h_small);
   delete ctx;
 }
@@ -507,18 +590,15 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
   }
   HIP_CHECK(ctx, hipStreamSynchronize(s));
   // read the references back: the CC-SN domain check and the context's own copy
-  std::vector<std::vector<float>> host(n_refs);
+  std::vector<std::vector<double>> host(n_refs);
   for (int i = 0; i < n_refs; ++i) {
     const ccpt_image& im = refs[i];
-    const size_t esz = im.dtype == CCPT_U16 ? 2 : 4;
-    std::vector<char> raw((size_t)im.ny * im.pitch * esz);
+    std::vector<char> raw(((size_t)(im.ny - 1) * im.pitch + im.nx) * dtype_bytes(im.dtype));
     HIP_CHECK(ctx, hipMemcpy(raw.data(), im.data, raw.size(), hipMemcpyDeviceToHost));
     host[i].resize((size_t)im.ny * im.nx);
     for (int y = 0; y < im.ny; ++y)
       for (int x = 0; x < im.nx; ++x) {
-        const size_t k = (size_t)y * im.pitch + x;
-        float v = im.dtype == CCPT_U16 ? (float)((const uint16_t*)raw.data())[k]
-                                       : ((const float*)raw.data())[k];
+        const double v = pixel(raw.data(), im.dtype, (size_t)y * im.pitch + x);
         if (!std::isfinite(v))
           return fail(ctx, CCPT_E_INVALID, "reference %d has a non-finite pixel", i);
         if (ctx->o.mode == CCPT_MODE_CCSN && !(v + ctx->o.eps > 0.0))
@@ -531,40 +611,60 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
   HIP_CHECK(ctx, hipDeviceSynchronize());
   for (auto& r : ctx->refs) {
     (void)hipFree(r.spec);
+    if (r.spec64) (void)hipFree(r.spec64);
     (void)hipFree(r.img);
   }
   ctx->refs.clear();
   ctx->last_desc.clear();
+  // scratch: one spectrum (FP64 size) plus the FP64 image of the FP64 mode
   size_t tmp_need = 0;
   for (int i = 0; i < n_refs; ++i) {
     const int n = refs[i].nx;
-    tmp_need = std::max(tmp_need, (size_t)n * (n / 2 + 1) * sizeof(float2));
+    tmp_need = std::max(tmp_need, spec_elems(n) * sizeof(double2) + (size_t)n * n * sizeof(double));
     rc = ensure_tables(ctx, n);
     if (rc) return rc;
   }
-  float2* T = nullptr;
-  HIP_CHECK(ctx, hipMalloc(&T, tmp_need));
+  char* tmp = nullptr;
+  HIP_CHECK(ctx, hipMalloc(&tmp, tmp_need));
+  float2* T = (float2*)tmp;
   for (int i = 0; i < n_refs; ++i) {
     const int n = refs[i].nx;
     Ref r;
     r.n = n;
-    if (hipMalloc(&r.spec, (size_t)n * (n / 2 + 1) * sizeof(float2)) != hipSuccess ||
-        hipMalloc(&r.img, (size_t)n * n * sizeof(float)) != hipSuccess) {
-      (void)hipFree(T);
+    if (hipMalloc(&r.spec, spec_elems(n) * sizeof(float2)) != hipSuccess ||
+        hipMalloc(&r.img, (size_t)n * n * sizeof(float)) != hipSuccess ||
+        (fp64(ctx) && hipMalloc(&r.spec64, spec_elems(n) * sizeof(double2)) != hipSuccess)) {
+      (void)hipFree(tmp);
+      if (r.spec) (void)hipFree(r.spec);
+      if (r.img) (void)hipFree(r.img);
       return fail(ctx, CCPT_E_NOMEM, "reference spectra");
     }
-    HIP_CHECK(ctx, hipMemcpy(r.img, host[i].data(), (size_t)n * n * sizeof(float),
+    ctx->refs.push_back(r);
+    std::vector<float> img32(host[i].begin(), host[i].end());
+    HIP_CHECK(ctx, hipMemcpy(r.img, img32.data(), (size_t)n * n * sizeof(float),
                              hipMemcpyHostToDevice));
     const int weight = ctx->o.mode == CCPT_MODE_CCSN ? 1 : 0;
     if (launch_spectrum(n, r.img, CCPT_F32, n, 0, 1, weight, (float)ctx->o.eps, 1, T, r.spec,
                         ctx->tables[n].tw, s)) {
-      (void)hipFree(T);
+      (void)hipFree(tmp);
       return fail(ctx, CCPT_E_HIP, "reference spectrum launch failed");
     }
-    ctx->refs.push_back(r);
+    if (fp64(ctx)) {
+      // the FP64 spectrum from the reference's own values, not their FP32 copy
+      double2* T64 = (double2*)tmp;
+      double* img64 = (double*)(T64 + spec_elems(n));
+      HIP_CHECK(ctx, hipStreamSynchronize(s));
+      HIP_CHECK(ctx, hipMemcpy(img64, host[i].data(), (size_t)n * n * sizeof(double),
+                               hipMemcpyHostToDevice));
+      if (launch_spectrum64(n, img64, CCPT_F64, n, 0, 1, weight, ctx->o.eps, 1, T64, r.spec64,
+                            ctx->tables[n].tw64, s)) {
+        (void)hipFree(tmp);
+        return fail(ctx, CCPT_E_HIP, "reference spectrum launch failed");
+      }
+    }
+    HIP_CHECK(ctx, hipStreamSynchronize(s));
   }
-  HIP_CHECK(ctx, hipStreamSynchronize(s));
-  HIP_CHECK(ctx, hipFree(T));
+  HIP_CHECK(ctx, hipFree(tmp));
   return CCPT_OK;
 }
 
@@ -588,6 +688,18 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
   }
   rc = ensure_ws(ctx, ws_need);
   if (rc) return rc;
+  size_t ypart_need = 0;
+  for (size_t gi = 0; gi < sig.size(); gi += 2) {
+    const int nn = sig[gi], cnt = sig[gi + 1];
+    const int ch = std::min(cnt, chunk_for(ctx, nn));
+    ypart_need = std::max(ypart_need, split_partials_bytes(ctx, nn, ch));
+    ypart_need = std::max(ypart_need, split_partials_bytes(ctx, nn, cnt % ch));
+  }
+  if (ypart_need > ctx->ypart_cap) {
+    drop_graphs(ctx);
+    rc = ensure_buf(ctx, ctx->ypart, ctx->ypart_cap, ypart_need);
+    if (rc) return rc;
+  }
   rc = upload_desc(ctx, plan.desc, s);
   if (rc) return rc;
 
@@ -635,7 +747,7 @@ int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_resul
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   Plan plan;
-  rc = plan_rois(ctx, rois, n, plan);
+  rc = plan_rois(ctx, rois, n, plan, true);
   if (rc) return rc;
   const int nrefs = (int)ctx->refs.size();
   // packed offsets of the frame gradients (roi order) and of the reference gradients
@@ -754,15 +866,12 @@ int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* strea
   const int n = mu->nx;
   HIP_CHECK(ctx, hipStreamSynchronize(s));
   {
-    const size_t esz = mu->dtype == CCPT_U16 ? 2 : 4;
-    std::vector<char> raw((size_t)mu->ny * mu->pitch * esz);
+    std::vector<char> raw(((size_t)(mu->ny - 1) * mu->pitch + mu->nx) * dtype_bytes(mu->dtype));
     HIP_CHECK(ctx, hipMemcpy(raw.data(), mu->data, raw.size(), hipMemcpyDeviceToHost));
     for (int y = 0; y < n; ++y)
       for (int x = 0; x < n; ++x) {
-        const size_t k = (size_t)y * mu->pitch + x;
-        const float v = mu->dtype == CCPT_U16 ? (float)((const uint16_t*)raw.data())[k]
-                                              : ((const float*)raw.data())[k];
-        if (!(v > 0.f) || !std::isfinite(v))
+        const double v = pixel(raw.data(), mu->dtype, (size_t)y * mu->pitch + x);
+        if (!(v > 0.0) || !std::isfinite(v))
           return fail(ctx, CCPT_E_INVALID, "mean image must be > 0 and finite (%d, %d)", y, x);
       }
   }
@@ -818,8 +927,69 @@ int ccpt_stage_times(ccpt_ctx* ctx, double* ms, int* launches, int n_stages, int
   return CCPT_OK;
 }
 
-int ccpt_autotune(ccpt_ctx* ctx, int, int, void*) {
+int ccpt_autotune(ccpt_ctx* ctx, int n, int batch, void* stream) {
   if (!ctx) return CCPT_E_INVALID;
+  if (batch < 1 || !supported_size(n)) return fail(ctx, CCPT_E_INVALID, "bad tuning shape");
+  int rid = -1;
+  for (int r = 0; r < (int)ctx->refs.size(); ++r)
+    if (ctx->refs[r].n == n) {
+      rid = r;
+      break;
+    }
+  if (rid < 0) return fail(ctx, CCPT_E_NOREF, "no reference of size %d to tune with", n);
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  // every tuning frame is the reference image itself (timing does not depend on content)
+  std::vector<ccpt_roi> rois(batch);
+  for (auto& r : rois) r = ccpt_roi{ctx->refs[rid].img, n, n, n, CCPT_F32, rid};
+  ccpt_result* out = nullptr;
+  HIP_CHECK(ctx, hipMalloc(&out, (size_t)batch * sizeof(ccpt_result)));
+  hipEvent_t e0, e1;
+  HIP_CHECK(ctx, hipEventCreate(&e0));
+  HIP_CHECK(ctx, hipEventCreate(&e1));
+  const int saved_flags = ctx->o.flags;
+  ctx->o.flags = 0;  // no graphs or profiling while tuning
+  const int cands[] = {16, 32, 64, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 4096};
+  int best_chunk = default_chunk(n, ctx->o.precision);
+  float best_ms = 1e30f;
+  for (int c : cands) {
+    if (c > batch && c != cands[0]) break;
+    const size_t need = frame_ws_bytes(n, ctx->o.precision) * (size_t)std::min(c, batch) + 256;
+    if (need > ((size_t)8 << 30)) break;
+    ctx->sched[n].chunk = c;
+    float total = 0.f;
+    int good = 1;
+    for (int rep = 0; rep < 4 && good; ++rep) {
+      if (rep == 1) (void)hipEventRecord(e0, s);
+      if (ccpt_track_batch(ctx, rois.data(), batch, out, stream) != CCPT_OK) good = 0;
+    }
+    (void)hipEventRecord(e1, s);
+    if (!good || hipEventSynchronize(e1) != hipSuccess) continue;
+    (void)hipEventElapsedTime(&total, e0, e1);
+    if (total < best_ms) {
+      best_ms = total;
+      best_chunk = c;
+    }
+  }
+  ctx->sched[n].chunk = best_chunk;
+  ctx->o.flags = saved_flags;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  ctx->last_desc.clear();
+  return CCPT_OK;
+}
+
+int ccpt_schedule(ccpt_ctx* ctx, int n, int* chunk, int set) {
+  if (!ctx || !chunk) return CCPT_E_INVALID;
+  if (!supported_size(n)) return fail(ctx, CCPT_E_UNSUPPORTED, "size %d", n);
+  if (set) {
+    if (*chunk < 0 || *chunk > (1 << 20)) return fail(ctx, CCPT_E_INVALID, "chunk %d", *chunk);
+    ctx->sched[n].chunk = *chunk;
+  } else {
+    *chunk = chunk_for(ctx, n);
+  }
   return CCPT_OK;
 }
 

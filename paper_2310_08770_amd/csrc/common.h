@@ -11,12 +11,13 @@ namespace ccpt {
 
 // Device-side descriptor of one frame of a launch group (32 bytes).
 struct FrameDesc {
-  const void* data;     // frame pixels (device)
-  const float2* rspec;  // conj F[B] of its reference, N x (N/2+1), row-major
-  int pitch;            // elements between row starts
-  int dtype;            // CCPT_U16 / CCPT_F32
-  int out_idx;          // index into the caller's result array
-  int ref_id;           // reference index
+  const void* data;   // frame pixels (device)
+  const void* rspec;  // conj F[B] of its reference, N x (N/2+1), row-major:
+                      // float2, or double2 in FP64 mode
+  int pitch;          // elements between row starts
+  int dtype;          // ccpt_dtype
+  int out_idx;        // index into the caller's result array
+  int ref_id;         // reference index
 };
 
 // Per-frame scratch kept in the workspace between the kernels of one chunk.
@@ -25,6 +26,15 @@ struct FrameState {
   unsigned long long grid_key;  // upsampled-grid maximum, same encoding
   unsigned amin, amax;          // order-preserving keys of min/max of A
   unsigned flags;               // CCPT_ST_NONFINITE
+  unsigned pad;
+};
+
+// FP64 mode: best correlation value of one row block of a frame and its
+// row-major index (ties to the lower index); reduced per frame before the
+// upsampled DFT, since an FP64 value and an index do not fit one 64-bit key.
+struct PeakCand {
+  double v;
+  unsigned idx;
   unsigned pad;
 };
 
@@ -48,10 +58,39 @@ struct GroupParams {
   int c;                  // grid centre index
   int newton_iters;
   double half_window;     // Newton results farther than this from p fall back
+  float* ypart;           // FP32 split-K partials for small launches, or null:
+                          // [count][Mp/32][slices][32][N rounded up to 32]
+  // FP64 mode (all null otherwise): T and X in double2, the per-row-block
+  // peak candidates [count][N / row_block64(N)], twiddles in FP64
+  double eps64;           // CC-SN offset (FP64 mode)
+  double2* T64;
+  double2* X64;
+  PeakCand* cand;
+  const double2* tw64;
 };
+
+// Small FP32 launches (fewer than kSplitMaxBlocks row tiles in all) split the
+// Stage A contraction over kSplitSlices ky slices for latency.
+constexpr int kSplitMaxBlocks = 128;
+constexpr int kSplitSlices = 8;
 
 // Row length (in words) of the split-precision spectrum rows: N rounded up to 32.
 __host__ __device__ constexpr int xb_pitch(int n) { return (n + 31) / 32 * 32; }
+
+// Rows per block of the FP64 row passes: 8 rows when they fit, else the
+// largest divisor of N whose rows hold at most 1024 complex values.
+__host__ __device__ constexpr int row_block64(int N) {
+  if (N % 8 == 0 && 8 * (N / 2 + 1) <= 2100) return 8;
+  int best = 1;
+  for (int r = 1; r <= N; ++r)
+    if (N % r == 0 && r * (N / 2) <= 1024) best = r;
+  return best;
+}
+
+// Bytes per pixel of a ccpt_dtype.
+__host__ __device__ constexpr int dtype_bytes(int dtype) {
+  return dtype == CCPT_U16 ? 2 : dtype == CCPT_F64 ? 8 : 4;
+}
 
 // Order-preserving map float -> uint32 (a < b  <=>  key(a) < key(b)).
 __host__ __device__ inline unsigned f2key(float v) {
@@ -91,16 +130,36 @@ int launch_spectrum(int N, const void* data, int dtype, int pitch, long img_stri
                     int weight, float eps, int conj_out, float2* T, float2* spec,
                     const float2* tw, hipStream_t s);
 
+// FP64 mode: the same two calls with every FFT in FP64 (g.T64, g.X64,
+// g.cand; the integer peak is left as per-row-block candidates).
+int launch_xcorr64(int N, const GroupParams& g, hipStream_t s, const Marker& mark);
+int launch_spectrum64(int N, const void* data, int dtype, int pitch, long img_stride, int n,
+                      int weight, double eps, int conj_out, double2* T, double2* spec,
+                      const double2* tw, hipStream_t s);
+
 // Stage 4: upsampled matrix DFT around the integer peak and its maximum.
 struct UpdftTables {
   const void* ky;    // Stage A operand table (layout depends on precision)
   const void* wb;    // Stage B operand table
   int Mp;            // padded grid size (multiple of 32)
   int precision;
+  const void* kfold; // split precision, N >= 256: folded K' table for every peak row
 };
+
+// Minimum frame size of the wide split-precision kernel (and its folded table).
+constexpr int kWideMinN = 256;
+
+// Builds the folded split table [N][2][Mp][xb_pitch(N)] words on the device.
+int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int Mp, hipStream_t s);
 int launch_updft(int N, const GroupParams& g, const UpdftTables& t, hipStream_t s);
 
-// Stage 5: FP64 Newton refinement and the result record.
+// FP64 mode: reduces the peak candidates, then the upsampled DFT in FP64 on
+// the vector units; K [Mp][N] and W [N/2+1][Mp] are complex FP64 tables.
+int launch_updft64(int N, const GroupParams& g, const double2* K, const double2* W, int Mp,
+                   hipStream_t s);
+
+// Stage 5: FP64 Newton refinement and the result record (from g.X64 when
+// set, else from g.X).
 int launch_newton(int N, const GroupParams& g, double step_limit, hipStream_t s);
 
 // Inverse 2-D c2r of n half spectra [n][N][N/2+1] into n N x N float images

@@ -10,17 +10,47 @@
 
 namespace ccpt {
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// Complex arithmetic on float2 (FP32 path) and double2 (FP64 path).
+template <typename C>
+struct cplx;
+template <>
+struct cplx<float2> {
+  using real = float;
+  static constexpr float sin60 = 0.86602540378443864676f;
+  static constexpr float sqrt_half = 0.70710678118654752440f;
+};
+template <>
+struct cplx<double2> {
+  using real = double;
+  static constexpr double sin60 = 0.86602540378443864676;
+  static constexpr double sqrt_half = 0.70710678118654752440;
+};
+template <typename C>
+using real_t = typename cplx<C>::real;
+
+template <typename C>
+__device__ __forceinline__ C mkc(real_t<C> x, real_t<C> y) {
+  if constexpr (sizeof(C) == sizeof(float2))
+    return make_float2(x, y);
+  else
+    return make_double2(x, y);
 }
-__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { return mkc<C>(a.x + b.x, a.y + b.y); }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { return mkc<C>(a.x - b.x, a.y - b.y); }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  return mkc<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename C>
+__device__ __forceinline__ C cconj(C a) { return mkc<C>(a.x, -a.y); }
+template <typename C>
+__device__ __forceinline__ C cscale(C a, real_t<C> s) { return mkc<C>(a.x * s, a.y * s); }
 // multiply by i * SIGN
-template <int SIGN>
-__device__ __forceinline__ float2 mul_i(float2 a) {
-  return SIGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+template <int SIGN, typename C>
+__device__ __forceinline__ C mul_i(C a) {
+  return SIGN > 0 ? mkc<C>(-a.y, a.x) : mkc<C>(a.y, -a.x);
 }
 
 // bf16 (round to nearest even) of a float, as the high 16 bits of its pattern
@@ -72,42 +102,43 @@ constexpr int fft_stages(int L) {
 }
 
 // In-register DFT of size R with exponent sign SIGN (-1 forward, +1 inverse).
-template <int R, int SIGN>
-__device__ __forceinline__ void dft(float2* v) {
+template <int R, int SIGN, typename C>
+__device__ __forceinline__ void dft(C* v) {
+  using Rt = real_t<C>;
   if constexpr (R == 2) {
-    float2 a = v[0], b = v[1];
+    C a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
   } else if constexpr (R == 3) {
-    const float c = -0.5f;
-    const float s = SIGN * 0.86602540378443864676f;
-    float2 a = v[0], b = v[1], d = v[2];
-    float2 t = cadd(b, d);
-    float2 u = csub(b, d);
+    const Rt c = Rt(-0.5);
+    const Rt s = SIGN * cplx<C>::sin60;
+    C a = v[0], b = v[1], d = v[2];
+    C t = cadd(b, d);
+    C u = csub(b, d);
     v[0] = cadd(a, t);
-    float2 m = make_float2(a.x + c * t.x, a.y + c * t.y);
+    C m = mkc<C>(a.x + c * t.x, a.y + c * t.y);
     // i * s * u
-    float2 r = make_float2(-s * u.y, s * u.x);
+    C r = mkc<C>(-s * u.y, s * u.x);
     v[1] = cadd(m, r);
     v[2] = csub(m, r);
   } else if constexpr (R == 4) {
-    float2 a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
-    float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
-    float2 s13 = cadd(a1, a3), d13 = mul_i<SIGN>(csub(a1, a3));
+    C a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    C s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    C s13 = cadd(a1, a3), d13 = mul_i<SIGN>(csub(a1, a3));
     v[0] = cadd(s02, s13);
     v[2] = csub(s02, s13);
     v[1] = cadd(d02, d13);
     v[3] = csub(d02, d13);
   } else if constexpr (R == 8) {
-    float2 e[4] = {v[0], v[2], v[4], v[6]};
-    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
     dft<4, SIGN>(e);
     dft<4, SIGN>(o);
-    const float h = 0.70710678118654752440f;
+    const Rt h = cplx<C>::sqrt_half;
     // w8^k = exp(SIGN * 2 pi i k / 8)
-    float2 o1 = make_float2(h * (o[1].x - SIGN * o[1].y), h * (o[1].y + SIGN * o[1].x));
-    float2 o2 = mul_i<SIGN>(o[2]);
-    float2 o3 = make_float2(h * (-o[3].x - SIGN * o[3].y), h * (-o[3].y + SIGN * o[3].x));
+    C o1 = mkc<C>(h * (o[1].x - SIGN * o[1].y), h * (o[1].y + SIGN * o[1].x));
+    C o2 = mul_i<SIGN>(o[2]);
+    C o3 = mkc<C>(h * (-o[3].x - SIGN * o[3].y), h * (-o[3].y + SIGN * o[3].x));
     v[0] = cadd(e[0], o[0]);
     v[4] = csub(e[0], o[0]);
     v[1] = cadd(e[1], o1);
@@ -122,18 +153,18 @@ __device__ __forceinline__ void dft(float2* v) {
 // One Stockham stage of radix R on `nseq` sequences of length L (sequence
 // q at src/dst + q*stride).  NS = product of the radices already applied.
 // tw: exp(-2 pi i m / NTW), m < NTW, with L | NTW.
-template <int L, int R, int SIGN, int NTW>
-__device__ __forceinline__ void fft_stage(const float2* __restrict__ src, float2* __restrict__ dst,
-                                          int nseq, int stride, int NS, const float2* tw,
+template <int L, int R, int SIGN, int NTW, typename C>
+__device__ __forceinline__ void fft_stage(const C* __restrict__ src, C* __restrict__ dst,
+                                          int nseq, int stride, int NS, const C* tw,
                                           int tid, int nthr) {
   constexpr int B = L / R;
   const int total = nseq * B;
   for (int b = tid; b < total; b += nthr) {
     const int q = b / B;
     const int j = b - q * B;
-    const float2* in = src + q * stride;
-    float2* out = dst + q * stride;
-    float2 v[R];
+    const C* in = src + q * stride;
+    C* out = dst + q * stride;
+    C v[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) v[t] = in[j + t * B];
     const int k = j % NS;
@@ -142,7 +173,7 @@ __device__ __forceinline__ void fft_stage(const float2* __restrict__ src, float2
       const int step = NTW / (NS * R);
 #pragma unroll
       for (int t = 1; t < R; ++t) {
-        float2 w = tw[t * k * step];
+        C w = tw[t * k * step];
         if (SIGN > 0) w.y = -w.y;
         v[t] = cmul(v[t], w);
       }
@@ -154,9 +185,9 @@ __device__ __forceinline__ void fft_stage(const float2* __restrict__ src, float2
   }
 }
 
-template <int L, int SIGN, int NTW, int ST>
-__device__ __forceinline__ float2* fft_run(float2* a, float2* b, int nseq, int stride, int NS,
-                                           const float2* tw, int tid, int nthr) {
+template <int L, int SIGN, int NTW, int ST, typename C>
+__device__ __forceinline__ C* fft_run(C* a, C* b, int nseq, int stride, int NS, const C* tw,
+                                      int tid, int nthr) {
   if constexpr (ST == fft_stages(L)) {
     return a;
   } else {
@@ -169,9 +200,8 @@ __device__ __forceinline__ float2* fft_run(float2* a, float2* b, int nseq, int s
 
 // Transforms nseq sequences in `a` (b is scratch of the same size); returns
 // the buffer holding the result.  Callers must __syncthreads() before.
-template <int L, int SIGN, int NTW>
-__device__ __forceinline__ float2* fft_lds(float2* a, float2* b, int nseq, int stride,
-                                           const float2* tw) {
+template <int L, int SIGN, int NTW, typename C>
+__device__ __forceinline__ C* fft_lds(C* a, C* b, int nseq, int stride, const C* tw) {
   return fft_run<L, SIGN, NTW, 0>(a, b, nseq, stride, 1, tw, threadIdx.x, blockDim.x);
 }
 

@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(kGThreads) k_grad_psi(const FrameDesc* __restr
   __syncthreads();
   const double inv = 1.0 / ((double)N * (double)N);
   const size_t base = (size_t)f * N * H;
-  const float2* R = d.rspec;
+  const float2* R = (const float2*)d.rspec;
   for (int i = tid; i < rows * H; i += kGThreads) {
     const int ky = y0 + i / H, kx = i % H;
     const size_t e = (size_t)ky * H + kx;
@@ -127,8 +127,9 @@ __global__ void k_grad_frames(const FrameDesc* __restrict__ desc, int first,
     if (mode == CCPT_MODE_CCSN) {
       const int y = i / N, x = i - y * N;
       const long idx = (long)y * d.pitch + x;
-      const float px = d.dtype == CCPT_U16 ? (float)((const unsigned short*)d.data)[idx]
-                                           : ((const float*)d.data)[idx];
+      const float px = d.dtype == CCPT_U16   ? (float)((const unsigned short*)d.data)[idx]
+                       : d.dtype == CCPT_F64 ? (float)((const double*)d.data)[idx]
+                                             : ((const float*)d.data)[idx];
       v *= 2.0f * (px + eps);
     }
     out[i] = v;
@@ -205,8 +206,9 @@ __global__ void k_fisher_partial(const float* __restrict__ dy, const float* __re
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * n; i += gridDim.x * blockDim.x) {
     const int y = i / n, x = i - y * n;
     const long idx = (long)y * pitch + x;
-    const double m = dtype == CCPT_U16 ? (double)((const unsigned short*)mu)[idx]
-                                       : (double)((const float*)mu)[idx];
+    const double m = dtype == CCPT_U16   ? (double)((const unsigned short*)mu)[idx]
+                     : dtype == CCPT_F64 ? ((const double*)mu)[idx]
+                                         : (double)((const float*)mu)[idx];
     const double p = dy[i], q = dx[i];
     a += p * p / m;
     b += p * q / m;

@@ -20,6 +20,7 @@
 // FP64 rounding for |e| <= 0.02 px with K = 7.  One streaming pass over the
 // FP32 spectrum (FP64 arithmetic) therefore gives C, its gradient and Hessian
 // anywhere near the seed, and the Newton iterations run on the polynomial.
+// (In the FP64 mode the spectrum itself is FP64.)
 // If an iterate moves farther than the model radius from the centre, the
 // model is rebuilt around it (at most three passes).
 //
@@ -35,7 +36,7 @@
 
 namespace ccpt {
 
-constexpr int kNThreads = 256;
+constexpr int kNThreads = 512;
 constexpr int kOrder = 7;                               // K
 constexpr int kCoef = (kOrder + 1) * (kOrder + 2) / 2;  // pairs with n + m <= K
 constexpr double kModelRadius = 0.02;                   // px
@@ -75,19 +76,6 @@ __device__ Deriv model_eval(const double* coef, double ey, double ex) {
   return d;
 }
 
-// acc[n, m] += w Re[P_m M_n] with P_m = phx (i b)^m (real part only if nyq_x).
-__device__ __forceinline__ void add_terms(double* acc, const double2* M, double2 phx, double b,
-                                          bool nyq_x, double w) {
-  double2 P = phx;
-#pragma unroll
-  for (int m = 0; m <= kOrder; ++m) {
-    const double pr = P.x, pim = nyq_x ? 0.0 : P.y;
-#pragma unroll
-    for (int n = 0; n + m <= kOrder; ++n) acc[coef_index(n, m)] += w * (pr * M[n].x - pim * M[n].y);
-    P = make_double2(-b * P.y, b * P.x);
-  }
-}
-
 // Accumulates t (i a)^n into M[n], n = 0..K.
 __device__ __forceinline__ void add_powers(double2* M, double2 t, double a) {
 #pragma unroll
@@ -98,16 +86,35 @@ __device__ __forceinline__ void add_powers(double2* M, double2 t, double a) {
   }
 }
 
-// One pass: the model coefficients around (sy, sx) into coef (LDS).
+constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (2 * p <= x) p *= 2;
+  return p;
+}
+
+// Work split of one model pass: each column kx < N/2 is shared by S adjacent
+// lanes (ky segments of length SEG); after their moments are combined, lane
+// `seg` accumulates the coefficients with m = seg, seg + S, ... (QM of them).
 template <int N>
-__device__ void build_model(const float2* __restrict__ Xf, double sy, double sx, double2* phy,
-                            double* ay, double (*red)[kNThreads / 64], double* coef) {
+struct ModelSplit {
+  static constexpr int NC = N / 2;
+  static constexpr int S0 = kNThreads / NC;
+  static constexpr int S = pow2_floor(S0 < 64 ? (S0 < N ? S0 : N) : 64);
+  static constexpr int SEG = (N + S - 1) / S;
+  static constexpr int QM = (kOrder + S) / S;
+};
+
+// One pass: the model coefficients around (sy, sx) into coef (LDS).  CX is
+// the spectrum's element type (float2, or double2 in FP64 mode).
+template <int N, typename CX>
+__device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, double2* phy,
+                            double* ay, double (*red)[kOrder + 1][kOrder + 1],
+                            double (*nred)[2 * (kOrder + 1)], double* coef) {
+  using MS = ModelSplit<N>;
   constexpr int H = N / 2 + 1;
-  constexpr int NC = N / 2;
-  constexpr int S = NC >= kNThreads ? 1 : kNThreads / NC;  // ky segments per column
-  constexpr int SEG = (N + S - 1) / S;
+  constexpr int NC = MS::NC, S = MS::S, SEG = MS::SEG, QM = MS::QM;
   const double pi = 3.14159265358979323846;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int ky = tid; ky < N; ky += kNThreads) {
     if (2 * ky == N) {
       phy[ky] = make_double2(0.0, 0.0);  // the Nyquist row is added separately
@@ -121,9 +128,6 @@ __device__ void build_model(const float2* __restrict__ Xf, double sy, double sx,
     }
   }
   __syncthreads();
-  double acc[kCoef];
-#pragma unroll
-  for (int q = 0; q < kCoef; ++q) acc[q] = 0.0;
   // Nyquist row: Re[exp(i pi sy) (i pi)^n]
   double ry[kOrder + 1];
   {
@@ -136,72 +140,131 @@ __device__ void build_model(const float2* __restrict__ Xf, double sy, double sx,
       t = make_double2(-pi * t.y, pi * t.x);
     }
   }
-  // columns kx < N/2, split into S ky segments
-  for (int item = tid; item < NC * S; item += kNThreads) {
-    const int kx = item / S, seg = item - kx * S;
-    const int y0 = seg * SEG, y1 = min(N, y0 + SEG);
-    double2 M[kOrder + 1];
+  // ---- moments of column kx over this lane's ky segment
+  const int kx = tid / S, seg = tid % S;
+  double2 M[kOrder + 1];
 #pragma unroll
-    for (int n = 0; n <= kOrder; ++n) M[n] = make_double2(0.0, 0.0);
-    const float2* col = Xf + kx;
+  for (int n = 0; n <= kOrder; ++n) M[n] = make_double2(0.0, 0.0);
+  if (kx < NC) {
+    const int y0 = seg * SEG, y1 = min(N, y0 + SEG);
+    const CX* col = Xf + kx;
+#pragma unroll 4
     for (int ky = y0; ky < y1; ++ky) {
-      const float2 xf = col[(size_t)ky * H];
+      const CX xf = col[(size_t)ky * H];
       const double2 ph = phy[ky];
-      const double2 t = make_double2((double)xf.x * ph.x - (double)xf.y * ph.y,
-                                     (double)xf.x * ph.y + (double)xf.y * ph.x);
-      add_powers(M, t, ay[ky]);
+      add_powers(M, make_double2((double)xf.x * ph.x - (double)xf.y * ph.y,
+                                 (double)xf.x * ph.y + (double)xf.y * ph.x),
+                 ay[ky]);
     }
     if (y0 <= N / 2 && N / 2 < y1) {
-      const float2 xf = col[(size_t)(N / 2) * H];
+      const CX xf = col[(size_t)(N / 2) * H];
 #pragma unroll
       for (int n = 0; n <= kOrder; ++n) {
         M[n].x += (double)xf.x * ry[n];
         M[n].y += (double)xf.y * ry[n];
       }
     }
+  }
+#pragma unroll
+  for (int off = 1; off < S; off <<= 1)
+#pragma unroll
+    for (int n = 0; n <= kOrder; ++n) {
+      M[n].x += __shfl_xor(M[n].x, off, 64);
+      M[n].y += __shfl_xor(M[n].y, off, 64);
+    }
+  // ---- this lane's share of the coefficients: m = seg + S q
+  double acc[QM][kOrder + 1];
+#pragma unroll
+  for (int q = 0; q < QM; ++q)
+#pragma unroll
+    for (int n = 0; n <= kOrder; ++n) acc[q][n] = 0.0;
+  if (kx < NC) {
+    const double b = 2.0 * pi * (double)kx / (double)N;
+    const double w = kx == 0 ? 1.0 : 2.0;
     double sn, cs;
     sincospi(2.0 * (double)kx * sx / (double)N, &sn, &cs);
-    add_terms(acc, M, make_double2(cs, sn), 2.0 * pi * (double)kx / (double)N, false,
-              kx == 0 ? 1.0 : 2.0);
-  }
-  // Nyquist column kx = N/2: every thread takes a few rows
-  {
-    double2 M[kOrder + 1];
+    double2 P = make_double2(cs, sn);
+    for (int k = 0; k < seg && k <= kOrder; ++k) P = make_double2(-b * P.y, b * P.x);
 #pragma unroll
-    for (int n = 0; n <= kOrder; ++n) M[n] = make_double2(0.0, 0.0);
-    for (int ky = tid; ky < N; ky += kNThreads) {
-      const float2 xf = Xf[(size_t)ky * H + NC];
-      if (2 * ky == N) {
+    for (int q = 0; q < QM; ++q) {
+      const int m = seg + S * q;
+      if (m <= kOrder) {
 #pragma unroll
-        for (int n = 0; n <= kOrder; ++n) {
-          M[n].x += (double)xf.x * ry[n];
-          M[n].y += (double)xf.y * ry[n];
-        }
-      } else {
-        const double2 ph = phy[ky];
-        add_powers(M, make_double2((double)xf.x * ph.x - (double)xf.y * ph.y,
-                                   (double)xf.x * ph.y + (double)xf.y * ph.x),
-                   ay[ky]);
+        for (int n = 0; n <= kOrder; ++n)
+          if (n + m <= kOrder) acc[q][n] += w * (P.x * M[n].x - P.y * M[n].y);
       }
+#pragma unroll
+      for (int k = 0; k < S && k <= kOrder; ++k) P = make_double2(-b * P.y, b * P.x);
     }
+  }
+  // sum over the columns of the wave (lanes with the same seg)
+#pragma unroll
+  for (int off = S; off < 64; off <<= 1)
+#pragma unroll
+    for (int q = 0; q < QM; ++q)
+#pragma unroll
+      for (int n = 0; n <= kOrder; ++n) acc[q][n] += __shfl_xor(acc[q][n], off, 64);
+  if (lane < S) {
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      const int m = lane + S * q;
+      if (m <= kOrder)
+#pragma unroll
+        for (int n = 0; n <= kOrder; ++n) red[wave][m][n] = acc[q][n];
+    }
+  }
+  // ---- Nyquist column kx = N/2: one row per thread
+  double2 Mn[kOrder + 1];
+#pragma unroll
+  for (int n = 0; n <= kOrder; ++n) Mn[n] = make_double2(0.0, 0.0);
+  for (int ky = tid; ky < N; ky += kNThreads) {
+    const CX xf = Xf[(size_t)ky * H + NC];
+    if (2 * ky == N) {
+#pragma unroll
+      for (int n = 0; n <= kOrder; ++n) {
+        Mn[n].x += (double)xf.x * ry[n];
+        Mn[n].y += (double)xf.y * ry[n];
+      }
+    } else {
+      const double2 ph = phy[ky];
+      add_powers(Mn, make_double2((double)xf.x * ph.x - (double)xf.y * ph.y,
+                                  (double)xf.x * ph.y + (double)xf.y * ph.x),
+                 ay[ky]);
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+    for (int n = 0; n <= kOrder; ++n) {
+      Mn[n].x += __shfl_xor(Mn[n].x, off, 64);
+      Mn[n].y += __shfl_xor(Mn[n].y, off, 64);
+    }
+  if (lane == 0)
+#pragma unroll
+    for (int n = 0; n <= kOrder; ++n) {
+      nred[wave][2 * n] = Mn[n].x;
+      nred[wave][2 * n + 1] = Mn[n].y;
+    }
+  __syncthreads();
+  // ---- final sums, fixed order
+  if (tid < kCoef) {
+    int n = 0, m = tid;
+    while (m > kOrder - n) {  // invert coef_index
+      m -= kOrder + 1 - n;
+      ++n;
+    }
+    double v = 0.0, mr = 0.0;
+    for (int w = 0; w < kNThreads / 64; ++w) {
+      v += red[w][m][n];
+      mr += nred[w][2 * n];
+    }
+    // Nyquist column: P_m = Re[exp(i pi sx) (i pi)^m], weight 1, real part of M_n
     double sn, cs;
     sincospi(sx, &sn, &cs);
-    add_terms(acc, M, make_double2(cs, sn), pi, true, 1.0);
-  }
-  // deterministic block reduction of the coefficients
-  const double inv = 1.0 / ((double)N * (double)N);
-#pragma unroll
-  for (int q = 0; q < kCoef; ++q) {
-    double v = acc[q];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((tid & 63) == 0) red[q][tid >> 6] = v;
-  }
-  __syncthreads();
-  if (tid < kCoef) {
-    double v = 0.0;
-    for (int w = 0; w < kNThreads / 64; ++w) v += red[tid][w];
-    coef[tid] = v * inv;
+    double2 P = make_double2(cs, sn);
+    for (int k = 0; k < m; ++k) P = make_double2(-pi * P.y, pi * P.x);
+    v += P.x * mr;
+    coef[coef_index(n, m)] = v / ((double)N * (double)N);
   }
   __syncthreads();
 }
@@ -219,11 +282,12 @@ __device__ void write_special(ccpt_result* out, unsigned status) {
   *out = r;
 }
 
-template <int N>
+template <int N, typename CX>
 __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step_limit) {
   __shared__ double2 phy[N];
   __shared__ double ay[N];
-  __shared__ double red[kCoef][kNThreads / 64];
+  __shared__ double red[kNThreads / 64][kOrder + 1][kOrder + 1];
+  __shared__ double nred[kNThreads / 64][2 * (kOrder + 1)];
   __shared__ double coef[kCoef];
   __shared__ double ctl[3];  // next centre y, x; another pass?
   const int f = blockIdx.x;
@@ -249,7 +313,8 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
   const int my = gk / g.M, mx = gk % g.M;
   const double dgy = py + (double)(my - g.c) / g.u;
   const double dgx = px + (double)(mx - g.c) / g.u;
-  const float2* Xf = g.X + (size_t)f * N * (N / 2 + 1);
+  const CX* Xf = (sizeof(CX) == sizeof(float2) ? (const CX*)g.X : (const CX*)g.X64) +
+                 (size_t)f * N * (N / 2 + 1);
 
   // the iterate and the decisions live in thread 0; the centre is broadcast
   double sy = dgy, sx = dgx;
@@ -259,7 +324,7 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
   double cy = dgy, cx = dgx;
   Deriv fin{0, 0, 0, 0, 0, 0};
   for (int pass = 0; pass < kMaxPasses; ++pass) {
-    build_model<N>(Xf, cy, cx, phy, ay, red, coef);
+    build_model<N, CX>(Xf, cy, cx, phy, ay, red, nred, coef);
     if (tid == 0) {
       while (!done && it_left > 0) {
         const Deriv e = model_eval(coef, sy - cy, sx - cx);
@@ -325,7 +390,10 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
 
 template <int N>
 static int newton_n(const GroupParams& g, double step_limit, hipStream_t s) {
-  hipLaunchKernelGGL((k_newton<N>), dim3(g.count), dim3(kNThreads), 0, s, g, step_limit);
+  if (g.X64)
+    hipLaunchKernelGGL((k_newton<N, double2>), dim3(g.count), dim3(kNThreads), 0, s, g, step_limit);
+  else
+    hipLaunchKernelGGL((k_newton<N, float2>), dim3(g.count), dim3(kNThreads), 0, s, g, step_limit);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

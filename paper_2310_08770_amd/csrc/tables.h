@@ -116,4 +116,39 @@ inline HostTables build_tables(int n, int u, int M, int c, int precision) {
   return t;
 }
 
+// FP64-mode tables: twiddles exp(-2 pi i m / N), K[m][ky] = phi_ky((m - c)/u)
+// as [Mp][N] and W[kx][mx] = w_kx phi_kx((mx - c)/u) / N^2 as [N/2+1][Mp],
+// complex FP64, zero beyond M.
+struct HostTables64 {
+  std::vector<double2> tw, ky, wb;
+};
+
+inline HostTables64 build_tables64(int n, int u, int M, int c, int Mp) {
+  HostTables64 t;
+  t.tw.resize(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = 2.0 * M_PI * (double)m / (double)n;
+    t.tw[m] = make_double2(std::cos(a), -std::sin(a));
+  }
+  const int H = n / 2 + 1;
+  t.ky.assign((size_t)Mp * n, make_double2(0.0, 0.0));
+  t.wb.assign((size_t)H * Mp, make_double2(0.0, 0.0));
+  const double inv = 1.0 / ((double)n * (double)n);
+  for (int m = 0; m < M; ++m) {
+    const double s = (double)(m - c) / u;
+    for (int ky = 0; ky < n; ++ky) {
+      double re, im;
+      phi_host(ky, n, s, re, im);
+      t.ky[(size_t)m * n + ky] = make_double2(re, im);
+    }
+    for (int kx = 0; kx < H; ++kx) {
+      double re, im;
+      phi_host(kx, n, s, re, im);
+      const double wt = (kx == 0 || 2 * kx == n) ? inv : 2.0 * inv;
+      t.wb[(size_t)kx * Mp + m] = make_double2(wt * re, wt * im);
+    }
+  }
+  return t;
+}
+
 }  // namespace ccpt

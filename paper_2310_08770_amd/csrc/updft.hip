@@ -58,12 +58,54 @@ constexpr int a_chunk(int N) {
   return best;
 }
 
+// Stage B of the FP32 path for one 32-row tile: U[32][Mp] = ym[32][KB] x
+// W[KB][Mp] on 16x16x4 tiles, then the tile's grid maximum merged into the
+// frame's key.  ym is in LDS; every thread of the block calls this.
+template <int N>
+__device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* __restrict__ Wtab,
+                            int Mp, int m0, int f, unsigned long long* red) {
+  constexpr int KB = (N + 31) / 32 * 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ntb = 2 * (Mp / 16);
+  unsigned long long best = 0;
+  const int l16 = lane & 15, q4 = lane >> 4;
+  for (int T = wave; T < ntb; T += 4) {
+    const int mt = T & 1, nt = T >> 1;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float* arow = ym + (mt * 16 + l16) * KB + q4;
+    const float* bcol = Wtab + (size_t)q4 * Mp + nt * 16 + l16;
+#pragma unroll 8
+    for (int k = 0; k < KB; k += 4) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k], bcol[(size_t)k * Mp], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int my = m0 + mt * 16 + q4 * 4 + v;
+      const int mx = nt * 16 + l16;
+      if (my < g.M && mx < g.M) {
+        const unsigned long long key = peak_key(acc[v], (unsigned)(my * g.M + mx));
+        best = key > best ? key : best;
+      }
+    }
+  }
+  best = wmax64(best);
+  if (lane == 0) red[wave] = best;
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < kUThreads / 64; ++w) best = red[w] > best ? red[w] : best;
+    atomicMax(&g.st[f].grid_key, best);
+  }
+}
+
 // ---------------------------------------------------------------- FP32
 // K table: float2 [Mp][N]  (K[m][ky] = phi_ky((m - c)/u))
 // W table: float  [Kb][Mp], Kb = N rounded up to 32 (zero rows past N)
-template <int N>
+// SPLIT (few frames, latency): blockIdx.z is one of `nsl` ky slices; the
+// block stores its partial Ymat to `ypart` and k_updft_f32_sum finishes.
+template <int N, bool SPLIT>
 __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const float2* __restrict__ Ktab,
-                                                         const float* __restrict__ Wtab, int Mp) {
+                                                         const float* __restrict__ Wtab, int Mp,
+                                                         float* __restrict__ ypart, int nsl) {
   constexpr int H = N / 2 + 1;
   constexpr int NC = N / 2;                 // columns on matrix cores
   constexpr int NT = (NC + 31) / 32;        // 32-wide column tiles
@@ -102,7 +144,10 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
   const int half = lane >> 5, l32 = lane & 31;
   __syncthreads();
 
-  for (int k0 = 0; k0 < N; k0 += KC) {
+  constexpr int NCH = N / KC;
+  const int ch0 = SPLIT ? (int)blockIdx.z * NCH / nsl : 0;
+  const int ch1 = SPLIT ? ((int)blockIdx.z + 1) * NCH / nsl : NCH;
+  for (int k0 = ch0 * KC; k0 < ch1 * KC; k0 += KC) {
     for (int i = tid; i < XS; i += kUThreads) {
       const int kk = i / H, kx = i - kk * H;
       const int ky = k0 + kk;
@@ -168,37 +213,35 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
     ym[tid * KB + NC] = s;
   }
   __syncthreads();
+  if constexpr (SPLIT) {
+    const int mtiles = Mp / 32;
+    float* dst = ypart + (((size_t)f * mtiles + blockIdx.x) * nsl + blockIdx.z) * 32 * KB;
+    for (int i = tid; i < 32 * KB; i += kUThreads) dst[i] = ym[i];
+  } else {
+    stage_b_f32<N>(g, ym, Wtab, Mp, m0, f, red);
+  }
+}
 
-  // Stage B: U[32][Mp] = ym[32][KB] x W[KB][Mp], 16x16x4 tiles
-  const int ntb = 2 * (Mp / 16);
-  unsigned long long best = 0;
-  const int l16 = lane & 15, q4 = lane >> 4;
-  for (int T = wave; T < ntb; T += 4) {
-    const int mt = T & 1, nt = T >> 1;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const float* arow = ym + (mt * 16 + l16) * KB + q4;
-    const float* bcol = Wtab + (size_t)q4 * Mp + nt * 16 + l16;
-#pragma unroll 8
-    for (int k = 0; k < KB; k += 4) {
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k], bcol[(size_t)k * Mp], acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int my = m0 + mt * 16 + q4 * 4 + v;
-      const int mx = nt * 16 + l16;
-      if (my < g.M && mx < g.M) {
-        const unsigned long long key = peak_key(acc[v], (unsigned)(my * g.M + mx));
-        best = key > best ? key : best;
-      }
-    }
+// Sums the ky-slice partials of one 32-row tile in a fixed order, then Stage B.
+template <int N>
+__global__ void __launch_bounds__(kUThreads) k_updft_f32_sum(GroupParams g, const float* __restrict__ Wtab,
+                                                             int Mp, const float* __restrict__ ypart,
+                                                             int nsl) {
+  constexpr int KB = (N + 31) / 32 * 32;
+  __shared__ float ym[32 * KB];
+  __shared__ unsigned long long red[kUThreads / 64];
+  const int f = blockIdx.y;
+  const FrameState st = g.st[f];
+  if (frame_skipped(st)) return;
+  const int mtiles = Mp / 32;
+  const float* src = ypart + ((size_t)f * mtiles + blockIdx.x) * nsl * 32 * KB;
+  for (int i = threadIdx.x; i < 32 * KB; i += kUThreads) {
+    float v = 0.f;
+    for (int q = 0; q < nsl; ++q) v += src[(size_t)q * 32 * KB + i];
+    ym[i] = v;
   }
-  best = wmax64(best);
-  if (lane == 0) red[wave] = best;
   __syncthreads();
-  if (tid == 0) {
-    for (int w = 1; w < kUThreads / 64; ++w) best = red[w] > best ? red[w] : best;
-    atomicMax(&g.st[f].grid_key, best);
-  }
+  stage_b_f32<N>(g, ym, Wtab, Mp, blockIdx.x * 32, f, red);
 }
 
 
@@ -422,16 +465,18 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
 
 // Wide variant for N >= 256: one block per frame and group of up to MT
 // 32-row m-tiles, one wave per 32-column kx tile.  Each frame's split
-// spectrum is streamed once from memory straight into the B operands (no
-// LDS staging, each fragment feeds 6 MT matrix instructions); the folded
-// K' rows of the block are built per 32-ky chunk in LDS and shared by all
-// waves.  The Nyquist column is accumulated in FP32 by the thread that
-// builds the row.  Stage B then runs m-tile by m-tile.
+// spectrum is streamed once from memory straight into the B operands (each
+// fragment feeds 6 MT matrix instructions).  The A operands come from the
+// precomputed folded table K'_p[m, ky] = phi_ky(p + (m - c)/u) for the
+// frame's integer peak row p (bf16 hi/lo words), copied per 32-ky chunk into
+// LDS and shared by all waves.  Row 0 of the split spectrum carries the
+// Nyquist column in its imaginary part, so Yi(., 0) is the Nyquist output.
+// The three products of each K step are issued pass by pass over all tiles
+// so consecutive matrix instructions never depend on each other.
 template <int N, int MT>
 __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
-    k_updft_bf16x2_wide(GroupParams g, const float2* __restrict__ Ktab,
+    k_updft_bf16x2_wide(GroupParams g, const unsigned* __restrict__ kfold,
                         const unsigned short* __restrict__ WbT, int Mp) {
-  constexpr int H = N / 2 + 1;
   constexpr int NC = N / 2;
   constexpr int NW = (NC + 31) / 32;  // waves = kx tiles
   constexpr int NTH = 64 * NW;
@@ -444,11 +489,8 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   constexpr int KW = 2 * ROWS * KCS;
   constexpr int YW = 32 * YST;
   constexpr int RAWW = KW > YW ? KW : YW;
-  static_assert(ROWS <= NTH, "one thread per K' row");
   __shared__ __attribute__((aligned(16))) unsigned raw[RAWW];
   __shared__ float2 twf[N];
-  __shared__ float2 xnyq[N];  // Nyquist column X[ky, N/2] of the frame
-  __shared__ float nyq[ROWS];
   __shared__ unsigned long long red[NW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -460,13 +502,13 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   unsigned pk = key_index(st.peak_key);
   if (pk >= (unsigned)(N * N)) pk = 0;
   const int iy = pk / N, ix = pk % N;
-  for (int i = tid; i < N; i += NTH) {
-    twf[i] = cconj(g.tw[i]);
-    xnyq[i] = g.X[(size_t)f * N * H + (size_t)i * H + NC];
-  }
+  for (int i = tid; i < N; i += NTH) twf[i] = cconj(g.tw[i]);
 
   unsigned* ks_hi = raw;
   unsigned* ks_lo = raw + ROWS * KCS;
+  const size_t kplane = (size_t)Mp * P;
+  const unsigned* Kh = kfold + (size_t)iy * 2 * kplane;
+  const unsigned* Kl = Kh + kplane;
   const unsigned* Xbh = g.Xb + (size_t)f * 2 * NC * P;
   const unsigned* Xbl = Xbh + (size_t)NC * P;
   const int h = lane >> 5, j = lane & 31;
@@ -478,9 +520,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   for (int t = 0; t < MT; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) accr[t][v] = acci[t][v] = 0.f;
-  float nacc = 0.f;
-  const bool krow = tid < mt_here * 32;
-  __syncthreads();
+  const int nrows = mt_here * 32;
 
   for (int k0 = 0; k0 < P; k0 += KC) {
     u32x4 bh[KC / 8], bl[KC / 8];
@@ -495,61 +535,49 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
         bl[s8] = u32x4{0u, 0u, 0u, 0u};
       }
     }
-    if (krow) {
-      // this thread's K row segment, fetched with 16-byte loads before use
-      const int m = tid;
-      const float4* krow_p = (const float4*)(Ktab + (size_t)(m0 + m) * N + k0);
-      constexpr int Q = KC / 2;  // float4 = two complex values
-      float4 kq[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q)
-        kq[q] = (k0 + 2 * q < N) ? krow_p[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int kk = 2 * q + e;
-          const int ky = k0 + kk;
-          float2 kv = make_float2(0.f, 0.f);
-          if (ky < N) {
-            const float2 kr = e ? make_float2(kq[q].z, kq[q].w) : make_float2(kq[q].x, kq[q].y);
-            kv = cmul(kr, twf[(ky * iy) % N]);
-            const float2 xn = xnyq[ky];
-            nacc += kv.x * xn.x - kv.y * xn.y;
-          }
-          unsigned wh, wl;
-          split_pair(kv, wh, wl);
-          ks_hi[m * KCS + kk] = wh;
-          ks_lo[m * KCS + kk] = wl;
-        }
-      }
+    // folded K' rows of this block: 16-byte copies into LDS
+    for (int i = tid; i < nrows * (KC / 4); i += NTH) {
+      const int r = i / (KC / 4), q = i - r * (KC / 4);
+      const size_t src = (size_t)(m0 + r) * P + k0 + 4 * q;
+      *(u32x4*)(ks_hi + r * KCS + 4 * q) = *(const u32x4*)(Kh + src);
+      *(u32x4*)(ks_lo + r * KCS + 4 * q) = *(const u32x4*)(Kl + src);
     }
     __syncthreads();
 #pragma unroll
     for (int s8 = 0; s8 < KC / 8; ++s8) {
       const int col = s8 * 8 + 4 * h;
       const bf16x8 b_h = as_bf(bh[s8]), b_l = as_bf(bl[s8]);
+      u32x4 ah[MT], al[MT];
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         if (t < mt_here) {
-          const u32x4 ah = *(const u32x4*)(ks_hi + (t * 32 + j) * KCS + col);
-          const u32x4 al = *(const u32x4*)(ks_lo + (t * 32 + j) * KCS + col);
-          const bf16x8 arh = as_bf(neg_im(ah)), aih = as_bf(swap_ri(ah));
-          const bf16x8 arl = as_bf(neg_im(al)), ail = as_bf(swap_ri(al));
-          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, b_h, accr[t], 0, 0, 0);
-          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, b_l, accr[t], 0, 0, 0);
-          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, b_h, accr[t], 0, 0, 0);
-          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, b_h, acci[t], 0, 0, 0);
-          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, b_l, acci[t], 0, 0, 0);
-          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, b_h, acci[t], 0, 0, 0);
+          ah[t] = *(const u32x4*)(ks_hi + (t * 32 + j) * KCS + col);
+          al[t] = *(const u32x4*)(ks_lo + (t * 32 + j) * KCS + col);
         }
       }
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        if (t < mt_here) {
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(neg_im(ah[t])), b_h, accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(swap_ri(ah[t])), b_h, acci[t], 0, 0, 0);
+        }
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        if (t < mt_here) {
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(neg_im(ah[t])), b_l, accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(swap_ri(ah[t])), b_l, acci[t], 0, 0, 0);
+        }
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        if (t < mt_here) {
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(neg_im(al[t])), b_h, accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(swap_ri(al[t])), b_h, acci[t], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
-  if (krow) nyq[tid] = (ix & 1) ? -nacc : nacc;  // kx phase exp(i pi p_x) of the Nyquist column
-  // kx phase of the fold
-  if (bvalid) {
+  // kx phase of the fold; column 0 holds (Y[., 0], Y[., N/2]) and its phase is 1
+  if (bvalid && kxrow > 0) {
     const float2 ph = twf[(kxrow * ix) % N];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
@@ -560,6 +588,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
         acci[t][v] = yr * ph.y + yi * ph.x;
       }
   }
+  const float nyq_sign = (ix & 1) ? -1.f : 1.f;  // exp(i pi p_x)
   unsigned short* ymh = (unsigned short*)raw;
   unsigned short* yml = ymh + 32 * YST;
   const int ntb = 2 * (Mp / 16);
@@ -575,24 +604,19 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
       ymh[r * YST + c] = 0;
       yml[r * YST + c] = 0;
     }
-    if (tid < 32) {
-      const float v = nyq[t * 32 + tid];
-      const unsigned a = bf16_bits(v);
-      ymh[tid * YST + NC] = (unsigned short)a;
-      yml[tid * YST + NC] = (unsigned short)bf16_bits(v - bf16_float(a));
-    }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int i = (v >> 2) * 8 + h * 4 + (v & 3);
       if (bvalid) {
-        const unsigned a = bf16_bits(accr[t][v]);
+        const float yr = accr[t][v];
+        const unsigned a = bf16_bits(yr);
         ymh[i * YST + kxrow] = (unsigned short)a;
-        yml[i * YST + kxrow] = (unsigned short)bf16_bits(accr[t][v] - bf16_float(a));
-        if (kxrow >= 1) {
-          const unsigned b = bf16_bits(acci[t][v]);
-          ymh[i * YST + NC + kxrow] = (unsigned short)b;
-          yml[i * YST + NC + kxrow] = (unsigned short)bf16_bits(acci[t][v] - bf16_float(b));
-        }
+        yml[i * YST + kxrow] = (unsigned short)bf16_bits(yr - bf16_float(a));
+        const float yi = kxrow == 0 ? nyq_sign * acci[t][v] : acci[t][v];
+        const int col = NC + kxrow;  // Yi of kx, or the Nyquist output for kx = 0
+        const unsigned b = bf16_bits(yi);
+        ymh[i * YST + col] = (unsigned short)b;
+        yml[i * YST + col] = (unsigned short)bf16_bits(yi - bf16_float(b));
       }
     }
     __syncthreads();
@@ -604,6 +628,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
       const unsigned short* al_p = yml + (mt * 16 + l16) * YST + 8 * q4;
       const unsigned short* bh_p = WbT + (size_t)(nt * 16 + l16) * KB + 8 * q4;
       const unsigned short* bl_p = WbL + (size_t)(nt * 16 + l16) * KB + 8 * q4;
+      f32x4 acc2 = {0.f, 0.f, 0.f, 0.f}, acc3 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
       for (int k = 0; k < KB; k += 32) {
         const bf16x8 a_h = as_bf(*(const u32x4*)(ah_p + k));
@@ -611,15 +636,16 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
         const bf16x8 w_h = as_bf(*(const u32x4*)(bh_p + k));
         const bf16x8 w_l = as_bf(*(const u32x4*)(bl_p + k));
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_h, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_l, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, w_h, acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_l, acc2, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, w_h, acc3, 0, 0, 0);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+        const float uval = acc[v] + (acc2[v] + acc3[v]);
         const int my = mrow0 + mt * 16 + q4 * 4 + v;
         const int mx = nt * 16 + l16;
         if (my < g.M && mx < g.M) {
-          const unsigned long long key = peak_key(acc[v], (unsigned)(my * g.M + mx));
+          const unsigned long long key = peak_key(uval, (unsigned)(my * g.M + mx));
           best = key > best ? key : best;
         }
       }
@@ -634,20 +660,72 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   }
 }
 
+// Folded split table for the wide kernel: K'_p[m, ky] = phi_ky(p + (m - c)/u)
+// for every integer peak row p, as bf16 hi/lo words (re | im << 16),
+// [N][2][Mp][xb_pitch(N)], computed in FP64 with exactly reduced phases.
+__global__ void k_build_kfold(unsigned* __restrict__ out, int N, int u, int M, int c, int Mp, int P) {
+  const size_t plane = (size_t)Mp * P;
+  const size_t total = (size_t)N * plane;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int iy = (int)(e / plane);
+    const size_t rem = e - (size_t)iy * plane;
+    const int m = (int)(rem / P), ky = (int)(rem % P);
+    double re = 0.0, im = 0.0;
+    if (m < M && ky < N) {
+      const long t = (long)iy * u + (m - c);  // position in units of 1/u
+      if (2 * ky == N) {
+        const long per = 2L * u;  // cos(pi t / u)
+        const long r = ((t % per) + per) % per;
+        re = cospi((double)r / (double)u);
+      } else {
+        const int kt = 2 * ky < N ? ky : ky - N;
+        const long per = (long)u * N;  // angle 2 pi kt t / (u N)
+        const long r = (((long)kt * t) % per + per) % per;
+        double sn, cs;
+        sincospi(2.0 * (double)r / (double)per, &sn, &cs);
+        re = cs;
+        im = sn;
+      }
+    }
+    const unsigned hr = bf16_bits((float)re), hm = bf16_bits((float)im);
+    const unsigned lr = bf16_bits((float)(re - (double)bf16_float(hr)));
+    const unsigned lm = bf16_bits((float)(im - (double)bf16_float(hm)));
+    const size_t base = (size_t)iy * 2 * plane + (size_t)m * P + ky;
+    out[base] = hr | (hm << 16);
+    out[base + plane] = lr | (lm << 16);
+  }
+}
+
+int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int Mp, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_kfold, dim3(4096), dim3(256), 0, s, out, N, u, M, c, Mp, xb_pitch(N));
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <int N>
 static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
   const int mtiles = t.Mp / 32;
   if (t.precision == CCPT_PREC_FP32) {
-    hipLaunchKernelGGL((k_updft_f32<N>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
-                       (const float2*)t.ky, (const float*)t.wb, t.Mp);
+    constexpr int NCH = N / a_chunk(N);
+    const int nsl = NCH < kSplitSlices ? NCH : kSplitSlices;
+    if (g.ypart && g.count * mtiles < kSplitMaxBlocks && nsl > 1) {
+      hipLaunchKernelGGL((k_updft_f32<N, true>), dim3(mtiles, g.count, nsl), dim3(kUThreads), 0, s,
+                         g, (const float2*)t.ky, (const float*)t.wb, t.Mp, g.ypart, nsl);
+      hipLaunchKernelGGL((k_updft_f32_sum<N>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
+                         (const float*)t.wb, t.Mp, (const float*)g.ypart, nsl);
+    } else {
+      hipLaunchKernelGGL((k_updft_f32<N, false>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
+                         (const float2*)t.ky, (const float*)t.wb, t.Mp, (float*)nullptr, 1);
+    }
   } else if (t.precision == CCPT_PREC_BF16X2) {
     if (!g.Xb) return -1;
-    if constexpr (N >= 256) {
+    if constexpr (N >= kWideMinN) {
       constexpr int MT = 5;
       constexpr int NW = (N / 2 + 31) / 32;
+      if (!t.kfold) return -1;
       hipLaunchKernelGGL((k_updft_bf16x2_wide<N, MT>), dim3((mtiles + MT - 1) / MT, g.count),
-                         dim3(64 * NW), 0, s, g, (const float2*)t.ky, (const unsigned short*)t.wb,
-                         t.Mp);
+                         dim3(64 * NW), 0, s, g, (const unsigned*)t.kfold,
+                         (const unsigned short*)t.wb, t.Mp);
     } else {
       hipLaunchKernelGGL((k_updft_bf16x2<N>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
                          (const float2*)t.ky, (const unsigned short*)t.wb, t.Mp);

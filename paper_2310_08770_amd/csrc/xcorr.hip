@@ -29,7 +29,7 @@ constexpr int rows_per_block(int N, int budget) {
 // no wider than the N/2+1 columns need
 constexpr int cols_per_block(int N) {
   int cb = 1;
-  while (cb * 2 * N <= 4096 && cb < N / 2 + 1) cb *= 2;
+  while (cb * 2 * N <= 4096 && cb < N / 2) cb *= 2;
   return cb;
 }
 
@@ -39,8 +39,26 @@ constexpr int row_block(int N) {
   return (N % 16 == 0 && 16 * (N / 2 + 1) <= 4200) ? 16 : rows_per_block(N, 2048);
 }
 
-__device__ __forceinline__ float load_px(const void* p, int dtype, long idx) {
-  return dtype == CCPT_U16 ? (float)((const unsigned short*)p)[idx] : ((const float*)p)[idx];
+// the same choices for FP64 data (half the values per LDS buffer)
+constexpr int cols_per_block64(int N) {
+  int cb = 1;
+  while (cb * 2 * N <= 2048 && cb < N / 2) cb *= 2;
+  return cb;
+}
+template <typename C>
+constexpr int row_block_of(int N) {
+  return sizeof(C) == sizeof(float2) ? row_block(N) : row_block64(N);
+}
+template <typename C>
+constexpr int cols_block_of(int N) {
+  return sizeof(C) == sizeof(float2) ? cols_per_block(N) : cols_per_block64(N);
+}
+
+template <typename R>
+__device__ __forceinline__ R load_px(const void* p, int dtype, long idx) {
+  if (dtype == CCPT_U16) return (R)((const unsigned short*)p)[idx];
+  if (dtype == CCPT_F64) return (R)((const double*)p)[idx];
+  return (R)((const float*)p)[idx];
 }
 
 // Where a row pass reads its images from.
@@ -63,7 +81,7 @@ __device__ __forceinline__ void img_of(const ImgSrc& s, int f, const void*& data
   } else {
     dtype = s.dtype;
     pitch = s.pitch;
-    data = (const char*)s.data + (size_t)f * s.img_stride * (dtype == CCPT_U16 ? 2 : 4);
+    data = (const char*)s.data + (size_t)f * s.img_stride * dtype_bytes(dtype);
   }
 }
 
@@ -103,17 +121,20 @@ __global__ void k_init_state(FrameState* st, int count) {
 }
 
 // Row pass, forward.  weight: 0 A = I, 1 B = -1/(E+eps), 2 A = (I+eps)^2.
-// Writes T[f][y][k], k < N/2+1.  With st != null records min/max of A and
-// non-finite pixels per frame.
-template <int N, int RPB>
-__global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, float eps,
-                                                       float2* __restrict__ T, FrameState* st,
-                                                       const float2* __restrict__ gtw) {
+// Writes T[f][y][k], k < N/2+1.  With st != null records min/max of A (as
+// FP32 keys) and non-finite pixels per frame.  C = float2 or double2 sets
+// the arithmetic.
+template <int N, int RPB, typename C>
+__global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, double eps_in,
+                                                       C* __restrict__ T, FrameState* st,
+                                                       const C* __restrict__ gtw) {
+  using R = real_t<C>;
   constexpr int L = N / 2, H = N / 2 + 1;
   constexpr int LS = L + 1;  // padded row stride in LDS
-  __shared__ float2 tw[N];
-  __shared__ float2 bufA[RPB * LS];
-  __shared__ float2 bufB[RPB * LS];
+  const R eps = (R)eps_in;
+  __shared__ C tw[N];
+  __shared__ C bufA[RPB * LS];
+  __shared__ C bufB[RPB * LS];
   __shared__ unsigned red[3][kThreads / 64];
   const int tid = threadIdx.x;
   const int f = blockIdx.y;
@@ -123,12 +144,12 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, f
   int dtype, pitch;
   img_of(src, f, data, dtype, pitch);
   unsigned kmin = 0xFFFFFFFFu, kmax = 0, bad = 0;
-  auto pro = [&](float a) {
-    if (weight == 1) a = -1.0f / (a + eps);
+  auto pro = [&](R a) {
+    if (weight == 1) a = R(-1) / (a + eps);
     else if (weight == 2) a = (a + eps) * (a + eps);
     if (!isfinite(a)) bad = 1;
-    kmin = min(kmin, f2key(a));
-    kmax = max(kmax, f2key(a));
+    kmin = min(kmin, f2key((float)a));
+    kmax = max(kmax, f2key((float)a));
     return a;
   };
   const bool vec16 = dtype == CCPT_U16 && N % 8 == 0 && pitch % 8 == 0 &&
@@ -143,22 +164,22 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, f
       const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        bufA[r * LS + 4 * q + e] = make_float2(pro((float)(w[e] & 0xFFFFu)), pro((float)(w[e] >> 16)));
+        bufA[r * LS + 4 * q + e] = mkc<C>(pro((R)(w[e] & 0xFFFFu)), pro((R)(w[e] >> 16)));
     }
   } else if (vec32) {
     for (int i = tid; i < RPB * (N / 4); i += kThreads) {
       const int r = i / (N / 4), q = i - r * (N / 4);
       const float4 v = *(const float4*)((const float*)data + (long)(y0 + r) * pitch + 4 * q);
-      bufA[r * LS + 2 * q] = make_float2(pro(v.x), pro(v.y));
-      bufA[r * LS + 2 * q + 1] = make_float2(pro(v.z), pro(v.w));
+      bufA[r * LS + 2 * q] = mkc<C>(pro((R)v.x), pro((R)v.y));
+      bufA[r * LS + 2 * q + 1] = mkc<C>(pro((R)v.z), pro((R)v.w));
     }
   } else {
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, c = i - r * L;
       const long idx = (long)(y0 + r) * pitch + 2 * c;
-      const float a0 = pro(load_px(data, dtype, idx));
-      const float a1 = pro(load_px(data, dtype, idx + 1));
-      bufA[r * LS + c] = make_float2(a0, a1);
+      const R a0 = pro(load_px<R>(data, dtype, idx));
+      const R a1 = pro(load_px<R>(data, dtype, idx + 1));
+      bufA[r * LS + c] = mkc<C>(a0, a1);
     }
   }
   if (st) {
@@ -182,115 +203,141 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, f
     atomicMax(&st[f].amax, kmax);
     if (bad) atomicOr(&st[f].flags, (unsigned)CCPT_ST_NONFINITE);
   }
-  float2* z = fft_lds<L, -1, N>(bufA, bufB, RPB, LS, tw);
+  C* z = fft_lds<L, -1, N>(bufA, bufB, RPB, LS, tw);
   // unpack: X[k] = E[k] + W^k O[k], E = (Z[k] + conj Z[L-k]) / 2,
   // O = (Z[k] - conj Z[L-k]) / (2i), W = exp(-2 pi i / N); stored column-major
   // T[k][y] so each column k receives RPB consecutive rows
-  float2* Tf = T + (size_t)f * N * H;
+  C* Tf = T + (size_t)f * N * H;
+  const R half = R(0.5);
   for (int i = tid; i < RPB * H; i += kThreads) {
     const int k = i / RPB, r = i - k * RPB;
-    const float2 zk = z[r * LS + (k == L ? 0 : k)];
-    const float2 zc = cconj(z[r * LS + (k == 0 ? 0 : L - k)]);
-    const float2 e = cscale(cadd(zk, zc), 0.5f);
-    const float2 d = csub(zk, zc);
-    const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // d / (2i)
+    const C zk = z[r * LS + (k == L ? 0 : k)];
+    const C zc = cconj(z[r * LS + (k == 0 ? 0 : L - k)]);
+    const C e = cscale(cadd(zk, zc), half);
+    const C d = csub(zk, zc);
+    const C o = mkc<C>(half * d.y, -half * d.x);  // d / (2i)
     Tf[(size_t)k * N + y0 + r] = cadd(e, cmul(tw[k], o));
   }
 }
 
 enum ColKind { COL_XCORR = 0, COL_FWD = 1, COL_FWD_CONJ = 2, COL_INV = 3 };
 
-// Column pass over CB of the N/2+1 columns.
+// Column pass over the N/2+1 columns: block b takes columns b*CB .. b*CB+CB-1
+// of the first N/2, and block 0 also takes the Nyquist column N/2 (so no
+// block is left with a single column, and block 0 holds both real-output
+// columns 0 and N/2 for the packed split-precision copy).
 //  COL_XCORR:    forward FFT, X = F[A] * rspec (stored to X), inverse FFT back into T
 //  COL_FWD:      forward FFT stored to `spec`
 //  COL_FWD_CONJ: conjugate of the forward FFT stored to `spec`
 //  COL_INV:      inverse FFT of `spec` stored to T
-template <int N, int CB, int KIND>
+template <int N, int CB, int KIND, typename C>
 __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__ desc, int first,
-                                                   float2* __restrict__ T, float2* __restrict__ X,
+                                                   C* __restrict__ T, C* __restrict__ X,
                                                    unsigned* __restrict__ Xb,
-                                                   float2* __restrict__ spec, long spec_stride,
-                                                   const float2* __restrict__ gtw) {
-  constexpr int H = N / 2 + 1, S = N + 1;
-  __shared__ float2 tw[N];
-  __shared__ float2 bufA[CB * S];
-  __shared__ float2 bufB[CB * S];
+                                                   C* __restrict__ spec, long spec_stride,
+                                                   const C* __restrict__ gtw) {
+  constexpr int H = N / 2 + 1, S = N + 1, NC = N / 2;
+  constexpr int CS = CB + 1;  // column slots: CB regular + the Nyquist slot of block 0
+  const C zero = mkc<C>(0, 0);
+  __shared__ C tw[N];
+  __shared__ C bufA[CS * S];
+  __shared__ C bufB[CS * S];
   const int tid = threadIdx.x;
   const int f = blockIdx.y;
   const int c0 = blockIdx.x * CB;
-  const int ncol = min(CB, H - c0);
+  const int nreg = min(CB, NC - c0);       // regular columns of this block
+  const bool has_nyq = blockIdx.x == 0;
+  const int nseq = has_nyq ? CS : CB;
+  // slot -> column index (-1 when empty)
+  auto col_of = [&](int c) { return c < nreg ? c0 + c : (c == CB && has_nyq ? NC : -1); };
   for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
   // T is column-major: column kx holds N consecutive rows
-  float2* Tf = T + (size_t)f * N * H;
+  C* Tf = T + (size_t)f * N * H;
   if constexpr (KIND == COL_INV) {
-    const float2* inp = spec + (size_t)f * spec_stride;  // row-major spectrum
-    for (int i = tid; i < N * CB; i += kThreads) {
-      const int y = i / CB, c = i - y * CB;
-      bufA[c * S + y] = c < ncol ? inp[(size_t)y * H + c0 + c] : make_float2(0.f, 0.f);
+    const C* inp = spec + (size_t)f * spec_stride;  // row-major spectrum
+    for (int i = tid; i < N * nseq; i += kThreads) {
+      const int y = i / nseq, c = i - y * nseq;
+      const int kx = col_of(c);
+      bufA[c * S + y] = kx >= 0 ? inp[(size_t)y * H + kx] : mkc<C>(0, 0);
     }
   } else {
-    for (int i = tid; i < N * CB; i += kThreads) {
+    for (int i = tid; i < N * nseq; i += kThreads) {
       const int c = i / N, y = i - c * N;
-      bufA[c * S + y] = c < ncol ? Tf[(size_t)(c0 + c) * N + y] : make_float2(0.f, 0.f);
+      const int kx = col_of(c);
+      bufA[c * S + y] = kx >= 0 ? Tf[(size_t)kx * N + y] : mkc<C>(0, 0);
     }
   }
   __syncthreads();
   if constexpr (KIND == COL_INV) {
-    float2* r = fft_lds<N, +1, N>(bufA, bufB, CB, S, tw);
-    for (int i = tid; i < N * CB; i += kThreads) {
+    C* r = fft_lds<N, +1, N>(bufA, bufB, nseq, S, tw);
+    for (int i = tid; i < N * nseq; i += kThreads) {
       const int c = i / N, y = i - c * N;
-      if (c < ncol) Tf[(size_t)(c0 + c) * N + y] = r[c * S + y];
+      const int kx = col_of(c);
+      if (kx >= 0) Tf[(size_t)kx * N + y] = r[c * S + y];
     }
   } else {
-    float2* r = fft_lds<N, -1, N>(bufA, bufB, CB, S, tw);
+    C* r = fft_lds<N, -1, N>(bufA, bufB, nseq, S, tw);
     if constexpr (KIND == COL_FWD || KIND == COL_FWD_CONJ) {
-      float2* out = spec + (size_t)f * spec_stride;
-      for (int i = tid; i < N * CB; i += kThreads) {
-        const int y = i / CB, c = i - y * CB;
-        if (c < ncol) {
-          float2 v = r[c * S + y];
+      C* out = spec + (size_t)f * spec_stride;
+      for (int i = tid; i < N * nseq; i += kThreads) {
+        const int y = i / nseq, c = i - y * nseq;
+        const int kx = col_of(c);
+        if (kx >= 0) {
+          C v = r[c * S + y];
           if (KIND == COL_FWD_CONJ) v.y = -v.y;
-          out[(size_t)y * H + c0 + c] = v;
+          out[(size_t)y * H + kx] = v;
         }
       }
     } else {
-      const float2* R = desc[first + f].rspec;
-      float2* Xf = X + (size_t)f * N * H;
-      for (int i = tid; i < N * CB; i += kThreads) {
-        const int y = i / CB, c = i - y * CB;
-        if (c < ncol) {
-          const float2 v = cmul(r[c * S + y], R[(size_t)y * H + c0 + c]);
-          Xf[(size_t)y * H + c0 + c] = v;
+      const C* R = (const C*)desc[first + f].rspec;
+      C* Xf = X + (size_t)f * N * H;
+      for (int i = tid; i < N * nseq; i += kThreads) {
+        const int y = i / nseq, c = i - y * nseq;
+        const int kx = col_of(c);
+        if (kx >= 0) {
+          const C v = cmul(r[c * S + y], R[(size_t)y * H + kx]);
+          Xf[(size_t)y * H + kx] = v;
           r[c * S + y] = v;
         } else {
-          r[c * S + y] = make_float2(0.f, 0.f);
+          r[c * S + y] = zero;
         }
       }
       __syncthreads();
+      if constexpr (sizeof(C) == sizeof(float2)) {
       if (Xb) {
-        // bf16 hi/lo split of X for the matrix cores, one row per column kx < N/2,
-        // ky contiguous, rows padded to xb_pitch(N) with zeros; DC dropped
-        constexpr int NC = N / 2, P = xb_pitch(N);
+        // bf16 hi/lo split of X for the matrix cores: one row per column
+        // kx < N/2, ky contiguous, rows padded to xb_pitch(N) with zeros.  Row
+        // 0 carries Z = X[., 0] + i X[., N/2]: both columns give real Stage A
+        // outputs, so Re and Im of the product with Z are the two of them.
+        // The DC term X[0, 0] is dropped.
+        constexpr int P = xb_pitch(N);
         unsigned* hi = Xb + (size_t)f * 2 * NC * P;
         unsigned* lo = hi + (size_t)NC * P;
-        for (int i = tid; i < CB * P; i += kThreads) {
+        for (int i = tid; i < nreg * P; i += kThreads) {
           const int c = i / P, y = i - c * P;
           const int kx = c0 + c;
-          if (c < ncol && kx < NC) {
-            float2 v = y < N ? r[c * S + y] : make_float2(0.f, 0.f);
-            if (kx == 0 && y == 0) v = make_float2(0.f, 0.f);
-            unsigned wh, wl;
-            split_pair(v, wh, wl);
-            hi[(size_t)kx * P + y] = wh;
-            lo[(size_t)kx * P + y] = wl;
+          float2 v = make_float2(0.f, 0.f);
+          if (y < N) {
+            v = r[c * S + y];
+            if (kx == 0) {
+              if (y == 0) v.x = 0.f;
+              const float2 nq = r[CB * S + y];
+              v = make_float2(v.x - nq.y, v.y + nq.x);  // + i * X[y, N/2]
+            }
           }
+          unsigned wh, wl;
+          split_pair(v, wh, wl);
+          hi[(size_t)kx * P + y] = wh;
+          lo[(size_t)kx * P + y] = wl;
         }
       }
-      float2* o = (r == bufA) ? bufB : bufA;
-      float2* q = fft_lds<N, +1, N>(r, o, CB, S, tw);
-      for (int i = tid; i < N * CB; i += kThreads) {
+      }
+      C* o = (r == bufA) ? bufB : bufA;
+      C* q = fft_lds<N, +1, N>(r, o, nseq, S, tw);
+      for (int i = tid; i < N * nseq; i += kThreads) {
         const int c = i / N, y = i - c * N;
-        if (c < ncol) Tf[(size_t)(c0 + c) * N + y] = q[c * S + y];
+        const int kx = col_of(c);
+        if (kx >= 0) Tf[(size_t)kx * N + y] = q[c * S + y];
       }
     }
   }
@@ -300,45 +347,52 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
 // complex values Z = E + i O with E = (X[k] + conj X[L-k]) / 2 and
 // O = (X[k] - conj X[L-k]) W^-k / 2, transformed, and read out as the N reals
 // z[n] = a[2n] + i a[2n+1].
-// ARGMAX: per-frame maximum with ties to the lowest row-major index.
-// Otherwise the real row is scaled and stored to img (N x N per frame).
-template <int N, int RPB, bool ARGMAX>
-__global__ void __launch_bounds__(kThreads) k_rows_inv(const float2* __restrict__ T,
-                                                       FrameState* st, float* img, float scale,
-                                                       const float2* __restrict__ gtw) {
+// ARGMAX: per-frame maximum with ties to the lowest row-major index: in FP32
+// one 64-bit atomic key per frame, in FP64 one candidate per row block
+// (cand[f][blockIdx.x]).  Otherwise the real row is scaled and stored to img
+// (N x N per frame, FP32 only).
+template <int N, int RPB, bool ARGMAX, typename C>
+__global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, FrameState* st,
+                                                       float* img, float scale,
+                                                       const C* __restrict__ gtw,
+                                                       PeakCand* __restrict__ cand) {
+  using R = real_t<C>;
+  constexpr bool FP64 = sizeof(C) != sizeof(float2);
   constexpr int L = N / 2, H = N / 2 + 1;
   constexpr int LS = L + 1;
-  __shared__ float2 tw[N];
-  __shared__ float2 raw[RPB * H];
-  __shared__ float2 bufA[RPB * LS];
-  __shared__ float2 bufB[RPB * LS];
+  __shared__ C tw[N];
+  __shared__ C raw[RPB * H];
+  __shared__ C bufA[RPB * LS];
+  __shared__ C bufB[RPB * LS];
   __shared__ unsigned long long red[kThreads / 64];
+  __shared__ double redv[kThreads / 64];
   const int tid = threadIdx.x;
   const int f = blockIdx.y;
   const int y0 = blockIdx.x * RPB;
   for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
   // column-major T: column k holds rows y0..y0+RPB-1 consecutively
-  const float2* Tf = T + (size_t)f * N * H + y0;
+  const C* Tf = T + (size_t)f * N * H + y0;
   for (int i = tid; i < RPB * H; i += kThreads) {
     const int k = i / RPB, r = i - k * RPB;
     raw[r * H + k] = Tf[(size_t)k * N + r];
   }
   __syncthreads();
+  const R half = R(0.5);
   for (int i = tid; i < RPB * L; i += kThreads) {
     const int r = i / L, k = i - r * L;
-    const float2 xk = raw[r * H + k];
-    const float2 xc = cconj(raw[r * H + L - k]);
-    const float2 e = cscale(cadd(xk, xc), 0.5f);
-    const float2 o = cmul(cscale(csub(xk, xc), 0.5f), cconj(tw[k]));
-    bufA[r * LS + k] = make_float2(e.x - o.y, e.y + o.x);  // e + i o
+    const C xk = raw[r * H + k];
+    const C xc = cconj(raw[r * H + L - k]);
+    const C e = cscale(cadd(xk, xc), half);
+    const C o = cmul(cscale(csub(xk, xc), half), cconj(tw[k]));
+    bufA[r * LS + k] = mkc<C>(e.x - o.y, e.y + o.x);  // e + i o
   }
   __syncthreads();
-  float2* z = fft_lds<L, +1, N>(bufA, bufB, RPB, LS, tw);
-  if constexpr (ARGMAX) {
+  C* z = fft_lds<L, +1, N>(bufA, bufB, RPB, LS, tw);
+  if constexpr (ARGMAX && !FP64) {
     unsigned long long best = 0;
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
-      const float2 v = z[r * LS + n];
+      const C v = z[r * LS + n];
       const unsigned flat = (unsigned)((y0 + r) * N + 2 * n);
       unsigned long long k0 = peak_key(v.x, flat);
       unsigned long long k1 = peak_key(v.y, flat + 1);
@@ -352,11 +406,44 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const float2* __restrict_
       for (int w = 1; w < kThreads / 64; ++w) best = red[w] > best ? red[w] : best;
       atomicMax(&st[f].peak_key, best);
     }
-  } else {
+  } else if constexpr (ARGMAX) {
+    // (value, index) pairs: larger value wins, equal values go to the lower
+    // index; NaN never wins
+    double bv = -__builtin_inf();
+    unsigned bi = 0xFFFFFFFFu;
+    auto take = [&](double v, unsigned i) {
+      if (v > bv || (v == bv && i < bi)) {
+        bv = v;
+        bi = i;
+      }
+    };
+    for (int i = tid; i < RPB * L; i += kThreads) {
+      const int r = i / L, n = i - r * L;
+      const C v = z[r * LS + n];
+      const unsigned flat = (unsigned)((y0 + r) * N + 2 * n);
+      take(v.x, flat);
+      take(v.y, flat + 1);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) take(__shfl_xor(bv, o, 64), (unsigned)__shfl_xor((int)bi, o, 64));
+    if ((tid & 63) == 0) {
+      redv[tid >> 6] = bv;
+      red[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < kThreads / 64; ++w) take(redv[w], (unsigned)red[w]);
+      PeakCand pc;
+      pc.v = bv;
+      pc.idx = bi;
+      pc.pad = 0;
+      cand[(size_t)f * gridDim.x + blockIdx.x] = pc;
+    }
+  } else if constexpr (!FP64) {
     float* out = img + (size_t)f * N * N + (size_t)y0 * N;
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
-      const float2 v = z[r * LS + n];
+      const C v = z[r * LS + n];
       out[r * N + 2 * n] = v.x * scale;
       out[r * N + 2 * n + 1] = v.y * scale;
     }
@@ -367,44 +454,67 @@ template <int N>
 static int xcorr_n(const GroupParams& g, hipStream_t s, const Marker& mark) {
   constexpr int RPB = row_block(N);
   constexpr int CB = cols_per_block(N);
-  constexpr int H = N / 2 + 1;
   mark(CCPT_STAGE_INIT, 1);
   hipLaunchKernelGGL(k_init_state, dim3((g.count + 255) / 256), dim3(256), 0, s, g.st, g.count);
   mark(CCPT_STAGE_INIT, 0);
   ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0};
   mark(CCPT_STAGE_ROWS_FWD, 1);
-  hipLaunchKernelGGL((k_rows_fwd<N, RPB>), dim3(N / RPB, g.count), dim3(kThreads), 0, s, src,
-                     g.mode == CCPT_MODE_CCSN ? 2 : 0, g.eps, g.T, g.st, g.tw);
+  hipLaunchKernelGGL((k_rows_fwd<N, RPB, float2>), dim3(N / RPB, g.count), dim3(kThreads), 0, s,
+                     src, g.mode == CCPT_MODE_CCSN ? 2 : 0, (double)g.eps, g.T, g.st, g.tw);
   mark(CCPT_STAGE_ROWS_FWD, 0);
   mark(CCPT_STAGE_COLS, 1);
-  hipLaunchKernelGGL((k_cols<N, CB, COL_XCORR>), dim3((H + CB - 1) / CB, g.count), dim3(kThreads),
-                     0, s, g.desc, g.first, g.T, g.X, g.Xb, (float2*)nullptr, 0L, g.tw);
+  hipLaunchKernelGGL((k_cols<N, CB, COL_XCORR, float2>), dim3((N / 2 + CB - 1) / CB, g.count),
+                     dim3(kThreads), 0, s, g.desc, g.first, g.T, g.X, g.Xb, (float2*)nullptr, 0L,
+                     g.tw);
   mark(CCPT_STAGE_COLS, 0);
   mark(CCPT_STAGE_ROWS_INV, 1);
-  hipLaunchKernelGGL((k_rows_inv<N, RPB, true>), dim3(N / RPB, g.count), dim3(kThreads), 0, s,
-                     g.T, g.st, (float*)nullptr, 1.0f, g.tw);
+  hipLaunchKernelGGL((k_rows_inv<N, RPB, true, float2>), dim3(N / RPB, g.count), dim3(kThreads), 0,
+                     s, g.T, g.st, (float*)nullptr, 1.0f, g.tw, (PeakCand*)nullptr);
   mark(CCPT_STAGE_ROWS_INV, 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int N>
+static int xcorr64_n(const GroupParams& g, hipStream_t s, const Marker& mark) {
+  constexpr int RPB = row_block64(N);
+  constexpr int CB = cols_per_block64(N);
+  mark(CCPT_STAGE_INIT, 1);
+  hipLaunchKernelGGL(k_init_state, dim3((g.count + 255) / 256), dim3(256), 0, s, g.st, g.count);
+  mark(CCPT_STAGE_INIT, 0);
+  ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0};
+  mark(CCPT_STAGE_ROWS_FWD, 1);
+  hipLaunchKernelGGL((k_rows_fwd<N, RPB, double2>), dim3(N / RPB, g.count), dim3(kThreads), 0, s,
+                     src, g.mode == CCPT_MODE_CCSN ? 2 : 0, g.eps64, g.T64, g.st, g.tw64);
+  mark(CCPT_STAGE_ROWS_FWD, 0);
+  mark(CCPT_STAGE_COLS, 1);
+  hipLaunchKernelGGL((k_cols<N, CB, COL_XCORR, double2>), dim3((N / 2 + CB - 1) / CB, g.count),
+                     dim3(kThreads), 0, s, g.desc, g.first, g.T64, g.X64, (unsigned*)nullptr,
+                     (double2*)nullptr, 0L, g.tw64);
+  mark(CCPT_STAGE_COLS, 0);
+  mark(CCPT_STAGE_ROWS_INV, 1);
+  hipLaunchKernelGGL((k_rows_inv<N, RPB, true, double2>), dim3(N / RPB, g.count), dim3(kThreads),
+                     0, s, g.T64, g.st, (float*)nullptr, 1.0f, g.tw64, g.cand);
+  mark(CCPT_STAGE_ROWS_INV, 0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, typename C>
 static int spectrum_n(const void* data, int dtype, int pitch, long img_stride, int n, int weight,
-                      float eps, int conj_out, float2* T, float2* spec, const float2* tw,
-                      hipStream_t s) {
-  constexpr int RPB = row_block(N);
-  constexpr int CB = cols_per_block(N);
+                      double eps, int conj_out, C* T, C* spec, const C* tw, hipStream_t s) {
+  constexpr int RPB = row_block_of<C>(N);
+  constexpr int CB = cols_block_of<C>(N);
   constexpr int H = N / 2 + 1;
   ImgSrc src{nullptr, 0, data, dtype, pitch, img_stride};
-  hipLaunchKernelGGL((k_rows_fwd<N, RPB>), dim3(N / RPB, n), dim3(kThreads), 0, s, src, weight,
+  hipLaunchKernelGGL((k_rows_fwd<N, RPB, C>), dim3(N / RPB, n), dim3(kThreads), 0, s, src, weight,
                      eps, T, (FrameState*)nullptr, tw);
   if (conj_out)
-    hipLaunchKernelGGL((k_cols<N, CB, COL_FWD_CONJ>), dim3((H + CB - 1) / CB, n), dim3(kThreads),
-                       0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (unsigned*)nullptr,
-                       spec, (long)N * H, tw);
+    hipLaunchKernelGGL((k_cols<N, CB, COL_FWD_CONJ, C>), dim3((N / 2 + CB - 1) / CB, n),
+                       dim3(kThreads), 0, s, (const FrameDesc*)nullptr, 0, T, (C*)nullptr,
+                       (unsigned*)nullptr, spec, (long)N * H, tw);
   else
-    hipLaunchKernelGGL((k_cols<N, CB, COL_FWD>), dim3((H + CB - 1) / CB, n), dim3(kThreads), 0, s,
-                       (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (unsigned*)nullptr, spec,
-                       (long)N * H, tw);
+    hipLaunchKernelGGL((k_cols<N, CB, COL_FWD, C>), dim3((N / 2 + CB - 1) / CB, n), dim3(kThreads),
+                       0, s, (const FrameDesc*)nullptr, 0, T, (C*)nullptr, (unsigned*)nullptr,
+                       spec, (long)N * H, tw);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -415,11 +525,11 @@ static int frame_spectra_n(const FrameDesc* desc, int first, int count, int mode
   constexpr int CB = cols_per_block(N);
   constexpr int H = N / 2 + 1;
   ImgSrc src{desc, first, nullptr, 0, 0, 0};
-  hipLaunchKernelGGL((k_rows_fwd<N, RPB>), dim3(N / RPB, count), dim3(kThreads), 0, s, src,
-                     mode == CCPT_MODE_CCSN ? 2 : 0, eps, T, (FrameState*)nullptr, tw);
-  hipLaunchKernelGGL((k_cols<N, CB, COL_FWD>), dim3((H + CB - 1) / CB, count), dim3(kThreads), 0,
-                     s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (unsigned*)nullptr,
-                     spec, (long)N * H, tw);
+  hipLaunchKernelGGL((k_rows_fwd<N, RPB, float2>), dim3(N / RPB, count), dim3(kThreads), 0, s, src,
+                     mode == CCPT_MODE_CCSN ? 2 : 0, (double)eps, T, (FrameState*)nullptr, tw);
+  hipLaunchKernelGGL((k_cols<N, CB, COL_FWD, float2>), dim3((N / 2 + CB - 1) / CB, count),
+                     dim3(kThreads), 0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr,
+                     (unsigned*)nullptr, spec, (long)N * H, tw);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -429,11 +539,11 @@ static int inverse_n(const float2* spec, int n, float scale, float2* T, float* i
   constexpr int RPB = row_block(N);
   constexpr int CB = cols_per_block(N);
   constexpr int H = N / 2 + 1;
-  hipLaunchKernelGGL((k_cols<N, CB, COL_INV>), dim3((H + CB - 1) / CB, n), dim3(kThreads), 0, s,
-                     (const FrameDesc*)nullptr, 0, T, (float2*)nullptr, (unsigned*)nullptr,
-                     (float2*)spec, (long)N * H, tw);
-  hipLaunchKernelGGL((k_rows_inv<N, RPB, false>), dim3(N / RPB, n), dim3(kThreads), 0, s, T,
-                     (FrameState*)nullptr, img, scale, tw);
+  hipLaunchKernelGGL((k_cols<N, CB, COL_INV, float2>), dim3((N / 2 + CB - 1) / CB, n),
+                     dim3(kThreads), 0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr,
+                     (unsigned*)nullptr, (float2*)spec, (long)N * H, tw);
+  hipLaunchKernelGGL((k_rows_inv<N, RPB, false, float2>), dim3(N / RPB, n), dim3(kThreads), 0, s,
+                     T, (FrameState*)nullptr, img, scale, tw, (PeakCand*)nullptr);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -452,13 +562,39 @@ int launch_xcorr(int N, const GroupParams& g, hipStream_t s, const Marker& mark)
   return -2;
 }
 
+int launch_xcorr64(int N, const GroupParams& g, hipStream_t s, const Marker& mark) {
+  switch (N) {
+#define CASE(n) \
+  case n:       \
+    return xcorr64_n<n>(g, s, mark);
+    CCPT_FOR_SIZES(CASE)
+#undef CASE
+  }
+  return -2;
+}
+
 int launch_spectrum(int N, const void* data, int dtype, int pitch, long img_stride, int n,
                     int weight, float eps, int conj_out, float2* T, float2* spec,
                     const float2* tw, hipStream_t s) {
   switch (N) {
-#define CASE(nn) \
-  case nn:       \
-    return spectrum_n<nn>(data, dtype, pitch, img_stride, n, weight, eps, conj_out, T, spec, tw, s);
+#define CASE(nn)                                                                                \
+  case nn:                                                                                      \
+    return spectrum_n<nn, float2>(data, dtype, pitch, img_stride, n, weight, (double)eps,       \
+                                  conj_out, T, spec, tw, s);
+    CCPT_FOR_SIZES(CASE)
+#undef CASE
+  }
+  return -2;
+}
+
+int launch_spectrum64(int N, const void* data, int dtype, int pitch, long img_stride, int n,
+                      int weight, double eps, int conj_out, double2* T, double2* spec,
+                      const double2* tw, hipStream_t s) {
+  switch (N) {
+#define CASE(nn)                                                                                 \
+  case nn:                                                                                       \
+    return spectrum_n<nn, double2>(data, dtype, pitch, img_stride, n, weight, eps, conj_out, T,  \
+                                   spec, tw, s);
     CCPT_FOR_SIZES(CASE)
 #undef CASE
   }

@@ -229,3 +229,47 @@ def test_template_optimisation_reduces_loss():
     _, losses = optimise_template(fr, t(shifts), ref0, tr, steps=20, log=say)
     assert losses[-1] < losses[0]
     tr.close()
+
+
+def test_autotune_and_chunking_do_not_change_results():
+    say("case: chunk sizes and the autotuner leave results unchanged")
+    from paper_2310_08770_amd import decode
+    w = S.config2(96)
+    ref = t(w.refs[0].astype(np.float32))
+    fr = t(np.stack(w.frames))
+    for prec in ("fp32", "bf16x2"):
+        tr = tracker(upsample=100, precision=prec)
+        tr.set_reference(ref)
+        outs = {}
+        for chunk in (7, 32, 96):
+            tr.set_chunk(256, chunk)
+            assert tr.chunk(256) == chunk
+            outs[chunk] = decode(tr.track(fr))
+        best = tr.autotune(256, 96)
+        assert best >= 1
+        tuned = decode(tr.track(fr))
+        # chunks of 32 and 96 frames sum Stage A in the same order: identical bits
+        assert outs[32].tobytes() == outs[96].tobytes(), prec
+        for other in (outs[7], tuned):
+            if prec == "bf16x2":
+                assert other.tobytes() == outs[32].tobytes(), prec
+            else:
+                # FP32 launches of fewer than 128 grid-row tiles (7 frames x 5 tiles)
+                # split Stage A over ky slices: the same sums in another order
+                assert np.array_equal(other["p"], outs[32]["p"])
+                err = np.max(np.abs(other["d"] - outs[32]["d"]))
+                say(f"  fp32 split-K vs whole-K launches: max |dd| = {err:.2e}")
+                assert err <= 1e-6
+        tr.close()
+
+
+def test_profile_stage_times():
+    say("case: per-stage event timing")
+    w = S.config1(10)
+    tr = tracker(upsample=20, profile=True)
+    tr.set_reference(t(w.refs[0].astype(np.float32)))
+    tr.track(t(np.stack(w.frames)))
+    st = tr.stage_times()
+    for k in ("rows_fwd", "cols", "rows_inv", "updft", "newton"):
+        assert st[k][1] >= 1 and st[k][0] > 0
+    tr.close()
