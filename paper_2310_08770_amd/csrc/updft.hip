@@ -58,13 +58,22 @@ constexpr int a_chunk(int N) {
   return best;
 }
 
+// Row stride (floats) of the FP32 path's Ymat in LDS: KB + 4, so the 16
+// rows read by one Stage B MFMA fall in 16 different bank groups.
+template <int N>
+constexpr int ym_stride() {
+  return (N + 31) / 32 * 32 + 4;
+}
+
 // Stage B of the FP32 path for one 32-row tile: U[32][Mp] = ym[32][KB] x
 // W[KB][Mp] on 16x16x4 tiles, then the tile's grid maximum merged into the
-// frame's key.  ym is in LDS; every thread of the block calls this.
+// frame's key.  ym is in LDS (row stride ym_stride); every thread of the
+// block calls this.
 template <int N>
 __device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* __restrict__ Wtab,
                             int Mp, int m0, int f, unsigned long long* red) {
   constexpr int KB = (N + 31) / 32 * 32;
+  constexpr int YR = ym_stride<N>();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ntb = 2 * (Mp / 16);
   unsigned long long best = 0;
@@ -72,7 +81,7 @@ __device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* 
   for (int T = wave; T < ntb; T += 4) {
     const int mt = T & 1, nt = T >> 1;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const float* arow = ym + (mt * 16 + l16) * KB + q4;
+    const float* arow = ym + (mt * 16 + l16) * YR + q4;
     const float* bcol = Wtab + (size_t)q4 * Mp + nt * 16 + l16;
 #pragma unroll 8
     for (int k = 0; k < KB; k += 4) {
@@ -111,10 +120,12 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
   constexpr int NT = (NC + 31) / 32;        // 32-wide column tiles
   constexpr int TPW = (NT + 3) / 4;         // tiles per wave
   constexpr int KC = a_chunk(N);
+  constexpr int KCS = KC + 1;               // K chunk row stride (float2): lanes on distinct banks
   constexpr int XS = KC * H;                // folded X' chunk (float2)
-  constexpr int KS = 32 * KC;               // K chunk (float2)
+  constexpr int KS = 32 * KCS;              // K chunk (float2)
   constexpr int KB = (N + 31) / 32 * 32;    // Stage B contraction, zero padded
-  constexpr int YS = 32 * KB / 2;           // Ymat as float2 count (32 x KB floats)
+  constexpr int YR = ym_stride<N>();        // Ymat row stride (floats)
+  constexpr int YS = 32 * YR / 2;           // Ymat as float2 count
   constexpr int RAW = (XS + KS) > YS ? (XS + KS) : YS;
   __shared__ float2 raw[RAW];
   __shared__ float2 twf[N];                 // exp(+2 pi i m / N)
@@ -156,14 +167,14 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
       if (ky == 0 && kx == 0) v = make_float2(0.f, 0.f);  // DC only shifts U by a constant
       xs[i] = v;
     }
-    for (int i = tid; i < KS; i += kUThreads) {
+    for (int i = tid; i < 32 * KC; i += kUThreads) {
       const int m = i / KC, kk = i - m * KC;
-      ks[i] = Ktab[(size_t)(m0 + m) * N + k0 + kk];
+      ks[m * KCS + kk] = Ktab[(size_t)(m0 + m) * N + k0 + kk];
     }
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < KC; ++kk) {
-      const float2 kv = ks[l32 * KC + kk];
+      const float2 kv = ks[l32 * KCS + kk];
       const float ar = half ? -kv.y : kv.x;
       const float ai = half ? kv.x : kv.y;
 #pragma unroll
@@ -182,7 +193,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
     {
       const int m = tid & 31, grp = tid >> 5;
       for (int kk = grp; kk < KC; kk += 8) {
-        const float2 kv = ks[m * KC + kk];
+        const float2 kv = ks[m * KCS + kk];
         const float2 xv = xs[kk * H + NC];
         nacc += kv.x * xv.x - kv.y * xv.y;
       }
@@ -194,7 +205,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
   float* ym = (float*)raw;
   for (int i = tid; i < 32 * (KB - N); i += kUThreads) {
     const int r = i / (KB - N), j = N + i % (KB - N);
-    ym[r * KB + j] = 0.f;
+    ym[r * YR + j] = 0.f;
   }
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
@@ -202,21 +213,21 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int i = (v >> 2) * 8 + half * 4 + (v & 3);
-      if (kx < NC) ym[i * KB + kx] = accr[t][v];
-      if (kx >= 1 && kx < NC) ym[i * KB + NC + kx] = acci[t][v];
+      if (kx < NC) ym[i * YR + kx] = accr[t][v];
+      if (kx >= 1 && kx < NC) ym[i * YR + NC + kx] = acci[t][v];
     }
   }
   __syncthreads();
   if (tid < 32) {
     float s = 0.f;
     for (int q = 0; q < 8; ++q) s += nyq[q][tid];
-    ym[tid * KB + NC] = s;
+    ym[tid * YR + NC] = s;
   }
   __syncthreads();
   if constexpr (SPLIT) {
     const int mtiles = Mp / 32;
     float* dst = ypart + (((size_t)f * mtiles + blockIdx.x) * nsl + blockIdx.z) * 32 * KB;
-    for (int i = tid; i < 32 * KB; i += kUThreads) dst[i] = ym[i];
+    for (int i = tid; i < 32 * KB; i += kUThreads) dst[i] = ym[(i / KB) * YR + i % KB];
   } else {
     stage_b_f32<N>(g, ym, Wtab, Mp, m0, f, red);
   }
@@ -228,7 +239,8 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32_sum(GroupParams g, cons
                                                              int Mp, const float* __restrict__ ypart,
                                                              int nsl) {
   constexpr int KB = (N + 31) / 32 * 32;
-  __shared__ float ym[32 * KB];
+  constexpr int YR = ym_stride<N>();
+  __shared__ float ym[32 * YR];
   __shared__ unsigned long long red[kUThreads / 64];
   const int f = blockIdx.y;
   const FrameState st = g.st[f];
@@ -238,7 +250,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32_sum(GroupParams g, cons
   for (int i = threadIdx.x; i < 32 * KB; i += kUThreads) {
     float v = 0.f;
     for (int q = 0; q < nsl; ++q) v += src[(size_t)q * 32 * KB + i];
-    ym[i] = v;
+    ym[(i / KB) * YR + i % KB] = v;
   }
   __syncthreads();
   stage_b_f32<N>(g, ym, Wtab, Mp, blockIdx.x * 32, f, red);
@@ -472,7 +484,13 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
 // LDS and shared by all waves.  Row 0 of the split spectrum carries the
 // Nyquist column in its imaginary part, so Yi(., 0) is the Nyquist output.
 // The three products of each K step are issued pass by pass over all tiles
-// so consecutive matrix instructions never depend on each other.
+// so consecutive matrix instructions never depend on each other.  Where a
+// block's waves fit one per SIMD (N <= 256) Stage A is software pipelined:
+// the next chunk's B fragments and K' rows are loaded while the current
+// chunk's MFMAs run, and K' chunks alternate between two LDS buffers.
+// Stage B converts Y to bf16 hi/lo for up to GB row tiles at a time into
+// LDS, so every W fragment a wave loads from L2 serves 2*GB row halves (W
+// is read 2 times per frame instead of 2*MT).
 template <int N, int MT>
 __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
     k_updft_bf16x2_wide(GroupParams g, const unsigned* __restrict__ kfold,
@@ -488,7 +506,12 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   constexpr int YST = KB + 8;
   constexpr int KW = 2 * ROWS * KCS;
   constexpr int YW = 32 * YST;
-  constexpr int RAWW = KW > YW ? KW : YW;
+  // the pipelined Stage A needs registers for a second chunk of operands:
+  // used where a block's waves fit one per SIMD (N <= 256)
+  constexpr bool PIPE = NW <= 4;
+  constexpr int GB = 3 * YW * 4 <= 120000 ? 3 : 2;  // row tiles per Stage B group
+  constexpr int KWT = PIPE ? 2 * KW : KW;
+  constexpr int RAWW = KWT > GB * YW ? KWT : GB * YW;
   __shared__ __attribute__((aligned(16))) unsigned raw[RAWW];
   __shared__ float2 twf[N];
   __shared__ unsigned long long red[NW];
@@ -504,8 +527,6 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   const int iy = pk / N, ix = pk % N;
   for (int i = tid; i < N; i += NTH) twf[i] = cconj(g.tw[i]);
 
-  unsigned* ks_hi = raw;
-  unsigned* ks_lo = raw + ROWS * KCS;
   const size_t kplane = (size_t)Mp * P;
   const unsigned* Kh = kfold + (size_t)iy * 2 * kplane;
   const unsigned* Kl = Kh + kplane;
@@ -521,28 +542,52 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
 #pragma unroll
     for (int v = 0; v < 16; ++v) accr[t][v] = acci[t][v] = 0.f;
   const int nrows = mt_here * 32;
+  constexpr int NCH = P / KC;
+  constexpr int KQ = (ROWS * (KC / 4) + NTH - 1) / NTH;  // 16-byte K' copies per thread
 
-  for (int k0 = 0; k0 < P; k0 += KC) {
-    u32x4 bh[KC / 8], bl[KC / 8];
+  // B fragments of this wave's kx tile for the ky chunk at k0 (global -> registers)
+  auto load_b = [&](int k0, u32x4* dh, u32x4* dl) {
 #pragma unroll
     for (int s8 = 0; s8 < KC / 8; ++s8) {
       const int col = k0 + s8 * 8 + 4 * h;
       if (bvalid) {
-        bh[s8] = *(const u32x4*)(Xbh + (size_t)kxrow * P + col);
-        bl[s8] = *(const u32x4*)(Xbl + (size_t)kxrow * P + col);
+        dh[s8] = *(const u32x4*)(Xbh + (size_t)kxrow * P + col);
+        dl[s8] = *(const u32x4*)(Xbl + (size_t)kxrow * P + col);
       } else {
-        bh[s8] = u32x4{0u, 0u, 0u, 0u};
-        bl[s8] = u32x4{0u, 0u, 0u, 0u};
+        dh[s8] = u32x4{0u, 0u, 0u, 0u};
+        dl[s8] = u32x4{0u, 0u, 0u, 0u};
       }
     }
-    // folded K' rows of this block: 16-byte copies into LDS
-    for (int i = tid; i < nrows * (KC / 4); i += NTH) {
-      const int r = i / (KC / 4), q = i - r * (KC / 4);
-      const size_t src = (size_t)(m0 + r) * P + k0 + 4 * q;
-      *(u32x4*)(ks_hi + r * KCS + 4 * q) = *(const u32x4*)(Kh + src);
-      *(u32x4*)(ks_lo + r * KCS + 4 * q) = *(const u32x4*)(Kl + src);
+  };
+  // the block's K' rows for the ky chunk at k0: global -> registers -> LDS
+  u32x4 kh[KQ], kl[KQ];
+  auto load_k = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int i = tid + q * NTH;
+      if (i < nrows * (KC / 4)) {
+        const int r = i / (KC / 4), c4 = i - r * (KC / 4);
+        const size_t src = (size_t)(m0 + r) * P + k0 + 4 * c4;
+        kh[q] = *(const u32x4*)(Kh + src);
+        kl[q] = *(const u32x4*)(Kl + src);
+      }
     }
-    __syncthreads();
+  };
+  auto store_k = [&](unsigned* dh) {
+    unsigned* dl = dh + ROWS * KCS;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int i = tid + q * NTH;
+      if (i < nrows * (KC / 4)) {
+        const int r = i / (KC / 4), c4 = i - r * (KC / 4);
+        *(u32x4*)(dh + r * KCS + 4 * c4) = kh[q];
+        *(u32x4*)(dl + r * KCS + 4 * c4) = kl[q];
+      }
+    }
+  };
+  // Stage A products of one ky chunk: three passes (hi*hi, hi*lo, lo*hi) per tile
+  auto mma_chunk = [&](const unsigned* ks_hi, const u32x4* bh, const u32x4* bl) {
+    const unsigned* ks_lo = ks_hi + ROWS * KCS;
 #pragma unroll
     for (int s8 = 0; s8 < KC / 8; ++s8) {
       const int col = s8 * 8 + 4 * h;
@@ -574,7 +619,43 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
           acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(swap_ri(al[t])), b_h, acci[t], 0, 0, 0);
         }
     }
+  };
+
+  u32x4 bh[KC / 8], bl[KC / 8];
+  if constexpr (PIPE) {
+    // software pipeline: chunk c + 1's operands are loaded while chunk c's
+    // MFMAs run; K' chunks alternate between two LDS buffers
+    u32x4 nh[KC / 8], nl[KC / 8];
+    load_b(0, bh, bl);
+    load_k(0);
+    store_k(raw);
     __syncthreads();
+    for (int c = 0; c < NCH; ++c) {
+      const bool more = c + 1 < NCH;
+      if (more) {
+        load_b((c + 1) * KC, nh, nl);
+        load_k((c + 1) * KC);
+      }
+      mma_chunk(raw + (c & 1) * KW, bh, bl);
+      if (more) store_k(raw + ((c + 1) & 1) * KW);
+      __syncthreads();
+      if (more) {
+#pragma unroll
+        for (int s8 = 0; s8 < KC / 8; ++s8) {
+          bh[s8] = nh[s8];
+          bl[s8] = nl[s8];
+        }
+      }
+    }
+  } else {
+    for (int c = 0; c < NCH; ++c) {
+      load_b(c * KC, bh, bl);
+      load_k(c * KC);
+      store_k(raw);
+      __syncthreads();
+      mma_chunk(raw, bh, bl);
+      __syncthreads();
+    }
   }
   // kx phase of the fold; column 0 holds (Y[., 0], Y[., N/2]) and its phase is 1
   if (bvalid && kxrow > 0) {
@@ -589,64 +670,82 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
       }
   }
   const float nyq_sign = (ix & 1) ? -1.f : 1.f;  // exp(i pi p_x)
-  unsigned short* ymh = (unsigned short*)raw;
-  unsigned short* yml = ymh + 32 * YST;
-  const int ntb = 2 * (Mp / 16);
+  // Stage B in groups of up to GB row tiles: their Y (bf16 hi/lo planes) sits in
+  // LDS together, so each W fragment a wave loads serves 2 * GB row halves
+  constexpr int SLOT = 2 * 32 * YST;  // u16 elements per row tile (hi, lo planes)
+  unsigned short* ybase = (unsigned short*)raw;
+  const int nnt = Mp / 16;
   unsigned long long best = 0;
   const int l16 = lane & 15, q4 = lane >> 4;
   const unsigned short* WbL = WbT + (size_t)Mp * KB;
 #pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    if (t >= mt_here) break;
+  for (int t0 = 0; t0 < MT; t0 += GB) {
+    if (t0 >= mt_here) break;
+    const int gn = min(GB, mt_here - t0);
     __syncthreads();
-    for (int i = tid; i < 32 * (KB - N); i += NTH) {
-      const int r = i / (KB - N), c = N + i % (KB - N);
-      ymh[r * YST + c] = 0;
-      yml[r * YST + c] = 0;
-    }
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = (v >> 2) * 8 + h * 4 + (v & 3);
-      if (bvalid) {
-        const float yr = accr[t][v];
-        const unsigned a = bf16_bits(yr);
-        ymh[i * YST + kxrow] = (unsigned short)a;
-        yml[i * YST + kxrow] = (unsigned short)bf16_bits(yr - bf16_float(a));
-        const float yi = kxrow == 0 ? nyq_sign * acci[t][v] : acci[t][v];
-        const int col = NC + kxrow;  // Yi of kx, or the Nyquist output for kx = 0
-        const unsigned b = bf16_bits(yi);
-        ymh[i * YST + col] = (unsigned short)b;
-        yml[i * YST + col] = (unsigned short)bf16_bits(yi - bf16_float(b));
+    for (int t = t0; t < t0 + GB && t < MT; ++t) {
+      if (t - t0 >= gn) break;
+      unsigned short* ymh = ybase + (t - t0) * SLOT;
+      unsigned short* yml = ymh + 32 * YST;
+      for (int i = tid; i < 32 * (KB - N); i += NTH) {
+        const int r = i / (KB - N), c = N + i % (KB - N);
+        ymh[r * YST + c] = 0;
+        yml[r * YST + c] = 0;
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = (v >> 2) * 8 + h * 4 + (v & 3);
+        if (bvalid) {
+          const float yr = accr[t][v];
+          const unsigned a = bf16_bits(yr);
+          ymh[i * YST + kxrow] = (unsigned short)a;
+          yml[i * YST + kxrow] = (unsigned short)bf16_bits(yr - bf16_float(a));
+          const float yi = kxrow == 0 ? nyq_sign * acci[t][v] : acci[t][v];
+          const int col = NC + kxrow;  // Yi of kx, or the Nyquist output for kx = 0
+          const unsigned b = bf16_bits(yi);
+          ymh[i * YST + col] = (unsigned short)b;
+          yml[i * YST + col] = (unsigned short)bf16_bits(yi - bf16_float(b));
+        }
       }
     }
     __syncthreads();
-    const int mrow0 = m0 + t * 32;
-    for (int T = wave; T < ntb; T += NW) {
-      const int mt = T & 1, nt = T >> 1;
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      const unsigned short* ah_p = ymh + (mt * 16 + l16) * YST + 8 * q4;
-      const unsigned short* al_p = yml + (mt * 16 + l16) * YST + 8 * q4;
+    // this wave's 16-column W tiles nt = wave, wave + NW, ...; every row half of the group
+    for (int nt = wave; nt < nnt; nt += NW) {
+      f32x4 acc[2 * GB], acc2[2 * GB], acc3[2 * GB];
+#pragma unroll
+      for (int r = 0; r < 2 * GB; ++r) acc[r] = acc2[r] = acc3[r] = f32x4{0.f, 0.f, 0.f, 0.f};
       const unsigned short* bh_p = WbT + (size_t)(nt * 16 + l16) * KB + 8 * q4;
       const unsigned short* bl_p = WbL + (size_t)(nt * 16 + l16) * KB + 8 * q4;
-      f32x4 acc2 = {0.f, 0.f, 0.f, 0.f}, acc3 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
+#pragma unroll 2
       for (int k = 0; k < KB; k += 32) {
-        const bf16x8 a_h = as_bf(*(const u32x4*)(ah_p + k));
-        const bf16x8 a_l = as_bf(*(const u32x4*)(al_p + k));
         const bf16x8 w_h = as_bf(*(const u32x4*)(bh_p + k));
         const bf16x8 w_l = as_bf(*(const u32x4*)(bl_p + k));
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_h, acc, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_l, acc2, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, w_h, acc3, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 2 * GB; ++r) {
+          if (r < 2 * gn) {
+            const unsigned short* ah_p = ybase + (r >> 1) * SLOT + ((r & 1) * 16 + l16) * YST + 8 * q4;
+            const bf16x8 a_h = as_bf(*(const u32x4*)(ah_p + k));
+            const bf16x8 a_l = as_bf(*(const u32x4*)(ah_p + 32 * YST + k));
+            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_h, acc[r], 0, 0, 0);
+            acc2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_l, acc2[r], 0, 0, 0);
+            acc3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, w_h, acc3[r], 0, 0, 0);
+          }
+        }
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float uval = acc[v] + (acc2[v] + acc3[v]);
-        const int my = mrow0 + mt * 16 + q4 * 4 + v;
-        const int mx = nt * 16 + l16;
-        if (my < g.M && mx < g.M) {
-          const unsigned long long key = peak_key(uval, (unsigned)(my * g.M + mx));
-          best = key > best ? key : best;
+      for (int r = 0; r < 2 * GB; ++r) {
+        if (r < 2 * gn) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float uval = acc[r][v] + (acc2[r][v] + acc3[r][v]);
+            const int my = m0 + (t0 + (r >> 1)) * 32 + (r & 1) * 16 + q4 * 4 + v;
+            const int mx = nt * 16 + l16;
+            if (my < g.M && mx < g.M) {
+              const unsigned long long key = peak_key(uval, (unsigned)(my * g.M + mx));
+              best = key > best ? key : best;
+            }
+          }
         }
       }
     }

@@ -14,7 +14,9 @@
 
 namespace ccpt {
 
-constexpr int kThreads = 256;
+// 512 threads (8 waves) per block: the passes are bound by memory latency
+// and LDS, so more resident waves per CU (16 to 32) hide more of it
+constexpr int kThreads = 512;
 
 // largest divisor of N whose block of rows holds at most `budget` complex values
 constexpr int rows_per_block(int N, int budget) {
@@ -24,12 +26,12 @@ constexpr int rows_per_block(int N, int budget) {
   return best;
 }
 
-// columns per block of the column pass: at most 4096 complex values per
-// LDS buffer (16 columns of 256: the row-major X stores are 128-byte lines),
+// columns per block of the column pass: at most 2048 complex values per
+// LDS buffer (8 columns of 256: 37 KB of LDS, so four blocks share a CU),
 // no wider than the N/2+1 columns need
 constexpr int cols_per_block(int N) {
   int cb = 1;
-  while (cb * 2 * N <= 4096 && cb < N / 2) cb *= 2;
+  while (cb * 2 * N <= 2048 && cb < N / 2) cb *= 2;
   return cb;
 }
 
