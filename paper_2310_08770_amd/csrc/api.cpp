@@ -169,10 +169,10 @@ int ensure_tables(ccpt_ctx* ctx, int n) {
     if (rc) return rc;
   }
   if (split(ctx) && n >= kWideMinN) {
-    const size_t words = (size_t)n * 2 * t.Mp * xb_pitch(n);
+    const size_t words = (size_t)n * 2 * kfold_rows(t.Mp) * xb_pitch(n);
     if (hipMalloc(&t.kfold, words * sizeof(unsigned)) != hipSuccess)
       return fail(ctx, CCPT_E_NOMEM, "folded table of %zu bytes", words * sizeof(unsigned));
-    if (launch_build_kfold(t.kfold, n, ctx->o.upsample, ctx->M, ctx->c, t.Mp, nullptr))
+    if (launch_build_kfold(t.kfold, n, ctx->o.upsample, ctx->M, ctx->c, kfold_rows(t.Mp), nullptr))
       return fail(ctx, CCPT_E_HIP, "folded table launch failed");
     HIP_CHECK(ctx, hipDeviceSynchronize());
   }

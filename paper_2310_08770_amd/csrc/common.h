@@ -148,9 +148,18 @@ struct UpdftTables {
 
 // Minimum frame size of the wide split-precision kernel (and its folded table).
 constexpr int kWideMinN = 256;
+// 32-row grid tiles per block of the wide kernel.
+constexpr int kWideMT = 5;
 
-// Builds the folded split table [N][2][Mp][xb_pitch(N)] words on the device.
-int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int Mp, hipStream_t s);
+// Rows per plane of the folded table: Mp padded to whole blocks of kWideMT
+// tiles (zero rows), so every block of the wide kernel runs all its tiles.
+__host__ __device__ constexpr int kfold_rows(int Mp) {
+  return (Mp / 32 + kWideMT - 1) / kWideMT * kWideMT * 32;
+}
+
+// Builds the folded split table [N][2][rows][xb_pitch(N)] words on the device
+// (rows = kfold_rows(Mp); rows m >= M are zero).
+int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int rows, hipStream_t s);
 int launch_updft(int N, const GroupParams& g, const UpdftTables& t, hipStream_t s);
 
 // FP64 mode: reduces the peak candidates, then the upsampled DFT in FP64 on

@@ -518,8 +518,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int f = blockIdx.y;
-  const int m0 = blockIdx.x * ROWS;
-  const int mt_here = min(MT, (Mp - m0) / 32);
+  const int m0 = blockIdx.x * ROWS;  // the folded table has rows up to a whole block
   const FrameState st = g.st[f];
   if (frame_skipped(st)) return;
   unsigned pk = key_index(st.peak_key);
@@ -527,7 +526,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   const int iy = pk / N, ix = pk % N;
   for (int i = tid; i < N; i += NTH) twf[i] = cconj(g.tw[i]);
 
-  const size_t kplane = (size_t)Mp * P;
+  const size_t kplane = (size_t)kfold_rows(Mp) * P;
   const unsigned* Kh = kfold + (size_t)iy * 2 * kplane;
   const unsigned* Kl = Kh + kplane;
   const unsigned* Xbh = g.Xb + (size_t)f * 2 * NC * P;
@@ -541,16 +540,17 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   for (int t = 0; t < MT; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) accr[t][v] = acci[t][v] = 0.f;
-  const int nrows = mt_here * 32;
   constexpr int NCH = P / KC;
-  constexpr int KQ = (ROWS * (KC / 4) + NTH - 1) / NTH;  // 16-byte K' copies per thread
+  constexpr int KCOPY = ROWS * (KC / 4);                 // 16-byte K' copies per chunk
+  constexpr int KQ = (KCOPY + NTH - 1) / NTH;            // per thread
+  constexpr bool BFULL = NC % 32 == 0;                   // every wave's kx tile is full
 
   // B fragments of this wave's kx tile for the ky chunk at k0 (global -> registers)
   auto load_b = [&](int k0, u32x4* dh, u32x4* dl) {
 #pragma unroll
     for (int s8 = 0; s8 < KC / 8; ++s8) {
       const int col = k0 + s8 * 8 + 4 * h;
-      if (bvalid) {
+      if (BFULL || bvalid) {
         dh[s8] = *(const u32x4*)(Xbh + (size_t)kxrow * P + col);
         dl[s8] = *(const u32x4*)(Xbl + (size_t)kxrow * P + col);
       } else {
@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
       const int i = tid + q * NTH;
-      if (i < nrows * (KC / 4)) {
+      if (KCOPY % NTH == 0 || i < KCOPY) {
         const int r = i / (KC / 4), c4 = i - r * (KC / 4);
         const size_t src = (size_t)(m0 + r) * P + k0 + 4 * c4;
         kh[q] = *(const u32x4*)(Kh + src);
@@ -578,7 +578,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
       const int i = tid + q * NTH;
-      if (i < nrows * (KC / 4)) {
+      if (KCOPY % NTH == 0 || i < KCOPY) {
         const int r = i / (KC / 4), c4 = i - r * (KC / 4);
         *(u32x4*)(dh + r * KCS + 4 * c4) = kh[q];
         *(u32x4*)(dl + r * KCS + 4 * c4) = kl[q];
@@ -591,33 +591,30 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
 #pragma unroll
     for (int s8 = 0; s8 < KC / 8; ++s8) {
       const int col = s8 * 8 + 4 * h;
-      const bf16x8 b_h = as_bf(bh[s8]), b_l = as_bf(bl[s8]);
-      u32x4 ah[MT], al[MT];
+      // B as (re, -im) for Re(K X) and as (im, re) for Im(K X); A is used as stored
+      const bf16x8 bh_r = as_bf(neg_im(bh[s8])), bh_i = as_bf(swap_ri(bh[s8]));
+      const bf16x8 bl_r = as_bf(neg_im(bl[s8])), bl_i = as_bf(swap_ri(bl[s8]));
+      bf16x8 ah[MT], al[MT];
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        if (t < mt_here) {
-          ah[t] = *(const u32x4*)(ks_hi + (t * 32 + j) * KCS + col);
-          al[t] = *(const u32x4*)(ks_lo + (t * 32 + j) * KCS + col);
-        }
+        ah[t] = as_bf(*(const u32x4*)(ks_hi + (t * 32 + j) * KCS + col));
+        al[t] = as_bf(*(const u32x4*)(ks_lo + (t * 32 + j) * KCS + col));
       }
 #pragma unroll
-      for (int t = 0; t < MT; ++t)
-        if (t < mt_here) {
-          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(neg_im(ah[t])), b_h, accr[t], 0, 0, 0);
-          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(swap_ri(ah[t])), b_h, acci[t], 0, 0, 0);
-        }
+      for (int t = 0; t < MT; ++t) {
+        accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], bh_r, accr[t], 0, 0, 0);
+        acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], bh_i, acci[t], 0, 0, 0);
+      }
 #pragma unroll
-      for (int t = 0; t < MT; ++t)
-        if (t < mt_here) {
-          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(neg_im(ah[t])), b_l, accr[t], 0, 0, 0);
-          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(swap_ri(ah[t])), b_l, acci[t], 0, 0, 0);
-        }
+      for (int t = 0; t < MT; ++t) {
+        accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], bl_r, accr[t], 0, 0, 0);
+        acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], bl_i, acci[t], 0, 0, 0);
+      }
 #pragma unroll
-      for (int t = 0; t < MT; ++t)
-        if (t < mt_here) {
-          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(neg_im(al[t])), b_h, accr[t], 0, 0, 0);
-          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(swap_ri(al[t])), b_h, acci[t], 0, 0, 0);
-        }
+      for (int t = 0; t < MT; ++t) {
+        accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t], bh_r, accr[t], 0, 0, 0);
+        acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t], bh_i, acci[t], 0, 0, 0);
+      }
     }
   };
 
@@ -636,7 +633,11 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
         load_b((c + 1) * KC, nh, nl);
         load_k((c + 1) * KC);
       }
+      // keep the next chunk's loads ahead of this chunk's MFMAs and their LDS
+      // stores (which wait for the loads) behind them
+      __builtin_amdgcn_sched_barrier(0);
       mma_chunk(raw + (c & 1) * KW, bh, bl);
+      __builtin_amdgcn_sched_barrier(0);
       if (more) store_k(raw + ((c + 1) & 1) * KW);
       __syncthreads();
       if (more) {
@@ -658,7 +659,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
     }
   }
   // kx phase of the fold; column 0 holds (Y[., 0], Y[., N/2]) and its phase is 1
-  if (bvalid && kxrow > 0) {
+  if ((BFULL || bvalid) && kxrow > 0) {
     const float2 ph = twf[(kxrow * ix) % N];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
@@ -680,12 +681,10 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   const unsigned short* WbL = WbT + (size_t)Mp * KB;
 #pragma unroll
   for (int t0 = 0; t0 < MT; t0 += GB) {
-    if (t0 >= mt_here) break;
-    const int gn = min(GB, mt_here - t0);
+    const int gn = min(GB, MT - t0);  // a constant once the loop is unrolled
     __syncthreads();
 #pragma unroll
     for (int t = t0; t < t0 + GB && t < MT; ++t) {
-      if (t - t0 >= gn) break;
       unsigned short* ymh = ybase + (t - t0) * SLOT;
       unsigned short* yml = ymh + 32 * YST;
       for (int i = tid; i < 32 * (KB - N); i += NTH) {
@@ -696,7 +695,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int i = (v >> 2) * 8 + h * 4 + (v & 3);
-        if (bvalid) {
+        if (BFULL || bvalid) {
           const float yr = accr[t][v];
           const unsigned a = bf16_bits(yr);
           ymh[i * YST + kxrow] = (unsigned short)a;
@@ -762,8 +761,8 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
 // Folded split table for the wide kernel: K'_p[m, ky] = phi_ky(p + (m - c)/u)
 // for every integer peak row p, as bf16 hi/lo words (re | im << 16),
 // [N][2][Mp][xb_pitch(N)], computed in FP64 with exactly reduced phases.
-__global__ void k_build_kfold(unsigned* __restrict__ out, int N, int u, int M, int c, int Mp, int P) {
-  const size_t plane = (size_t)Mp * P;
+__global__ void k_build_kfold(unsigned* __restrict__ out, int N, int u, int M, int c, int rows, int P) {
+  const size_t plane = (size_t)rows * P;
   const size_t total = (size_t)N * plane;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -796,8 +795,8 @@ __global__ void k_build_kfold(unsigned* __restrict__ out, int N, int u, int M, i
   }
 }
 
-int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int Mp, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_kfold, dim3(4096), dim3(256), 0, s, out, N, u, M, c, Mp, xb_pitch(N));
+int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_kfold, dim3(4096), dim3(256), 0, s, out, N, u, M, c, rows, xb_pitch(N));
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -819,7 +818,7 @@ static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
   } else if (t.precision == CCPT_PREC_BF16X2) {
     if (!g.Xb) return -1;
     if constexpr (N >= kWideMinN) {
-      constexpr int MT = 5;
+      constexpr int MT = kWideMT;
       constexpr int NW = (N / 2 + 31) / 32;
       if (!t.kfold) return -1;
       hipLaunchKernelGGL((k_updft_bf16x2_wide<N, MT>), dim3((mtiles + MT - 1) / MT, g.count),
