@@ -97,7 +97,7 @@ enum ccpt_dtype { CCPT_U16 = 0, CCPT_F32 = 1, CCPT_F64 = 2 };
 
 /* stage ids of ccpt_stage_times */
 enum ccpt_stage {
-  CCPT_STAGE_INIT = 0,     /* per-frame state reset */
+  CCPT_STAGE_INIT = 0,     /* reserved (frame states are reset by the Newton stage) */
   CCPT_STAGE_ROWS_FWD = 1, /* prologue + row r2c FFTs */
   CCPT_STAGE_COLS = 2,     /* column FFTs, cross-power spectrum, inverse column FFTs */
   CCPT_STAGE_ROWS_INV = 3, /* row c2r FFTs + integer peak */

@@ -99,6 +99,11 @@ struct ccpt_ctx {
   // FP32 split-K partials of small launches
   void* ypart = nullptr;
   size_t ypart_cap = 0;
+  // per-frame states of a chunk: kept in the initial state between chunks by
+  // the Newton kernel; re-initialised after a failed launch
+  FrameState* st_buf = nullptr;
+  size_t st_cap = 0;
+  bool st_dirty = true;
   // errors
   int last_code = CCPT_OK;
   std::string last_msg;
@@ -210,9 +215,8 @@ size_t split_words(int n) { return (size_t)2 * (n / 2) * xb_pitch(n); }
 
 size_t frame_ws_bytes(int n, int precision) {
   if (precision == CCPT_PREC_FP64)
-    return 2 * spec_elems(n) * sizeof(double2) + (size_t)(n / row_block64(n)) * sizeof(PeakCand) +
-           sizeof(FrameState);
-  size_t b = 2 * spec_elems(n) * sizeof(float2) + sizeof(FrameState);
+    return 2 * spec_elems(n) * sizeof(double2) + (size_t)(n / row_block64(n)) * sizeof(PeakCand);
+  size_t b = 2 * spec_elems(n) * sizeof(float2);
   if (precision == CCPT_PREC_BF16X2) b += split_words(n) * sizeof(unsigned);
   return b;
 }
@@ -240,7 +244,7 @@ void carve(ccpt_ctx* ctx, int n, int chunk, GroupParams& g) {
     g.T64 = (double2*)ctx->ws;
     g.X64 = g.T64 + spec * chunk;
     g.cand = (PeakCand*)(g.X64 + spec * chunk);
-    g.st = (FrameState*)(g.cand + (size_t)(n / row_block64(n)) * chunk);
+    g.st = ctx->st_buf;
     return;
   }
   g.T = (float2*)ctx->ws;
@@ -251,7 +255,8 @@ void carve(ccpt_ctx* ctx, int n, int chunk, GroupParams& g) {
     g.Xb = (unsigned*)p;
     p += split_words(n) * sizeof(unsigned) * chunk;
   }
-  g.st = (FrameState*)p;
+  (void)p;
+  g.st = ctx->st_buf;
 }
 
 int check_image(ccpt_ctx* ctx, const void* data, int ny, int nx, int pitch, int dtype,
@@ -353,6 +358,7 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
     carve(ctx, n, chunk, g);
     const size_t yb = split_partials_bytes(ctx, n, g.count);
     g.ypart = (yb && yb <= ctx->ypart_cap) ? (float*)ctx->ypart : nullptr;
+    ctx->st_dirty = true;  // until this chunk's Newton launch has gone in
     if ((fp64(ctx) ? launch_xcorr64(n, g, s, mark) : launch_xcorr(n, g, s, mark)))
       return fail(ctx, CCPT_E_HIP, "correlation launch failed");
     mark(CCPT_STAGE_UPDFT, 1);
@@ -363,6 +369,7 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
     if (launch_newton(n, g, step_limit(ctx), s))
       return fail(ctx, CCPT_E_HIP, "Newton launch failed");
     mark(CCPT_STAGE_NEWTON, 0);
+    ctx->st_dirty = false;
   }
   return CCPT_OK;
 }
@@ -462,6 +469,28 @@ int ensure_buf(ccpt_ctx* ctx, void*& p, size_t& cap, size_t bytes) {
     return fail(ctx, CCPT_E_NOMEM, "buffer of %zu bytes", bytes);
   }
   cap = bytes;
+  return CCPT_OK;
+}
+
+// The frame-state buffer for chunks of up to `count` frames, in the initial
+// state (a new buffer, or one left dirty by a failed launch, is initialised on
+// stream s before any kernel of the call uses it).
+int ensure_state(ccpt_ctx* ctx, size_t count, hipStream_t s) {
+  if (count > ctx->st_cap) {
+    drop_graphs(ctx);
+    size_t cap = ctx->st_cap;
+    void* p = ctx->st_buf;
+    int rc = ensure_buf(ctx, p, cap, count * sizeof(FrameState));
+    ctx->st_buf = (FrameState*)p;
+    ctx->st_cap = cap / sizeof(FrameState);
+    if (rc) return rc;
+    ctx->st_dirty = true;
+  }
+  if (ctx->st_dirty) {
+    if (launch_init_state(ctx->st_buf, (int)ctx->st_cap, s))
+      return fail(ctx, CCPT_E_HIP, "state initialisation launch failed");
+    ctx->st_dirty = false;
+  }
   return CCPT_OK;
 }
 
@@ -573,6 +602,7 @@ void ccpt_destroy(ccpt_ctx* ctx) {
   if (ctx->gsmall) (void)hipFree(ctx->gsmall);
   if (ctx->acc_buf) (void)hipFree(ctx->acc_buf);
   if (ctx->ypart) (void)hipFree(ctx->ypart);
+  if (ctx->st_buf) (void)hipFree(ctx->st_buf);
   if (ctx->h_small) (void)hipHostFree(ctx->h_small);
   delete ctx;
 }
@@ -687,6 +717,11 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
     ws_need = std::max(ws_need, frame_ws_bytes(nn, ctx->o.precision) * (size_t)chunk + 256);
   }
   rc = ensure_ws(ctx, ws_need);
+  if (rc) return rc;
+  size_t st_need = 0;
+  for (size_t gi = 0; gi < sig.size(); gi += 2)
+    st_need = std::max(st_need, (size_t)std::min(sig[gi + 1], chunk_for(ctx, sig[gi])));
+  rc = ensure_state(ctx, st_need, s);
   if (rc) return rc;
   size_t ypart_need = 0;
   for (size_t gi = 0; gi < sig.size(); gi += 2) {

@@ -20,7 +20,10 @@ struct FrameDesc {
   int ref_id;         // reference index
 };
 
-// Per-frame scratch kept in the workspace between the kernels of one chunk.
+// Per-frame scratch passed between the kernels of one chunk.  It lives in a
+// buffer of its own that starts in the initial state (below) and is returned
+// to it by the Newton kernel, the last of a chunk, for every frame: no reset
+// launch is needed per chunk.
 struct FrameState {
   unsigned long long peak_key;  // integer-lag maximum: value key << 32 | ~flat index
   unsigned long long grid_key;  // upsampled-grid maximum, same encoding
@@ -119,8 +122,12 @@ struct Marker {
 
 // ---- launchers (defined in the .hip files) -------------------------------
 
-// Stage 0-3: state reset, forward 2-D r2c FFT with the prologue, cross-power
-// spectrum, inverse 2-D c2r FFT and the integer-peak search.
+// Puts count frame states in the initial state (keys 0, amin all ones, amax
+// and flags 0).
+int launch_init_state(FrameState* st, int count, hipStream_t s);
+
+// Stages 1-3: forward 2-D r2c FFT with the prologue, cross-power spectrum,
+// inverse 2-D c2r FFT and the integer-peak search.
 int launch_xcorr(int N, const GroupParams& g, hipStream_t s, const Marker& mark);
 
 // Forward 2-D r2c FFT of n images (pitch in elements) into spec

@@ -70,6 +70,18 @@ __device__ __forceinline__ void split_pair(float2 v, unsigned& hi, unsigned& lo)
   lo = lr | (lm << 16);
 }
 
+// LDS layout of an FFT sequence: element i sits at lds_idx(i), with one
+// unused slot after every 2^kLdsPadShift elements when the shift is nonzero,
+// so the strided writes of the early Stockham stages spread over the LDS
+// banks.  lds_len(n) slots hold a sequence of n elements.
+constexpr int kLdsPadShift = 4;
+__host__ __device__ constexpr int lds_idx(int i) {
+  return kLdsPadShift ? i + (i >> kLdsPadShift) : i;
+}
+__host__ __device__ constexpr int lds_len(int n) {
+  return kLdsPadShift ? n + (n >> kLdsPadShift) : n;
+}
+
 constexpr int fft_radix(int L, int stage) {
   int i = 0;
   while (L % 3 == 0) {
@@ -166,7 +178,7 @@ __device__ __forceinline__ void fft_stage(const C* __restrict__ src, C* __restri
     C* out = dst + q * stride;
     C v[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t) v[t] = in[j + t * B];
+    for (int t = 0; t < R; ++t) v[t] = in[lds_idx(j + t * B)];
     const int k = j % NS;
     if (NS > 1) {
       // twiddle exp(SIGN * 2 pi i t k / (NS R)) = tw[t k NTW / (NS R)] (conj for SIGN > 0)
@@ -181,7 +193,7 @@ __device__ __forceinline__ void fft_stage(const C* __restrict__ src, C* __restri
     dft<R, SIGN>(v);
     const int base = (j / NS) * NS * R + k;
 #pragma unroll
-    for (int t = 0; t < R; ++t) out[base + t * NS] = v[t];
+    for (int t = 0; t < R; ++t) out[lds_idx(base + t * NS)] = v[t];
   }
 }
 

@@ -295,14 +295,32 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
   const FrameState st = g.st[f];
   const FrameDesc d = g.desc[g.first + f];
   ccpt_result* out = g.out + d.out_idx;
+  // the state goes back to its initial value for the next chunk once every
+  // thread has read it
+  auto reset_state = [&]() {
+    __syncthreads();
+    if (tid == 0) {
+      FrameState z;
+      z.peak_key = 0;
+      z.grid_key = 0;
+      z.amin = 0xFFFFFFFFu;
+      z.amax = 0;
+      z.flags = 0;
+      z.pad = 0;
+      g.st[f] = z;
+    }
+  };
   if (st.flags & CCPT_ST_NONFINITE) {
     if (tid == 0) write_special(out, CCPT_ST_NONFINITE);
+    reset_state();
     return;
   }
   if (st.amin == st.amax) {
     if (tid == 0) write_special(out, CCPT_ST_FLAT);
+    reset_state();
     return;
   }
+  reset_state();
   unsigned pk = key_index(st.peak_key);
   if (pk >= (unsigned)(N * N)) pk = 0;
   int py = pk / N, px = pk % N;

@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, d
                                                        const C* __restrict__ gtw) {
   using R = real_t<C>;
   constexpr int L = N / 2, H = N / 2 + 1;
-  constexpr int LS = L + 1;  // padded row stride in LDS
+  constexpr int LS = lds_len(L) + 1;  // row stride in LDS
   const R eps = (R)eps_in;
   __shared__ C tw[N];
   __shared__ C bufA[RPB * LS];
@@ -166,14 +166,14 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, d
       const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        bufA[r * LS + 4 * q + e] = mkc<C>(pro((R)(w[e] & 0xFFFFu)), pro((R)(w[e] >> 16)));
+        bufA[r * LS + lds_idx(4 * q + e)] = mkc<C>(pro((R)(w[e] & 0xFFFFu)), pro((R)(w[e] >> 16)));
     }
   } else if (vec32) {
     for (int i = tid; i < RPB * (N / 4); i += kThreads) {
       const int r = i / (N / 4), q = i - r * (N / 4);
       const float4 v = *(const float4*)((const float*)data + (long)(y0 + r) * pitch + 4 * q);
-      bufA[r * LS + 2 * q] = mkc<C>(pro((R)v.x), pro((R)v.y));
-      bufA[r * LS + 2 * q + 1] = mkc<C>(pro((R)v.z), pro((R)v.w));
+      bufA[r * LS + lds_idx(2 * q)] = mkc<C>(pro((R)v.x), pro((R)v.y));
+      bufA[r * LS + lds_idx(2 * q + 1)] = mkc<C>(pro((R)v.z), pro((R)v.w));
     }
   } else {
     for (int i = tid; i < RPB * L; i += kThreads) {
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, d
       const long idx = (long)(y0 + r) * pitch + 2 * c;
       const R a0 = pro(load_px<R>(data, dtype, idx));
       const R a1 = pro(load_px<R>(data, dtype, idx + 1));
-      bufA[r * LS + c] = mkc<C>(a0, a1);
+      bufA[r * LS + lds_idx(c)] = mkc<C>(a0, a1);
     }
   }
   if (st) {
@@ -213,8 +213,8 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, d
   const R half = R(0.5);
   for (int i = tid; i < RPB * H; i += kThreads) {
     const int k = i / RPB, r = i - k * RPB;
-    const C zk = z[r * LS + (k == L ? 0 : k)];
-    const C zc = cconj(z[r * LS + (k == 0 ? 0 : L - k)]);
+    const C zk = z[r * LS + lds_idx(k == L ? 0 : k)];
+    const C zc = cconj(z[r * LS + lds_idx(k == 0 ? 0 : L - k)]);
     const C e = cscale(cadd(zk, zc), half);
     const C d = csub(zk, zc);
     const C o = mkc<C>(half * d.y, -half * d.x);  // d / (2i)
@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
                                                    unsigned* __restrict__ Xb,
                                                    C* __restrict__ spec, long spec_stride,
                                                    const C* __restrict__ gtw) {
-  constexpr int H = N / 2 + 1, S = N + 1, NC = N / 2;
+  constexpr int H = N / 2 + 1, S = lds_len(N) + 1, NC = N / 2;
   constexpr int CS = CB + 1;  // column slots: CB regular + the Nyquist slot of block 0
   const C zero = mkc<C>(0, 0);
   __shared__ C tw[N];
@@ -260,13 +260,13 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
     for (int i = tid; i < N * nseq; i += kThreads) {
       const int y = i / nseq, c = i - y * nseq;
       const int kx = col_of(c);
-      bufA[c * S + y] = kx >= 0 ? inp[(size_t)y * H + kx] : mkc<C>(0, 0);
+      bufA[c * S + lds_idx(y)] = kx >= 0 ? inp[(size_t)y * H + kx] : mkc<C>(0, 0);
     }
   } else {
     for (int i = tid; i < N * nseq; i += kThreads) {
       const int c = i / N, y = i - c * N;
       const int kx = col_of(c);
-      bufA[c * S + y] = kx >= 0 ? Tf[(size_t)kx * N + y] : mkc<C>(0, 0);
+      bufA[c * S + lds_idx(y)] = kx >= 0 ? Tf[(size_t)kx * N + y] : mkc<C>(0, 0);
     }
   }
   __syncthreads();
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
     for (int i = tid; i < N * nseq; i += kThreads) {
       const int c = i / N, y = i - c * N;
       const int kx = col_of(c);
-      if (kx >= 0) Tf[(size_t)kx * N + y] = r[c * S + y];
+      if (kx >= 0) Tf[(size_t)kx * N + y] = r[c * S + lds_idx(y)];
     }
   } else {
     C* r = fft_lds<N, -1, N>(bufA, bufB, nseq, S, tw);
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
         const int y = i / nseq, c = i - y * nseq;
         const int kx = col_of(c);
         if (kx >= 0) {
-          C v = r[c * S + y];
+          C v = r[c * S + lds_idx(y)];
           if (KIND == COL_FWD_CONJ) v.y = -v.y;
           out[(size_t)y * H + kx] = v;
         }
@@ -297,11 +297,11 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
         const int y = i / nseq, c = i - y * nseq;
         const int kx = col_of(c);
         if (kx >= 0) {
-          const C v = cmul(r[c * S + y], R[(size_t)y * H + kx]);
+          const C v = cmul(r[c * S + lds_idx(y)], R[(size_t)y * H + kx]);
           Xf[(size_t)y * H + kx] = v;
-          r[c * S + y] = v;
+          r[c * S + lds_idx(y)] = v;
         } else {
-          r[c * S + y] = zero;
+          r[c * S + lds_idx(y)] = zero;
         }
       }
       __syncthreads();
@@ -320,10 +320,10 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
           const int kx = c0 + c;
           float2 v = make_float2(0.f, 0.f);
           if (y < N) {
-            v = r[c * S + y];
+            v = r[c * S + lds_idx(y)];
             if (kx == 0) {
               if (y == 0) v.x = 0.f;
-              const float2 nq = r[CB * S + y];
+              const float2 nq = r[CB * S + lds_idx(y)];
               v = make_float2(v.x - nq.y, v.y + nq.x);  // + i * X[y, N/2]
             }
           }
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
       for (int i = tid; i < N * nseq; i += kThreads) {
         const int c = i / N, y = i - c * N;
         const int kx = col_of(c);
-        if (kx >= 0) Tf[(size_t)kx * N + y] = q[c * S + y];
+        if (kx >= 0) Tf[(size_t)kx * N + y] = q[c * S + lds_idx(y)];
       }
     }
   }
@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
   using R = real_t<C>;
   constexpr bool FP64 = sizeof(C) != sizeof(float2);
   constexpr int L = N / 2, H = N / 2 + 1;
-  constexpr int LS = L + 1;
+  constexpr int LS = lds_len(L) + 1;
   __shared__ C tw[N];
   __shared__ C raw[RPB * H];
   __shared__ C bufA[RPB * LS];
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
     const C xc = cconj(raw[r * H + L - k]);
     const C e = cscale(cadd(xk, xc), half);
     const C o = cmul(cscale(csub(xk, xc), half), cconj(tw[k]));
-    bufA[r * LS + k] = mkc<C>(e.x - o.y, e.y + o.x);  // e + i o
+    bufA[r * LS + lds_idx(k)] = mkc<C>(e.x - o.y, e.y + o.x);  // e + i o
   }
   __syncthreads();
   C* z = fft_lds<L, +1, N>(bufA, bufB, RPB, LS, tw);
@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
     unsigned long long best = 0;
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
-      const C v = z[r * LS + n];
+      const C v = z[r * LS + lds_idx(n)];
       const unsigned flat = (unsigned)((y0 + r) * N + 2 * n);
       unsigned long long k0 = peak_key(v.x, flat);
       unsigned long long k1 = peak_key(v.y, flat + 1);
@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
     };
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
-      const C v = z[r * LS + n];
+      const C v = z[r * LS + lds_idx(n)];
       const unsigned flat = (unsigned)((y0 + r) * N + 2 * n);
       take(v.x, flat);
       take(v.y, flat + 1);
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
     float* out = img + (size_t)f * N * N + (size_t)y0 * N;
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
-      const C v = z[r * LS + n];
+      const C v = z[r * LS + lds_idx(n)];
       out[r * N + 2 * n] = v.x * scale;
       out[r * N + 2 * n + 1] = v.y * scale;
     }
@@ -456,9 +456,6 @@ template <int N>
 static int xcorr_n(const GroupParams& g, hipStream_t s, const Marker& mark) {
   constexpr int RPB = row_block(N);
   constexpr int CB = cols_per_block(N);
-  mark(CCPT_STAGE_INIT, 1);
-  hipLaunchKernelGGL(k_init_state, dim3((g.count + 255) / 256), dim3(256), 0, s, g.st, g.count);
-  mark(CCPT_STAGE_INIT, 0);
   ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0};
   mark(CCPT_STAGE_ROWS_FWD, 1);
   hipLaunchKernelGGL((k_rows_fwd<N, RPB, float2>), dim3(N / RPB, g.count), dim3(kThreads), 0, s,
@@ -480,9 +477,6 @@ template <int N>
 static int xcorr64_n(const GroupParams& g, hipStream_t s, const Marker& mark) {
   constexpr int RPB = row_block64(N);
   constexpr int CB = cols_per_block64(N);
-  mark(CCPT_STAGE_INIT, 1);
-  hipLaunchKernelGGL(k_init_state, dim3((g.count + 255) / 256), dim3(256), 0, s, g.st, g.count);
-  mark(CCPT_STAGE_INIT, 0);
   ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0};
   mark(CCPT_STAGE_ROWS_FWD, 1);
   hipLaunchKernelGGL((k_rows_fwd<N, RPB, double2>), dim3(N / RPB, g.count), dim3(kThreads), 0, s,
@@ -562,6 +556,12 @@ int launch_xcorr(int N, const GroupParams& g, hipStream_t s, const Marker& mark)
 #undef CASE
   }
   return -2;
+}
+
+int launch_init_state(FrameState* st, int count, hipStream_t s) {
+  if (count <= 0) return 0;
+  hipLaunchKernelGGL(k_init_state, dim3((count + 255) / 256), dim3(256), 0, s, st, count);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_xcorr64(int N, const GroupParams& g, hipStream_t s, const Marker& mark) {
