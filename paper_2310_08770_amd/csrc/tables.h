@@ -97,9 +97,12 @@ inline HostTables build_tables(int n, int u, int M, int c, int precision) {
   float2* K = (float2*)t.ky.data();
   for (size_t i = 0; i < (size_t)Mp * n; ++i) K[i] = make_float2((float)kr[i], (float)ki[i]);
   if (precision == CCPT_PREC_FP32) {
+    // Stage B operand, transposed W^T[mx][j] (FP32, [Mp][Kb]): a lane reads its
+    // K values as contiguous 16-byte runs
     t.wb.resize((size_t)Kb * Mp * sizeof(float));
     float* W = (float*)t.wb.data();
-    for (size_t i = 0; i < (size_t)Kb * Mp; ++i) W[i] = (float)w[i];
+    for (int mx = 0; mx < Mp; ++mx)
+      for (int j = 0; j < Kb; ++j) W[(size_t)mx * Kb + j] = (float)w[(size_t)j * Mp + mx];
   } else {
     // Stage B operand, transposed W^T[mx][j] as bf16, hi plane then lo plane:
     // [2][Mp][Kb] uint16

@@ -58,19 +58,23 @@ constexpr int a_chunk(int N) {
   return best;
 }
 
-// Row stride (floats) of the FP32 path's Ymat in LDS: KB + 4, so the 16
-// rows read by one Stage B MFMA fall in 16 different bank groups.
+// Row stride (floats) of the FP32 path's Ymat in LDS: KB + 1, so the 16 rows
+// and 4 lane groups (16 floats apart) of one Stage B MFMA read fall in
+// distinct banks.
 template <int N>
 constexpr int ym_stride() {
-  return (N + 31) / 32 * 32 + 4;
+  return (N + 31) / 32 * 32 + 1;
 }
 
 // Stage B of the FP32 path for one 32-row tile: U[32][Mp] = ym[32][KB] x
 // W[KB][Mp] on 16x16x4 tiles, then the tile's grid maximum merged into the
-// frame's key.  ym is in LDS (row stride ym_stride); every thread of the
-// block calls this.
+// frame's key.  ym is in LDS (row stride ym_stride); W comes transposed
+// ([Mp][KB]).  Within each 64-wide block of K, lane group q4 takes the 16
+// consecutive k = 16 q4 + i over the block's 16 MFMA steps (the same k for
+// A and B), so a lane loads its W values as four 16-byte runs per block.
+// Every thread of the block calls this.
 template <int N>
-__device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* __restrict__ Wtab,
+__device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* __restrict__ WtT,
                             int Mp, int m0, int f, unsigned long long* red) {
   constexpr int KB = (N + 31) / 32 * 32;
   constexpr int YR = ym_stride<N>();
@@ -81,11 +85,36 @@ __device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* 
   for (int T = wave; T < ntb; T += 4) {
     const int mt = T & 1, nt = T >> 1;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const float* arow = ym + (mt * 16 + l16) * YR + q4;
-    const float* bcol = Wtab + (size_t)q4 * Mp + nt * 16 + l16;
-#pragma unroll 8
-    for (int k = 0; k < KB; k += 4) {
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k], bcol[(size_t)k * Mp], acc, 0, 0, 0);
+    const float* arow = ym + (mt * 16 + l16) * YR + 16 * q4;
+    const float* bcol = WtT + (size_t)(nt * 16 + l16) * KB + 16 * q4;
+    // KB is a multiple of 32: whole 64-wide blocks, then at most one of 32
+    for (int k0 = 0; k0 < KB; k0 += 64) {
+      if (k0 + 64 <= KB) {
+        float4 w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = *(const float4*)(bcol + k0 + 4 * i);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i], w[i].x, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i + 1], w[i].y, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i + 2], w[i].z, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i + 3], w[i].w, acc, 0, 0, 0);
+        }
+      } else {
+        // last 32 of K: lane group q4 takes k = k0 + 8 q4 + i
+        const float* ar = arow - 8 * q4;
+        const float* bc = bcol - 8 * q4;
+        float4 w[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) w[i] = *(const float4*)(bc + k0 + 4 * i);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i], w[i].x, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i + 1], w[i].y, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i + 2], w[i].z, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i + 3], w[i].w, acc, 0, 0, 0);
+        }
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -108,7 +137,7 @@ __device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* 
 
 // ---------------------------------------------------------------- FP32
 // K table: float2 [Mp][N]  (K[m][ky] = phi_ky((m - c)/u))
-// W table: float  [Kb][Mp], Kb = N rounded up to 32 (zero rows past N)
+// W table: float  [Mp][Kb] (transposed), Kb = N rounded up to 32 (zero columns past N)
 // SPLIT (few frames, latency): blockIdx.z is one of `nsl` ky slices; the
 // block stores its partial Ymat to `ypart` and k_updft_f32_sum finishes.
 template <int N, bool SPLIT>
@@ -247,10 +276,24 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32_sum(GroupParams g, cons
   if (frame_skipped(st)) return;
   const int mtiles = Mp / 32;
   const float* src = ypart + ((size_t)f * mtiles + blockIdx.x) * nsl * 32 * KB;
-  for (int i = threadIdx.x; i < 32 * KB; i += kUThreads) {
-    float v = 0.f;
-    for (int q = 0; q < nsl; ++q) v += src[(size_t)q * 32 * KB + i];
-    ym[(i / KB) * YR + i % KB] = v;
+  // every element a thread owns is loaded at once per slice (the partials
+  // come from other XCDs: one round trip per slice, not per element); each
+  // element is summed over the slices in order
+  constexpr int PER = 32 * KB / kUThreads;  // KB is a multiple of 32
+  float v[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) v[e] = 0.f;
+  for (int q = 0; q < nsl; ++q) {
+    float p[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) p[e] = src[(size_t)q * 32 * KB + threadIdx.x + e * kUThreads];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) v[e] += p[e];
+  }
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int i = threadIdx.x + e * kUThreads;
+    ym[(i / KB) * YR + i % KB] = v[e];
   }
   __syncthreads();
   stage_b_f32<N>(g, ym, Wtab, Mp, blockIdx.x * 32, f, red);
