@@ -104,6 +104,9 @@ struct ccpt_ctx {
   FrameState* st_buf = nullptr;
   size_t st_cap = 0;
   bool st_dirty = true;
+  // partial Newton models of small launches
+  void* nparts = nullptr;
+  size_t nparts_cap = 0;
   // errors
   int last_code = CCPT_OK;
   std::string last_msg;
@@ -358,6 +361,7 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
     carve(ctx, n, chunk, g);
     const size_t yb = split_partials_bytes(ctx, n, g.count);
     g.ypart = (yb && yb <= ctx->ypart_cap) ? (float*)ctx->ypart : nullptr;
+    g.nparts = (double*)ctx->nparts;
     ctx->st_dirty = true;  // until this chunk's Newton launch has gone in
     if ((fp64(ctx) ? launch_xcorr64(n, g, s, mark) : launch_xcorr(n, g, s, mark)))
       return fail(ctx, CCPT_E_HIP, "correlation launch failed");
@@ -486,6 +490,11 @@ int ensure_state(ccpt_ctx* ctx, size_t count, hipStream_t s) {
     if (rc) return rc;
     ctx->st_dirty = true;
   }
+  if (!ctx->nparts) {
+    const size_t bytes = (size_t)kNewtonSplitMax * kNewtonParts * kNewtonCoef * sizeof(double);
+    int rc = ensure_buf(ctx, ctx->nparts, ctx->nparts_cap, bytes);
+    if (rc) return rc;
+  }
   if (ctx->st_dirty) {
     if (launch_init_state(ctx->st_buf, (int)ctx->st_cap, s))
       return fail(ctx, CCPT_E_HIP, "state initialisation launch failed");
@@ -603,6 +612,7 @@ void ccpt_destroy(ccpt_ctx* ctx) {
   if (ctx->acc_buf) (void)hipFree(ctx->acc_buf);
   if (ctx->ypart) (void)hipFree(ctx->ypart);
   if (ctx->st_buf) (void)hipFree(ctx->st_buf);
+  if (ctx->nparts) (void)hipFree(ctx->nparts);
   if (ctx->h_small) (void)hipHostFree(ctx->h_small);
   delete ctx;
 }

@@ -65,12 +65,20 @@ struct GroupParams {
                           // [count][Mp/32][slices][32][N rounded up to 32]
   // FP64 mode (all null otherwise): T and X in double2, the per-row-block
   // peak candidates [count][N / row_block64(N)], twiddles in FP64
+  double* nparts;         // Newton partial model coefficients of small launches, or
+                          // null: [count][kNewtonParts][kNewtonCoef] doubles
   double eps64;           // CC-SN offset (FP64 mode)
   double2* T64;
   double2* X64;
   PeakCand* cand;
   const double2* tw64;
 };
+
+// Launches of fewer than kNewtonSplitMax frames build the first Newton model
+// over kNewtonParts blocks per frame (ky ranges), for latency.
+constexpr int kNewtonSplitMax = 64;
+constexpr int kNewtonParts = 8;
+constexpr int kNewtonCoef = 36;  // Taylor coefficients of the degree-7 model
 
 // Small FP32 launches (fewer than kSplitMaxBlocks row tiles in all) split the
 // Stage A contraction over kSplitSlices ky slices for latency.

@@ -39,6 +39,7 @@ namespace ccpt {
 constexpr int kNThreads = 512;
 constexpr int kOrder = 7;                               // K
 constexpr int kCoef = (kOrder + 1) * (kOrder + 2) / 2;  // pairs with n + m <= K
+static_assert(kCoef == kNewtonCoef, "model size");
 constexpr double kModelRadius = 0.02;                   // px
 constexpr int kMaxPasses = 3;
 
@@ -104,15 +105,18 @@ struct ModelSplit {
   static constexpr int QM = (kOrder + S) / S;
 };
 
-// One pass: the model coefficients around (sy, sx) into coef (LDS).  CX is
-// the spectrum's element type (float2, or double2 in FP64 mode).
+// One pass: the model coefficients around (sy, sx) into coef (LDS), from
+// the spectrum rows ky_lo <= ky < ky_hi (all rows: the full model; a range:
+// its share, the coefficients being linear in the spectrum).  CX is the
+// spectrum's element type (float2, or double2 in FP64 mode).
 template <int N, typename CX>
 __device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, double2* phy,
                             double* ay, double (*red)[kOrder + 1][kOrder + 1],
-                            double (*nred)[2 * (kOrder + 1)], double* coef) {
+                            double (*nred)[2 * (kOrder + 1)], double* coef, int ky_lo = 0,
+                            int ky_hi = N) {
   using MS = ModelSplit<N>;
   constexpr int H = N / 2 + 1;
-  constexpr int NC = MS::NC, S = MS::S, SEG = MS::SEG, QM = MS::QM;
+  constexpr int NC = MS::NC, S = MS::S, QM = MS::QM;
   const double pi = 3.14159265358979323846;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int ky = tid; ky < N; ky += kNThreads) {
@@ -146,7 +150,8 @@ __device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, dou
 #pragma unroll
   for (int n = 0; n <= kOrder; ++n) M[n] = make_double2(0.0, 0.0);
   if (kx < NC) {
-    const int y0 = seg * SEG, y1 = min(N, y0 + SEG);
+    const int segl = (ky_hi - ky_lo + S - 1) / S;  // SEG for the full range
+    const int y0 = ky_lo + seg * segl, y1 = min(ky_hi, y0 + segl);
     const CX* col = Xf + kx;
 #pragma unroll 4
     for (int ky = y0; ky < y1; ++ky) {
@@ -217,7 +222,7 @@ __device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, dou
   double2 Mn[kOrder + 1];
 #pragma unroll
   for (int n = 0; n <= kOrder; ++n) Mn[n] = make_double2(0.0, 0.0);
-  for (int ky = tid; ky < N; ky += kNThreads) {
+  for (int ky = ky_lo + tid; ky < ky_hi; ky += kNThreads) {
     const CX xf = Xf[(size_t)ky * H + NC];
     if (2 * ky == N) {
 #pragma unroll
@@ -282,8 +287,50 @@ __device__ void write_special(ccpt_result* out, unsigned status) {
   *out = r;
 }
 
+// Integer peak (py, px) and grid estimate (dgy, dgx) of a frame from its state.
+template <int N>
+__device__ void grid_seed(const GroupParams& g, const FrameState& st, int& py, int& px,
+                          double& dgy, double& dgx) {
+  unsigned pk = key_index(st.peak_key);
+  if (pk >= (unsigned)(N * N)) pk = 0;
+  py = pk / N;
+  px = pk % N;
+  if (2 * py >= N) py -= N;
+  if (2 * px >= N) px -= N;
+  unsigned gk = key_index(st.grid_key);
+  if (gk >= (unsigned)(g.M * g.M)) gk = (unsigned)(g.c * g.M + g.c);
+  const int my = gk / g.M, mx = gk % g.M;
+  dgy = py + (double)(my - g.c) / g.u;
+  dgx = px + (double)(mx - g.c) / g.u;
+}
+
+// Small launches: block b of frame f builds the first model's share of the
+// spectrum rows b N / nb <= ky < (b + 1) N / nb around the grid estimate and
+// stores its coefficients to parts[f][b]; the Newton kernel adds the shares
+// in block order.
 template <int N, typename CX>
-__global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step_limit) {
+__global__ void __launch_bounds__(kNThreads) k_newton_part(GroupParams g, double* __restrict__ parts,
+                                                           int nb) {
+  __shared__ double2 phy[N];
+  __shared__ double ay[N];
+  __shared__ double red[kNThreads / 64][kOrder + 1][kOrder + 1];
+  __shared__ double nred[kNThreads / 64][2 * (kOrder + 1)];
+  __shared__ double coef[kCoef];
+  const int f = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
+  const FrameState st = g.st[f];
+  if ((st.flags & CCPT_ST_NONFINITE) || st.amin == st.amax) return;  // no model needed
+  int py, px;
+  double dgy, dgx;
+  grid_seed<N>(g, st, py, px, dgy, dgx);
+  const CX* Xf = (sizeof(CX) == sizeof(float2) ? (const CX*)g.X : (const CX*)g.X64) +
+                 (size_t)f * N * (N / 2 + 1);
+  build_model<N, CX>(Xf, dgy, dgx, phy, ay, red, nred, coef, b * N / nb, (b + 1) * N / nb);
+  if (tid < kCoef) parts[((size_t)f * nb + b) * kCoef + tid] = coef[tid];
+}
+
+template <int N, typename CX>
+__global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step_limit,
+                                                      const double* __restrict__ parts, int nb) {
   __shared__ double2 phy[N];
   __shared__ double ay[N];
   __shared__ double red[kNThreads / 64][kOrder + 1][kOrder + 1];
@@ -321,16 +368,9 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
     return;
   }
   reset_state();
-  unsigned pk = key_index(st.peak_key);
-  if (pk >= (unsigned)(N * N)) pk = 0;
-  int py = pk / N, px = pk % N;
-  if (2 * py >= N) py -= N;
-  if (2 * px >= N) px -= N;
-  unsigned gk = key_index(st.grid_key);
-  if (gk >= (unsigned)(g.M * g.M)) gk = (unsigned)(g.c * g.M + g.c);
-  const int my = gk / g.M, mx = gk % g.M;
-  const double dgy = py + (double)(my - g.c) / g.u;
-  const double dgx = px + (double)(mx - g.c) / g.u;
+  int py, px;
+  double dgy, dgx;
+  grid_seed<N>(g, st, py, px, dgy, dgx);
   const CX* Xf = (sizeof(CX) == sizeof(float2) ? (const CX*)g.X : (const CX*)g.X64) +
                  (size_t)f * N * (N / 2 + 1);
 
@@ -342,7 +382,17 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
   double cy = dgy, cx = dgx;
   Deriv fin{0, 0, 0, 0, 0, 0};
   for (int pass = 0; pass < kMaxPasses; ++pass) {
-    build_model<N, CX>(Xf, cy, cx, phy, ay, red, nred, coef);
+    if (pass == 0 && parts) {
+      // the first model from the blocks of k_newton_part, added in block order
+      if (tid < kCoef) {
+        double v = 0.0;
+        for (int b = 0; b < nb; ++b) v += parts[((size_t)f * nb + b) * kCoef + tid];
+        coef[tid] = v;
+      }
+      __syncthreads();
+    } else {
+      build_model<N, CX>(Xf, cy, cx, phy, ay, red, nred, coef);
+    }
     if (tid == 0) {
       while (!done && it_left > 0) {
         const Deriv e = model_eval(coef, sy - cy, sx - cx);
@@ -408,10 +458,23 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
 
 template <int N>
 static int newton_n(const GroupParams& g, double step_limit, hipStream_t s) {
-  if (g.X64)
-    hipLaunchKernelGGL((k_newton<N, double2>), dim3(g.count), dim3(kNThreads), 0, s, g, step_limit);
-  else
-    hipLaunchKernelGGL((k_newton<N, float2>), dim3(g.count), dim3(kNThreads), 0, s, g, step_limit);
+  // few frames: the first model is built by kNewtonParts blocks per frame
+  const bool split = g.nparts && g.count < kNewtonSplitMax;
+  double* parts = split ? g.nparts : nullptr;
+  const int nb = split ? kNewtonParts : 0;
+  if (g.X64) {
+    if (split)
+      hipLaunchKernelGGL((k_newton_part<N, double2>), dim3(nb, g.count), dim3(kNThreads), 0, s, g,
+                         parts, nb);
+    hipLaunchKernelGGL((k_newton<N, double2>), dim3(g.count), dim3(kNThreads), 0, s, g, step_limit,
+                       (const double*)parts, nb);
+  } else {
+    if (split)
+      hipLaunchKernelGGL((k_newton_part<N, float2>), dim3(nb, g.count), dim3(kNThreads), 0, s, g,
+                         parts, nb);
+    hipLaunchKernelGGL((k_newton<N, float2>), dim3(g.count), dim3(kNThreads), 0, s, g, step_limit,
+                       (const double*)parts, nb);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
