@@ -134,6 +134,93 @@ def time_plain(tr, frames_t, count, torch):
     return np.array(lat)
 
 
+def _sync_time(fn, reps, torch):
+    """Wall time per call of fn() over reps calls, synchronised on both sides."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def leg_uneven_rois(dev, torch, Tracker):
+    """4096 ROIs of seven sizes (32..256) with their own references, one
+    batched FP32 call: the default chunking against the autotuned one."""
+    from synth import frames as S
+    w = S.config3(4096)
+    refs = [torch.from_numpy(r.astype(np.float32)).to(dev) for r in w.refs]
+    fr = [torch.from_numpy(np.ascontiguousarray(f)).to(dev) for f in w.frames]
+    ids = [int(i) for i in w.ref_ids]
+    out = {}
+    for tuned in (False, True):
+        tr = Tracker(upsample=w.u)
+        tr.set_reference(refs)
+        rois = tr.rois(fr, ids)
+        res = torch.empty((len(fr), 72), dtype=torch.uint8, device=dev)
+        if tuned:
+            sizes = w.meta["sizes"]
+            for n in sorted(set(int(x) for x in sizes)):
+                tr.autotune(n, int((sizes == n).sum()))
+        dt = _sync_time(lambda: tr.track(None, out=res, rois=rois), 10, torch)
+        out["autotuned" if tuned else "default"] = dict(rois_per_s=round(len(fr) / dt, 1),
+                                                        ms_per_call=round(dt * 1e3, 3))
+        tr.close()
+    return out
+
+
+def leg_gauss512(dev, torch, Tracker):
+    """2048 frames of 512x512 at u = 200 (M = 300): batched split precision
+    against batched FP32."""
+    from synth import frames as S
+    w = S.config4(2048)
+    fr = torch.from_numpy(np.stack(w.frames)).to(dev)
+    ref = torch.from_numpy(w.refs[0].astype(np.float32)).to(dev)
+    out = {}
+    for prec in ("bf16x2", "fp32"):
+        tr = Tracker(upsample=w.u, precision=prec)
+        tr.set_reference(ref)
+        tr.autotune(512, fr.shape[0])
+        rois = tr.rois(fr)
+        res = torch.empty((fr.shape[0], 72), dtype=torch.uint8, device=dev)
+        dt = _sync_time(lambda: tr.track(None, out=res, rois=rois), 5, torch)
+        out[prec] = dict(frames_per_s=round(fr.shape[0] / dt, 1), ms_per_call=round(dt * 1e3, 3))
+        tr.close()
+    return out
+
+
+def leg_grad128(dev, torch, Tracker):
+    """1024 frames of 128x128 (float32 photon counts): forward + backward
+    (frame and template gradients) throughput, and the time of one Adam step
+    of the template optimisation."""
+    from synth import frames as S
+    from paper_2310_08770_amd.autograd import optimise_template
+    w = S.config5(1024)
+    fr = torch.from_numpy(np.stack(w.frames)).to(dev)
+    ref = torch.from_numpy(w.refs[0].astype(np.float32)).to(dev)
+    tr = Tracker(upsample=w.u)
+    tr.set_reference(ref)
+    g_d = torch.randn((fr.shape[0], 2), dtype=torch.float64, device=dev)
+
+    def fwd_bwd():
+        o = tr.track(fr)
+        tr.track_grad(fr, o, g_d, None)
+
+    dt = _sync_time(fwd_bwd, 10, torch)
+    shifts = torch.from_numpy(w.shifts - w.shifts[0]).to(dev)
+    ref0 = torch.from_numpy(np.maximum(w.frames[0], 1.0).astype(np.float32)).to(dev)
+    optimise_template(fr, shifts, ref0, tr, steps=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, losses = optimise_template(fr, shifts, ref0, tr, steps=20)
+    torch.cuda.synchronize()
+    adam = (time.perf_counter() - t0) / 20
+    tr.close()
+    return dict(fwd_bwd_frames_per_s=round(fr.shape[0] / dt, 1), fwd_bwd_ms=round(dt * 1e3, 3),
+                adam_step_ms=round(adam * 1e3, 3), loss_first=losses[0], loss_last=losses[-1])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +232,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-frame legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (mixed ROIs, 512x512 u=200, 128x128 gradients)")
     ap.add_argument("--no-tune", action="store_true", help="skip the chunk autotuner")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (counter calibration)")
@@ -274,6 +363,17 @@ def main():
         st = trp.stage_times(reset=True)
         legs["plain"]["gpu_stage_us"] = {k: round(v[0] / max(1, v[1]) * 1e3, 2) for k, v in st.items() if v[1]}
         trp.close()
+
+    # ---- the other workloads (each guarded: a failure is recorded, not fatal)
+    if not args.no_extra:
+        for name, fn in (("uneven_rois_u100", leg_uneven_rois), ("gauss512_u200", leg_gauss512),
+                         ("gauss128_grad", leg_grad128)):
+            t0 = time.perf_counter()
+            try:
+                legs[name] = fn(dev, torch, Tracker)
+            except Exception as e:  # noqa: BLE001
+                legs[name] = dict(error=str(e)[:300])
+            log(f"[bench] {name}: {legs[name]} ({time.perf_counter() - t0:.1f} s)")
 
     # ---- accuracy against the oracle sample
     accuracy = None
