@@ -24,6 +24,9 @@ particle tracking"):
                    reference by the implicit function theorem
   O9 Fisher / CRB  Cramer-Rao bound of the displacement under Poisson noise
                    (the shot-noise limit of Sec. IV)
+  O10 offline reference  Sec. III.A, Eq. (8): the reference as the mean of
+                   all frames shifted back by their displacements, in Fourier
+                   space, iterated pass by pass from F[E_0] = F[I_0]
 
 Readings where the paper is silent or loose (each is also listed in the
 design notes of the repository):
@@ -44,6 +47,13 @@ design notes of the repository):
 * Refinement: Newton on C(s) from d_grid, with fallback to d_grid when the
   Hessian is not negative definite, a step exceeds 1/u, or the result
   leaves the 0.75-px half window.
+* Reference updates (Eq. 8-9): the reference E is the mean image of the
+  frames (Eq. 5 makes E the mean of the frames; the substitution rule of
+  Sec. III applies to the correlation, not to this average), in both CC-U
+  and CC-SN.  A frame shifted back by its displacement d is I(r + d) (the
+  paper's I(r - r0)); its spectrum is F[I](k) phi_ky(d_y) phi_kx(d_x) with
+  the same Nyquist rule, i.e. the band-limited shift.  Frames whose
+  tracking was non-finite or flat are left out of the mean.
 """
 from __future__ import annotations
 
@@ -387,3 +397,43 @@ def crb(mu):
 def shot_noise_limit(w0, n_photons):
     """Shot-noise limit of Sec. IV: sigma_pos = w0 / (2 sqrt(N_gamma))."""
     return w0 / (2.0 * math.sqrt(n_photons))
+
+
+# --------------------------------------------------------------------------
+# O10  offline reference (Sec. III.A, Eq. 8)
+# --------------------------------------------------------------------------
+def align_spectrum(F, d):
+    """Spectrum of a frame shifted back by its displacement d = (d_y, d_x):
+    F[I(r + d)](k) = F[I](k) phi_ky(d_y) phi_kx(d_x) (band-limited shift,
+    Nyquist bins scaled by cos(pi d))."""
+    ny, nx = F.shape
+    return F * np.outer(phi(ny, d[0]), phi(nx, d[1]))
+
+
+def mean_aligned(frames, ds, statuses=None):
+    """Eq. (8) for one pass: the inverse transform of (1/n) sum_i
+    F[I_i(r - r0_i)] over the frames that tracked (status without NONFINITE
+    or FLAT), with r0 = -d."""
+    acc = None
+    n = 0
+    for i, (f, d) in enumerate(zip(frames, ds)):
+        if statuses is not None and (int(statuses[i]) & (NONFINITE | FLAT)):
+            continue
+        a = align_spectrum(np.fft.fft2(np.asarray(f, dtype=np.float64)), d)
+        acc = a if acc is None else acc + a
+        n += 1
+    if n == 0:
+        raise ValueError("no frame to average")
+    return np.fft.ifft2(acc / n).real
+
+
+def iterative_reference(frames, u, passes, mode=MODE_CCU, eps=200.0):
+    """Sec. III.A: E_0 = I_0; pass n tracks every frame against E_{n-1} and
+    E_n = mean_aligned(frames, displacements).  Returns (E_passes, the
+    results of the last pass)."""
+    E = np.asarray(frames[0], dtype=np.float64)
+    res = None
+    for _ in range(passes):
+        res = [track(f, E, u, mode, eps) for f in frames]
+        E = mean_aligned(frames, [r["d"] for r in res], [r["status"] for r in res])
+    return E, res

@@ -90,3 +90,13 @@ def test_fisher_without_poisson_weight_is_caught(monkeypatch):
 
     monkeypatch.setattr(O, "fisher", bad)
     _fails(P.test_p9_crb_closed_form_zero_background)
+
+
+def test_reversed_alignment_shift_is_caught(monkeypatch):
+    good = O.align_spectrum
+
+    def bad(F, d):
+        return good(F, -np.asarray(d))
+
+    monkeypatch.setattr(O, "align_spectrum", bad)
+    _fails(P.test_p13_integer_rolls_average_back_to_the_image)

@@ -367,3 +367,47 @@ def test_window_exit_on_two_equal_spots():
                 + S.phase_ramp_shift(S.zero_nyquist(ref), (0.0, -0.5)))
     res = O.track(fr, ref, 10)
     assert np.max(np.abs(res["d"] - np.array(res["p"]))) <= O.HALF_WINDOW
+
+
+# ---------------------------------------------------------------- offline reference (Eq. 8)
+def test_p13_integer_rolls_average_back_to_the_image():
+    """Frames that are exact circular shifts of one image, averaged after
+    shifting back by their (integer) displacements, give that image."""
+    rng = np.random.Generator(np.random.PCG64(13))
+    img = rng.random((16, 24)) * 100.0
+    shifts = [(0, 0), (1, -3), (-8, 5), (7, 11), (3, -12)]
+    frames = [np.roll(img, s, axis=(0, 1)) for s in shifts]
+    E = O.mean_aligned(frames, [np.array(s, float) for s in shifts])
+    assert np.max(np.abs(E - img)) <= 1e-12 * np.max(img)
+
+
+def test_p13_subpixel_shifts_average_back_to_the_spot():
+    """Noiseless sub-pixel phase-ramp shifts of a spot without Nyquist
+    content undo exactly under the band-limited shift."""
+    spot = S.zero_nyquist(S.gaussian_spot(32, 2.5, 1000.0))
+    ds = [np.array(d) for d in [(0.3, -0.7), (1.25, 0.5), (-1.9, 1.1), (0.0, 0.0)]]
+    frames = [S.phase_ramp_shift(spot, d) for d in ds]
+    E = O.mean_aligned(frames, ds)
+    assert np.max(np.abs(E - spot)) <= 1e-10 * np.max(spot)
+
+
+def test_p13_mean_skips_frames_that_did_not_track():
+    img = S.gaussian_spot(16, 2.0, 50.0)
+    bad = np.full((16, 16), np.nan)
+    E = O.mean_aligned([img, bad], [np.zeros(2), np.zeros(2)], [0, O.NONFINITE])
+    assert np.max(np.abs(E - img)) <= 1e-12 * np.max(img)
+
+
+def test_p13_one_pass_aligns_noiseless_copies_to_the_first_frame():
+    """With F[E_0] = F[I_0], one pass over noiseless shifted copies of a spot
+    measures each copy's shift relative to frame 0 and averages them back
+    onto frame 0; the next pass then reports exactly those relative shifts."""
+    spot = S.zero_nyquist(S.gaussian_spot(32, 2.5, 1000.0))
+    d_true = np.array([(0.4, -0.3), (1.2, 0.8), (-0.6, 1.7), (0.9, -1.4)])
+    frames = [S.phase_ramp_shift(spot, d) for d in d_true]
+    E1, res1 = O.iterative_reference(frames, 20, 1)
+    assert np.max(np.abs(E1 - frames[0])) <= 1e-8 * np.max(spot)
+    rel = d_true - d_true[0]
+    assert np.max(np.abs(np.array([r["d"] for r in res1]) - rel)) <= 1e-9
+    E2, res2 = O.iterative_reference(frames, 20, 2)
+    assert np.max(np.abs(np.array([r["d"] for r in res2]) - rel)) <= 1e-9
