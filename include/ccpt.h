@@ -202,6 +202,25 @@ int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_resul
    (CCPT_E_INVALID otherwise, checked on the host after the copy). */
 int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* stream);
 
+/* Offline reference of Sec. III.A (Eq. 8): the mean of the frames shifted
+   back by their measured displacements, taken in Fourier space,
+     out = F^-1[ (1/n') sum_i F[I_i](k) phi_ky(d_iy) phi_kx(d_ix) ],
+   phi_k(s) = exp(2 pi i k~ s / N), cos(pi s) for a Nyquist bin (the
+   band-limited shift of the interpolant the tracker maximises); frame i
+   shifted back is I_i(r + d_i), the paper's I_i(r - r0).  The mean image is
+   the reference in both modes (CC-SN then uses -1/(E + eps) of it).
+   rois: n frames of one size N (host array as for ccpt_track_batch;
+   ref_id is not used).  fwd: their results from ccpt_track_batch (device,
+   roi order).  Frames whose status has CCPT_ST_NONFINITE or CCPT_ST_FLAT
+   are left out; n' counts the others (n' = 0 gives zeros).  out: N x N
+   float32, row-major, device, caller-owned.  One pass of Eq. 8 is
+   ccpt_track_batch against E_n, this call, then ccpt_set_reference(out).
+   Stream-ordered; may grow the context's workspace.
+   Returns CCPT_E_INVALID for null pointers, n < 1 or mixed sizes,
+   CCPT_E_UNSUPPORTED for an unsupported size. */
+int ccpt_mean_aligned(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_result* fwd,
+                      float* out, void* stream);
+
 /* Launch scheduling of the batched path (a10): frames of one size are run in
    chunks whose spectra workspace stays resident in the Infinity Cache; the
    chunk size trades that residency against the number of launches.

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libccpt.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "xcorr.hip", "updft.hip", "updft64.hip", "newton.hip", "grad.hip"]
+SOURCES = ["api.cpp", "xcorr.hip", "updft.hip", "updft64.hip", "newton.hip", "grad.hip",
+           "reference.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -96,6 +96,8 @@ def lib():
         L.ccpt_track_grad.restype = c_int
         L.ccpt_fisher.argtypes = [c_void_p, POINTER(Image), c_void_p, c_void_p]
         L.ccpt_fisher.restype = c_int
+        L.ccpt_mean_aligned.argtypes = [c_void_p, POINTER(Roi), c_int, c_void_p, c_void_p, c_void_p]
+        L.ccpt_mean_aligned.restype = c_int
         L.ccpt_autotune.argtypes = [c_void_p, c_int, c_int, c_void_p]
         L.ccpt_autotune.restype = c_int
         L.ccpt_schedule.argtypes = [c_void_p, c_int, POINTER(c_int), c_int]
@@ -112,7 +114,7 @@ def lib():
 
 EXPORTS = ["ccpt_default_options", "ccpt_create", "ccpt_destroy", "ccpt_set_reference",
            "ccpt_track_batch", "ccpt_track_grad", "ccpt_fisher", "ccpt_autotune", "ccpt_schedule",
-           "ccpt_stage_times", "ccpt_status_string", "ccpt_last_error"]
+           "ccpt_stage_times", "ccpt_status_string", "ccpt_last_error", "ccpt_mean_aligned"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -266,6 +268,17 @@ class Tracker:
                                       c_void_p(_stream_handle(stream))))
         f = out
         return torch.stack([torch.stack([f[0], f[1]]), torch.stack([f[1], f[2]])])
+
+    def mean_aligned(self, frames, fwd, stream=None):
+        """Offline reference of Eq. (8): the mean of the frames shifted back by
+        their displacements in fwd (track() results for the same frames, in
+        order), as an [N, N] float32 device tensor."""
+        arr, n = self.rois(frames)
+        N = arr[0].nx
+        out = torch.empty((N, N), dtype=torch.float32, device=self.device)
+        self._check(lib().ccpt_mean_aligned(self._h, arr, n, c_void_p(fwd.data_ptr()),
+                                            c_void_p(out.data_ptr()), c_void_p(_stream_handle(stream))))
+        return out
 
     def stage_times(self, reset=True):
         """{stage: (total ms, launches)} recorded with profile=True."""

@@ -947,6 +947,51 @@ int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* strea
   return CCPT_OK;
 }
 
+int ccpt_mean_aligned(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_result* fwd,
+                      float* out, void* stream) {
+  if (!ctx) return CCPT_E_INVALID;
+  if (n < 1 || !rois || !fwd || !out) return fail(ctx, CCPT_E_INVALID, "bad arguments");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int N = rois[0].nx;
+  std::vector<FrameDesc> desc(n);
+  for (int i = 0; i < n; ++i) {
+    const ccpt_roi& r = rois[i];
+    rc = check_image(ctx, r.data, r.ny, r.nx, r.pitch, r.dtype, "roi", i);
+    if (rc) return rc;
+    if (r.nx != N) return fail(ctx, CCPT_E_INVALID, "roi %d: size %d differs from %d", i, r.nx, N);
+    desc[i] = FrameDesc{r.data, nullptr, r.pitch, r.dtype, i, 0};
+  }
+  rc = ensure_tables(ctx, N);
+  if (rc) return rc;
+  const size_t spec = spec_elems(N);
+  const size_t per_frame = 2 * spec * sizeof(float2);  // T and the frame's spectrum
+  const int chunk = std::max(1, std::min<int>(n, (int)(((size_t)256 << 20) / per_frame)));
+  const size_t head = spec * sizeof(float2) + 256;  // accumulator, counter
+  rc = ensure_ws(ctx, head + per_frame * chunk);
+  if (rc) return rc;
+  rc = upload_desc(ctx, desc, s);
+  if (rc) return rc;
+  float2* acc = (float2*)ctx->ws;
+  unsigned* cnt = (unsigned*)(acc + spec);
+  float2* T = (float2*)((char*)ctx->ws + head);
+  float2* F = T + spec * chunk;
+  const float2* tw = ctx->tables[N].tw;
+  if (launch_zero(acc, head, s)) return fail(ctx, CCPT_E_HIP, "zero launch failed");
+  for (int c0 = 0; c0 < n; c0 += chunk) {
+    const int count = std::min(chunk, n - c0);
+    if (launch_frame_spectra(N, ctx->d_desc, c0, count, CCPT_MODE_CCU, 0.f, T, F, tw, s) ||
+        launch_align_accumulate(N, ctx->d_desc, c0, count, fwd, F, acc, cnt, s))
+      return fail(ctx, CCPT_E_HIP, "alignment launch failed");
+  }
+  // the row pass of the inverse returns half the unnormalised transform
+  if (launch_inverse(N, acc, 1, 2.0f / ((float)N * (float)N), T, out, tw, s) ||
+      launch_scale_by_count(out, N * N, 1.0f, cnt, s))
+    return fail(ctx, CCPT_E_HIP, "inverse launch failed");
+  return CCPT_OK;
+}
+
 int ccpt_stage_times(ccpt_ctx* ctx, double* ms, int* launches, int n_stages, int reset) {
   if (!ctx || n_stages < 0 || (n_stages > 0 && (!ms || !launches))) return CCPT_E_INVALID;
   for (int i = 0; i < n_stages; ++i) {

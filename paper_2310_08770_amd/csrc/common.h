@@ -210,6 +210,16 @@ int launch_fisher_deriv(int N, const float2* F, float2* Dy, float2* Dx, hipStrea
 int launch_fisher_reduce(const float* dy, const float* dx, const void* mu, int dtype, int pitch,
                          int n, double* part, int nblocks, double* out, hipStream_t s);
 
+// Offline reference (reference.hip): for a chunk of frames whose spectra
+// are in F ([count][N][N/2+1]), multiplies each by the phases of its
+// displacement (results fwd[desc.out_idx]), adds them in frame order to acc
+// and counts the frames that tracked into cnt.
+int launch_align_accumulate(int N, const FrameDesc* desc, int first, int count,
+                            const ccpt_result* fwd, float2* F, float2* acc, unsigned* cnt,
+                            hipStream_t s);
+// img *= scale / *cnt (zeros when *cnt == 0).
+int launch_scale_by_count(float* img, int nn, float scale, const unsigned* cnt, hipStream_t s);
+
 // Fills bytes of device memory with zero using a kernel (graph-safe).
 int launch_zero(void* p, size_t bytes, hipStream_t s);
 

@@ -1,0 +1,126 @@
+// Reference images from aligned frames: the offline reference of Sec. III.A
+// (Eq. 8), the mean of all frames shifted back by their measured
+// displacements, taken in Fourier space.
+//
+// A frame I tracked at displacement d (frame(r) ~ ref(r - d)) shifted back
+// is I(r + d), the paper's I(r - r0) with r0 = -d; its spectrum is
+// F[I](k) phi_ky(d_y) phi_kx(d_x) with phi_k(s) = exp(2 pi i k~ s / N) and
+// phi = cos(pi s) for a Nyquist bin (the band-limited shift, the same
+// interpolant the tracker maximises).  Frames whose tracking was non-finite
+// or flat are left out of the mean.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "common.h"
+#include "fft.h"
+
+namespace ccpt {
+
+constexpr int kRefThreads = 256;
+constexpr int kAlignRows = 8;  // spectrum rows per block of k_align_spectra
+
+__device__ __forceinline__ bool tracked(const ccpt_result& r) {
+  return !(r.status & (CCPT_ST_NONFINITE | CCPT_ST_FLAT));
+}
+
+// phi_k(d) of one axis as FP32 complex, computed in FP64.
+__device__ __forceinline__ float2 shift_phase(int k, int N, double d) {
+  if (2 * k == N) return make_float2((float)cospi(d), 0.f);
+  const int kt = 2 * k < N ? k : k - N;
+  double sn, cs;
+  sincospi(2.0 * (double)kt * d / (double)N, &sn, &cs);
+  return make_float2((float)cs, (float)sn);
+}
+
+// F[f] (row-major N x (N/2+1)) *= phi_ky(d_y) phi_kx(d_x) for frame f's
+// displacement; frames that did not track are zeroed.
+template <int N>
+__global__ void __launch_bounds__(kRefThreads) k_align_spectra(const FrameDesc* __restrict__ desc,
+                                                               int first,
+                                                               const ccpt_result* __restrict__ fwd,
+                                                               float2* __restrict__ F) {
+  constexpr int H = N / 2 + 1;
+  __shared__ float2 px[H];
+  __shared__ float2 py[kAlignRows];
+  const int f = blockIdx.y, y0 = blockIdx.x * kAlignRows, tid = threadIdx.x;
+  const ccpt_result r = fwd[desc[first + f].out_idx];
+  const bool ok = tracked(r);
+  for (int k = tid; k < H; k += kRefThreads) px[k] = ok ? shift_phase(k, N, r.d[1]) : make_float2(0.f, 0.f);
+  for (int k = tid; k < kAlignRows; k += kRefThreads)
+    py[k] = (ok && y0 + k < N) ? shift_phase(y0 + k, N, r.d[0]) : make_float2(0.f, 0.f);
+  __syncthreads();
+  float2* Ff = F + (size_t)f * N * H;
+  const int rows = min(kAlignRows, N - y0);
+  for (int i = tid; i < rows * H; i += kRefThreads) {
+    const int ry = i / H, kx = i - ry * H;
+    const size_t e = (size_t)(y0 + ry) * H + kx;
+    // (a frame that did not track may hold NaN: written as zeros, not scaled)
+    Ff[e] = ok ? cmul(Ff[e], cmul(py[ry], px[kx])) : make_float2(0.f, 0.f);
+  }
+}
+
+// acc[k] += sum over the chunk's frames of F[f][k], frames in order.
+template <int N>
+__global__ void k_sum_spectra(int count, const float2* __restrict__ F, float2* __restrict__ acc) {
+  constexpr int H = N / 2 + 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * H) return;
+  float2 sum = make_float2(0.f, 0.f);
+  for (int f = 0; f < count; ++f) sum = cadd(sum, F[(size_t)f * N * H + e]);
+  acc[e] = cadd(acc[e], sum);
+}
+
+__global__ void k_count_tracked(const FrameDesc* __restrict__ desc, int first, int count,
+                                const ccpt_result* __restrict__ fwd, unsigned* __restrict__ cnt) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < count && tracked(fwd[desc[first + f].out_idx])) atomicAdd(cnt, 1u);
+}
+
+// img *= scale / count (count >= 1; an empty mean is left as zeros)
+__global__ void k_scale_by_count(float* __restrict__ img, int nn, float scale,
+                                 const unsigned* __restrict__ cnt) {
+  const unsigned c = *cnt;
+  const float s = c ? scale / (float)c : 0.f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += gridDim.x * blockDim.x)
+    img[i] *= s;
+}
+
+template <int N>
+static int align_accumulate_n(const FrameDesc* desc, int first, int count, const ccpt_result* fwd,
+                              float2* F, float2* acc, unsigned* cnt, hipStream_t s) {
+  constexpr int H = N / 2 + 1;
+  hipLaunchKernelGGL((k_align_spectra<N>), dim3((N + kAlignRows - 1) / kAlignRows, count),
+                     dim3(kRefThreads), 0, s, desc, first, fwd, F);
+  hipLaunchKernelGGL((k_sum_spectra<N>), dim3((N * H + 255) / 256), dim3(256), 0, s, count,
+                     (const float2*)F, acc);
+  hipLaunchKernelGGL(k_count_tracked, dim3((count + 255) / 256), dim3(256), 0, s, desc, first,
+                     count, fwd, cnt);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+#define CCPT_FOR_SIZES(X) \
+  X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
+  X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
+
+int launch_align_accumulate(int N, const FrameDesc* desc, int first, int count,
+                            const ccpt_result* fwd, float2* F, float2* acc, unsigned* cnt,
+                            hipStream_t s) {
+  switch (N) {
+#define CASE(n) \
+  case n:       \
+    return align_accumulate_n<n>(desc, first, count, fwd, F, acc, cnt, s);
+    CCPT_FOR_SIZES(CASE)
+#undef CASE
+  }
+  return -2;
+}
+
+int launch_scale_by_count(float* img, int nn, float scale, const unsigned* cnt, hipStream_t s) {
+  int blocks = (nn + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_scale_by_count, dim3(blocks), dim3(256), 0, s, img, nn, scale, cnt);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace ccpt
