@@ -27,6 +27,10 @@ particle tracking"):
   O10 offline reference  Sec. III.A, Eq. (8): the reference as the mean of
                    all frames shifted back by their displacements, in Fourier
                    space, iterated pass by pass from F[E_0] = F[I_0]
+  O11 real-time reference  Sec. III.B, Eq. (9): low-pass update of the
+                   reference spectrum by each tracked frame shifted back
+  O12 drift correction  Sec. III.B, Eq. (10)-(12): low-pass offset of the
+                   displacement stream, optionally rate-limited to alpha/u
 
 Readings where the paper is silent or loose (each is also listed in the
 design notes of the repository):
@@ -437,3 +441,50 @@ def iterative_reference(frames, u, passes, mode=MODE_CCU, eps=200.0):
         res = [track(f, E, u, mode, eps) for f in frames]
         E = mean_aligned(frames, [r["d"] for r in res], [r["status"] for r in res])
     return E, res
+
+
+# --------------------------------------------------------------------------
+# O11  real-time reference (Sec. III.B, Eq. 9)
+# --------------------------------------------------------------------------
+def realtime_track(frames, u, a0, mode=MODE_CCU, eps=200.0):
+    """Tracks the frames in order against a reference updated after each
+    frame by F[E_i] = a0 F[I_i(r - r0_i)] + b1 F[E_{i-1}], b1 = 1 - a0,
+    starting from E_{-1} = E_0 = I_0 (so frame 0 is tracked against itself
+    and leaves E unchanged).  A frame that did not track (NONFINITE or FLAT)
+    leaves the reference unchanged.  Returns the list of results."""
+    E = np.asarray(frames[0], dtype=np.float64)
+    FE = np.fft.fft2(E)
+    b1 = 1.0 - a0
+    out = []
+    for f in frames:
+        r = track(f, E, u, mode, eps)
+        out.append(r)
+        if r["status"] & (NONFINITE | FLAT):
+            continue
+        FE = a0 * align_spectrum(np.fft.fft2(np.asarray(f, dtype=np.float64)), r["d"]) + b1 * FE
+        E = np.fft.ifft2(FE).real
+    return out
+
+
+# --------------------------------------------------------------------------
+# O12  drift correction (Sec. III.B, Eq. 10-12)
+# --------------------------------------------------------------------------
+def drift_filter(r, a0, rate_limit=0.0):
+    """Offsets R_n and corrected displacements r_n - R_n for a sequence of
+    displacements r ([n, 2]).  Eq. (10): R_n = a0 r_n + b1 R_{n-1} with
+    R_{-1} = 0 (so R_0 = a0 r_0).  With rate_limit = alpha/u > 0, Eq. (11)-(12):
+    dR_n = a0 r_n + (b1 - 1) R_{n-1}, and a step longer than rate_limit is
+    cut to that length along dR_n."""
+    r = np.asarray(r, dtype=np.float64)
+    b1 = 1.0 - a0
+    R = np.zeros(2)
+    offsets = np.zeros_like(r)
+    for n, rn in enumerate(r):
+        if rate_limit > 0.0:
+            dR = a0 * rn + (b1 - 1.0) * R
+            L = math.hypot(dR[0], dR[1])
+            R = R + (rate_limit * dR / L if L > rate_limit else dR)
+        else:
+            R = a0 * rn + b1 * R
+        offsets[n] = R
+    return offsets, r - offsets

@@ -100,3 +100,17 @@ def test_reversed_alignment_shift_is_caught(monkeypatch):
 
     monkeypatch.setattr(O, "align_spectrum", bad)
     _fails(P.test_p13_integer_rolls_average_back_to_the_image)
+
+
+def test_realtime_update_with_unshifted_frames_is_caught(monkeypatch):
+    def bad(F, d):
+        return F  # the frame is not shifted back before the update
+
+    monkeypatch.setattr(O, "align_spectrum", bad)
+    _fails(P.test_p14_perfectly_tracked_frames_keep_the_reference_in_place, 0.5)
+
+
+def test_drift_filter_without_rate_limit_is_caught(monkeypatch):
+    good = O.drift_filter
+    monkeypatch.setattr(O, "drift_filter", lambda r, a0, rate_limit=0.0: good(r, a0))
+    _fails(P.test_p15_rate_limit_bounds_every_step_and_is_inactive_for_small_steps)

@@ -411,3 +411,73 @@ def test_p13_one_pass_aligns_noiseless_copies_to_the_first_frame():
     assert np.max(np.abs(np.array([r["d"] for r in res1]) - rel)) <= 1e-9
     E2, res2 = O.iterative_reference(frames, 20, 2)
     assert np.max(np.abs(np.array([r["d"] for r in res2]) - rel)) <= 1e-9
+
+
+# ---------------------------------------------------------------- real-time reference (Eq. 9)
+def _noiseless_copies(n=32, count=6, seed=4):
+    spot = S.zero_nyquist(S.gaussian_spot(n, 2.5, 1000.0))
+    d = np.random.Generator(np.random.PCG64(seed)).uniform(-1.5, 1.5, size=(count, 2))
+    return spot, d, [S.phase_ramp_shift(spot, x) for x in d]
+
+
+def test_p14_zero_gain_tracks_everything_against_the_first_frame():
+    _, _, frames = _noiseless_copies()
+    res = O.realtime_track(frames, 20, 0.0)
+    for f, r in zip(frames, res):
+        assert np.max(np.abs(r["d"] - O.track(f, frames[0], 20)["d"])) <= 1e-12
+
+
+@pytest.mark.parametrize("a0", [0.05, 0.5, 1.0])
+def test_p14_perfectly_tracked_frames_keep_the_reference_in_place(a0):
+    """Noiseless shifted copies, shifted back by their measured displacements,
+    all equal frame 0, so the low-pass reference stays frame 0 and every
+    displacement is measured relative to frame 0."""
+    _, d, frames = _noiseless_copies()
+    res = O.realtime_track(frames, 20, a0)
+    got = np.array([r["d"] for r in res])
+    assert np.max(np.abs(got - (d - d[0]))) <= 1e-9
+
+
+def test_p14_full_gain_chains_consecutive_frames():
+    """With a0 = 1 the reference is the previous frame shifted back: for
+    frames whose content differs (two spots of different widths) the chain
+    still reports each shift relative to frame 0 when tracking is exact."""
+    a = S.zero_nyquist(S.gaussian_spot(32, 2.0, 1000.0) + 0.5 * S.gaussian_spot(32, 4.0, 600.0))
+    d = np.array([(0.0, 0.0), (0.35, -0.6), (1.1, 0.25), (-0.4, 0.9)])
+    frames = [S.phase_ramp_shift(a, x) for x in d]
+    res = O.realtime_track(frames, 20, 1.0)
+    assert np.max(np.abs(np.array([r["d"] for r in res]) - d)) <= 1e-9
+
+
+# ---------------------------------------------------------------- drift correction (Eq. 10-12)
+def test_p15_low_pass_of_a_constant_is_a_geometric_sum():
+    a0 = 0.1
+    r = np.tile([[0.3, -0.2]], (40, 1))
+    R, out = O.drift_filter(r, a0)
+    n = np.arange(40)[:, None]
+    want = r * (1.0 - (1.0 - a0) ** (n + 1))
+    assert np.max(np.abs(R - want)) <= 1e-15
+    assert np.max(np.abs(out - (r - want))) <= 1e-15
+
+
+def test_p15_rate_limit_bounds_every_step_and_is_inactive_for_small_steps():
+    rng = np.random.Generator(np.random.PCG64(8))
+    r = np.cumsum(rng.normal(0, 0.3, size=(500, 2)), axis=0)
+    a0, lim = 0.2, 0.5 / 100
+    R, _ = O.drift_filter(r, a0, lim)
+    steps = np.hypot(*np.diff(np.vstack([[0, 0], R]), axis=0).T)
+    assert np.all(steps <= lim * (1 + 1e-12))
+    small = 1e-4 * np.sin(np.arange(200))[:, None] * np.array([[1.0, 0.5]])
+    R1, _ = O.drift_filter(small, a0, lim)
+    R0, _ = O.drift_filter(small, a0)
+    assert np.max(np.abs(R1 - R0)) <= 1e-18
+
+
+def test_p15_rate_limited_step_response_is_a_ramp():
+    """A jump of 1 px with limit 0.005 px per frame: the offset walks towards
+    it in steps of exactly the limit while the filtered step exceeds it."""
+    a0, lim = 0.5, 0.005
+    r = np.tile([[1.0, 0.0]], (50, 1))
+    R, _ = O.drift_filter(r, a0, lim)
+    assert np.allclose(R[:, 0], lim * np.arange(1, 51), atol=1e-15)
+    assert np.all(R[:, 1] == 0.0)
