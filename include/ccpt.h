@@ -221,6 +221,35 @@ int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* strea
 int ccpt_mean_aligned(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_result* fwd,
                       float* out, void* stream);
 
+/* Real-time tracking with the reference low-pass of Sec. III.B (Eq. 9):
+   tracks one frame against reference roi->ref_id (as ccpt_track_batch with
+   n = 1; the result goes to out), then updates that reference with the
+   frame shifted back by its displacement,
+     F[E_i] = a0 F[I_i(r + d_i)] + (1 - a0) F[E_{i-1}],
+   a0 = 1 - exp(-T/tau) in [0, 1] (T the frame interval, tau the filter time
+   constant).  The reference starts as ccpt_set_reference left it (the
+   paper's F[E_0] = F[I_0]: set the first frame).  A frame whose status has
+   CCPT_ST_NONFINITE or CCPT_ST_FLAT leaves the reference unchanged.  E is
+   the mean image in both modes; CC-SN recomputes B = -1/(E + eps) from the
+   updated E (frames with values >= 0 keep E + eps > 0 for eps > 0).
+   roi: one frame (host struct, device data); out: one result (device).
+   Stream-ordered with no host synchronisation, so calls can follow each
+   other at the frame rate.  CCPT_E_UNSUPPORTED in FP64 precision. */
+int ccpt_track_update(ccpt_ctx* ctx, const ccpt_roi* roi, double a0, ccpt_result* out,
+                      void* stream);
+
+/* Drift correction of Sec. III.B (Eq. 10-12) on a stream of displacements
+   (host arrays r and out of n (y, x) pairs; they may be the same array):
+   Eq. 10  R_n = a0 r_n + (1 - a0) R_{n-1};
+   or, with rate_limit > 0 (alpha/u; the paper suggests alpha = 0.5),
+   Eq. 11-12  dR_n = a0 r_n - a0 R_{n-1}, a step longer than rate_limit cut
+   to that length along dR_n, R_n = R_{n-1} + dR_n;
+   out_n = r_n - R_n.  state[2] holds R_{n-1} (y, x) and is updated, so a
+   stream can be processed in pieces; zeros to start (R_0 = a0 r_0).  Pure
+   host computation (no context).  CCPT_E_INVALID for bad arguments. */
+int ccpt_drift_filter(const double* r, int n, double a0, double rate_limit, double* state,
+                      double* out);
+
 /* Launch scheduling of the batched path (a10): frames of one size are run in
    chunks whose spectra workspace stays resident in the Infinity Cache; the
    chunk size trades that residency against the number of launches.

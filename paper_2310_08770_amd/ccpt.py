@@ -98,6 +98,10 @@ def lib():
         L.ccpt_fisher.restype = c_int
         L.ccpt_mean_aligned.argtypes = [c_void_p, POINTER(Roi), c_int, c_void_p, c_void_p, c_void_p]
         L.ccpt_mean_aligned.restype = c_int
+        L.ccpt_track_update.argtypes = [c_void_p, POINTER(Roi), c_double, c_void_p, c_void_p]
+        L.ccpt_track_update.restype = c_int
+        L.ccpt_drift_filter.argtypes = [c_void_p, c_int, c_double, c_double, c_void_p, c_void_p]
+        L.ccpt_drift_filter.restype = c_int
         L.ccpt_autotune.argtypes = [c_void_p, c_int, c_int, c_void_p]
         L.ccpt_autotune.restype = c_int
         L.ccpt_schedule.argtypes = [c_void_p, c_int, POINTER(c_int), c_int]
@@ -114,7 +118,8 @@ def lib():
 
 EXPORTS = ["ccpt_default_options", "ccpt_create", "ccpt_destroy", "ccpt_set_reference",
            "ccpt_track_batch", "ccpt_track_grad", "ccpt_fisher", "ccpt_autotune", "ccpt_schedule",
-           "ccpt_stage_times", "ccpt_status_string", "ccpt_last_error", "ccpt_mean_aligned"]
+           "ccpt_stage_times", "ccpt_status_string", "ccpt_last_error", "ccpt_mean_aligned",
+           "ccpt_track_update", "ccpt_drift_filter"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -280,6 +285,18 @@ class Tracker:
                                             c_void_p(out.data_ptr()), c_void_p(_stream_handle(stream))))
         return out
 
+    def track_update(self, frame, a0, out=None, ref_id=0, stream=None):
+        """Real-time tracking of one frame with the reference low-pass of
+        Eq. (9); returns the device result buffer (uint8 [1, 72])."""
+        arr, n = self.rois(frame, [ref_id])
+        if n != 1:
+            raise ValueError("one frame per call")
+        if out is None:
+            out = torch.empty((1, RESULT_BYTES), dtype=torch.uint8, device=self.device)
+        self._check(lib().ccpt_track_update(self._h, arr, float(a0), c_void_p(out.data_ptr()),
+                                            c_void_p(_stream_handle(stream))))
+        return out
+
     def stage_times(self, reset=True):
         """{stage: (total ms, launches)} recorded with profile=True."""
         k = len(STAGES)
@@ -324,3 +341,16 @@ class Tracker:
     def set_chunk(self, n, chunk):
         c = c_int(int(chunk))
         self._check(lib().ccpt_schedule(self._h, int(n), ctypes.byref(c), 1))
+
+
+def drift_filter(r, a0, rate_limit=0.0, state=None):
+    """Drift correction of Eq. (10)-(12) on displacements r ([n, 2], host):
+    returns (r - R, state); pass the returned state to continue a stream."""
+    r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1, 2)
+    out = np.empty_like(r)
+    st = np.zeros(2) if state is None else np.array(state, dtype=np.float64)
+    rc = lib().ccpt_drift_filter(r.ctypes.data, r.shape[0], float(a0), float(rate_limit),
+                                 st.ctypes.data, out.ctypes.data)
+    if rc != OK:
+        raise CcptError(rc, "ccpt_drift_filter: bad arguments")
+    return out, st

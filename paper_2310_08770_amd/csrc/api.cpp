@@ -44,6 +44,7 @@ struct Ref {
   float2* spec = nullptr;     // conj F[B], N x (N/2+1) (the adjoint always uses it)
   double2* spec64 = nullptr;  // the same in FP64 (FP64 mode)
   float* img = nullptr;       // E as float (N x N), kept for the CC-SN chain rule
+  float2* espec = nullptr;    // CC-SN: F[E], N x (N/2+1), for real-time updates
 };
 
 struct Schedule {
@@ -107,6 +108,9 @@ struct ccpt_ctx {
   // partial Newton models of small launches
   void* nparts = nullptr;
   size_t nparts_cap = 0;
+  // real-time updates: scratch spectra T and F
+  void* rt_buf = nullptr;
+  size_t rt_cap = 0;
   // errors
   int last_code = CCPT_OK;
   std::string last_msg;
@@ -601,6 +605,7 @@ void ccpt_destroy(ccpt_ctx* ctx) {
   for (auto& r : ctx->refs) {
     (void)hipFree(r.spec);
     if (r.spec64) (void)hipFree(r.spec64);
+    if (r.espec) (void)hipFree(r.espec);
     (void)hipFree(r.img);
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
@@ -613,6 +618,7 @@ void ccpt_destroy(ccpt_ctx* ctx) {
   if (ctx->ypart) (void)hipFree(ctx->ypart);
   if (ctx->st_buf) (void)hipFree(ctx->st_buf);
   if (ctx->nparts) (void)hipFree(ctx->nparts);
+  if (ctx->rt_buf) (void)hipFree(ctx->rt_buf);
   if (ctx->h_small) (void)hipHostFree(ctx->h_small);
   delete ctx;
 }
@@ -652,6 +658,7 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
   for (auto& r : ctx->refs) {
     (void)hipFree(r.spec);
     if (r.spec64) (void)hipFree(r.spec64);
+    if (r.espec) (void)hipFree(r.espec);
     (void)hipFree(r.img);
   }
   ctx->refs.clear();
@@ -688,6 +695,19 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
                         ctx->tables[n].tw, s)) {
       (void)hipFree(tmp);
       return fail(ctx, CCPT_E_HIP, "reference spectrum launch failed");
+    }
+    if (ctx->o.mode == CCPT_MODE_CCSN) {
+      // F[E] itself, the state of real-time updates (B = -1/(E+eps) is not linear in E)
+      Ref& rr = ctx->refs.back();
+      if (hipMalloc(&rr.espec, spec_elems(n) * sizeof(float2)) != hipSuccess) {
+        (void)hipFree(tmp);
+        return fail(ctx, CCPT_E_NOMEM, "reference spectra");
+      }
+      HIP_CHECK(ctx, hipStreamSynchronize(s));
+      if (launch_spectrum(n, r.img, CCPT_F32, n, 0, 1, 0, 0.f, 0, T, rr.espec, ctx->tables[n].tw, s)) {
+        (void)hipFree(tmp);
+        return fail(ctx, CCPT_E_HIP, "reference spectrum launch failed");
+      }
     }
     if (fp64(ctx)) {
       // the FP64 spectrum from the reference's own values, not their FP32 copy
@@ -989,6 +1009,70 @@ int ccpt_mean_aligned(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_res
   if (launch_inverse(N, acc, 1, 2.0f / ((float)N * (float)N), T, out, tw, s) ||
       launch_scale_by_count(out, N * N, 1.0f, cnt, s))
     return fail(ctx, CCPT_E_HIP, "inverse launch failed");
+  return CCPT_OK;
+}
+
+int ccpt_track_update(ccpt_ctx* ctx, const ccpt_roi* roi, double a0, ccpt_result* out,
+                      void* stream) {
+  if (!ctx) return CCPT_E_INVALID;
+  if (!roi || !out || !(a0 >= 0.0 && a0 <= 1.0))
+    return fail(ctx, CCPT_E_INVALID, "bad arguments");
+  if (fp64(ctx)) return fail(ctx, CCPT_E_UNSUPPORTED, "real-time updates need FP32 or BF16X2 precision");
+  int rc = ccpt_track_batch(ctx, roi, 1, out, stream);  // validates roi and reference id
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Ref& R = ctx->refs[roi->ref_id];
+  const int N = R.n;
+  const size_t spec = spec_elems(N);
+  rc = ensure_buf(ctx, ctx->rt_buf, ctx->rt_cap, 2 * spec * sizeof(float2));
+  if (rc) return rc;
+  float2* T = (float2*)ctx->rt_buf;
+  float2* F = T + spec;
+  const float2* tw = ctx->tables[N].tw;
+  const float fa0 = (float)a0, fb1 = (float)(1.0 - a0);
+  // the frame's own spectrum F[I] (track_batch left its descriptor at index 0)
+  if (launch_frame_spectra(N, ctx->d_desc, 0, 1, CCPT_MODE_CCU, 0.f, T, F, tw, s))
+    return fail(ctx, CCPT_E_HIP, "frame spectrum launch failed");
+  if (ctx->o.mode == CCPT_MODE_CCU) {
+    if (launch_rt_update(N, out, F, R.spec, fa0, fb1, 1, s))
+      return fail(ctx, CCPT_E_HIP, "reference update launch failed");
+  } else {
+    // update F[E], then E, then conj F[-1/(E+eps)]
+    if (launch_rt_update(N, out, F, R.espec, fa0, fb1, 0, s) ||
+        launch_inverse(N, R.espec, 1, 2.0f / ((float)N * (float)N), T, R.img, tw, s) ||
+        launch_spectrum(N, R.img, CCPT_F32, N, 0, 1, 1, (float)ctx->o.eps, 1, T, R.spec, tw, s))
+      return fail(ctx, CCPT_E_HIP, "reference update launch failed");
+  }
+  return CCPT_OK;
+}
+
+int ccpt_drift_filter(const double* r, int n, double a0, double rate_limit, double* state,
+                      double* out) {
+  if (n < 0 || (n > 0 && (!r || !out)) || !state || !(a0 >= 0.0 && a0 <= 1.0) ||
+      !(rate_limit >= 0.0))
+    return CCPT_E_INVALID;
+  const double b1 = 1.0 - a0;
+  double Ry = state[0], Rx = state[1];
+  for (int i = 0; i < n; ++i) {
+    const double ry = r[2 * i], rx = r[2 * i + 1];
+    if (rate_limit > 0.0) {
+      double dy = a0 * ry + (b1 - 1.0) * Ry, dx = a0 * rx + (b1 - 1.0) * Rx;
+      const double L = std::hypot(dy, dx);
+      if (L > rate_limit) {
+        dy *= rate_limit / L;
+        dx *= rate_limit / L;
+      }
+      Ry += dy;
+      Rx += dx;
+    } else {
+      Ry = a0 * ry + b1 * Ry;
+      Rx = a0 * rx + b1 * Rx;
+    }
+    out[2 * i] = ry - Ry;
+    out[2 * i + 1] = rx - Rx;
+  }
+  state[0] = Ry;
+  state[1] = Rx;
   return CCPT_OK;
 }
 

@@ -217,6 +217,10 @@ int launch_fisher_reduce(const float* dy, const float* dx, const void* mu, int d
 int launch_align_accumulate(int N, const FrameDesc* desc, int first, int count,
                             const ccpt_result* fwd, float2* F, float2* acc, unsigned* cnt,
                             hipStream_t s);
+// Real-time reference update of Eq. 9 by one frame (spectrum F, result res):
+// S <- a0 v + b1 S with v the frame shifted back (conjugated when conj_s).
+int launch_rt_update(int N, const ccpt_result* res, const float2* F, float2* S, float a0, float b1,
+                     int conj_s, hipStream_t s);
 // img *= scale / *cnt (zeros when *cnt == 0).
 int launch_scale_by_count(float* img, int nn, float scale, const unsigned* cnt, hipStream_t s);
 

@@ -1,6 +1,7 @@
 // Reference images from aligned frames: the offline reference of Sec. III.A
 // (Eq. 8), the mean of all frames shifted back by their measured
-// displacements, taken in Fourier space.
+// displacements, and the real-time low-pass of Sec. III.B (Eq. 9), both
+// taken in Fourier space.
 //
 // A frame I tracked at displacement d (frame(r) ~ ref(r - d)) shifted back
 // is I(r + d), the paper's I(r - r0) with r0 = -d; its spectrum is
@@ -86,6 +87,46 @@ __global__ void k_scale_by_count(float* __restrict__ img, int nn, float scale,
     img[i] *= s;
 }
 
+// Real-time reference update (Sec. III.B, Eq. 9) by one frame with spectrum
+// F (row-major N x (N/2+1)) and result res: v = F phi_ky(d_y) phi_kx(d_x)
+// (the frame shifted back) enters the resident spectrum S as
+//   S <- a0 conj(v) + b1 S   (conj_s: S = conj F[E], the CC-U reference)
+//   S <- a0 v + b1 S         (S = F[E], kept for CC-SN)
+// and a frame that did not track leaves S unchanged.
+template <int N>
+__global__ void __launch_bounds__(kRefThreads) k_rt_update(const ccpt_result* __restrict__ res,
+                                                           const float2* __restrict__ F,
+                                                           float2* __restrict__ S, float a0,
+                                                           float b1, int conj_s) {
+  constexpr int H = N / 2 + 1;
+  __shared__ float2 px[H];
+  __shared__ float2 py[kAlignRows];
+  const int y0 = blockIdx.x * kAlignRows, tid = threadIdx.x;
+  const ccpt_result r = *res;
+  if (!tracked(r)) return;
+  for (int k = tid; k < H; k += kRefThreads) px[k] = shift_phase(k, N, r.d[1]);
+  for (int k = tid; k < kAlignRows; k += kRefThreads)
+    py[k] = y0 + k < N ? shift_phase(y0 + k, N, r.d[0]) : make_float2(0.f, 0.f);
+  __syncthreads();
+  const int rows = min(kAlignRows, N - y0);
+  for (int i = tid; i < rows * H; i += kRefThreads) {
+    const int ry = i / H, kx = i - ry * H;
+    const size_t e = (size_t)(y0 + ry) * H + kx;
+    float2 v = cmul(F[e], cmul(py[ry], px[kx]));
+    if (conj_s) v = cconj(v);
+    const float2 o = S[e];
+    S[e] = make_float2(a0 * v.x + b1 * o.x, a0 * v.y + b1 * o.y);
+  }
+}
+
+template <int N>
+static int rt_update_n(const ccpt_result* res, const float2* F, float2* S, float a0, float b1,
+                       int conj_s, hipStream_t s) {
+  hipLaunchKernelGGL((k_rt_update<N>), dim3((N + kAlignRows - 1) / kAlignRows), dim3(kRefThreads),
+                     0, s, res, F, S, a0, b1, conj_s);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <int N>
 static int align_accumulate_n(const FrameDesc* desc, int first, int count, const ccpt_result* fwd,
                               float2* F, float2* acc, unsigned* cnt, hipStream_t s) {
@@ -110,6 +151,18 @@ int launch_align_accumulate(int N, const FrameDesc* desc, int first, int count,
 #define CASE(n) \
   case n:       \
     return align_accumulate_n<n>(desc, first, count, fwd, F, acc, cnt, s);
+    CCPT_FOR_SIZES(CASE)
+#undef CASE
+  }
+  return -2;
+}
+
+int launch_rt_update(int N, const ccpt_result* res, const float2* F, float2* S, float a0, float b1,
+                     int conj_s, hipStream_t s) {
+  switch (N) {
+#define CASE(n) \
+  case n:       \
+    return rt_update_n<n>(res, F, S, a0, b1, conj_s, s);
     CCPT_FOR_SIZES(CASE)
 #undef CASE
   }

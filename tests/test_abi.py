@@ -46,3 +46,35 @@ def test_host_only_calls():
     # null context arguments are rejected without touching a device
     assert lib.ccpt_track_batch(None, None, 0, None, None) == -1
     assert lib.ccpt_create(None, 0, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libccpt.so not built")
+@pytest.mark.parametrize("rate_limit", [0.0, 0.005])
+def test_drift_filter_matches_the_oracle(rate_limit):
+    """ccpt_drift_filter is host code: the same stream in one call and in
+    three pieces (state carried) against the oracle's Eq. 10-12."""
+    import numpy as np
+    from oracle import ccpt_oracle as O
+    from paper_2310_08770_amd import drift_filter
+    rng = np.random.Generator(np.random.PCG64(3))
+    r = np.cumsum(rng.normal(0, 0.2, size=(300, 2)), axis=0) + 0.5
+    _, want = O.drift_filter(r, 0.05, rate_limit)
+    got, _ = drift_filter(r, 0.05, rate_limit)
+    assert np.max(np.abs(got - want)) <= 1e-12
+    st = None
+    parts = []
+    for a, b in ((0, 70), (70, 71), (71, 300)):
+        p, st = drift_filter(r[a:b], 0.05, rate_limit, st)
+        parts.append(p)
+    assert np.max(np.abs(np.vstack(parts) - want)) <= 1e-12
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libccpt.so not built")
+def test_drift_filter_rejects_bad_arguments():
+    lib = ctypes.CDLL(LIB)
+    lib.ccpt_drift_filter.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    st = (ctypes.c_double * 2)()
+    assert lib.ccpt_drift_filter(None, 3, 0.1, 0.0, st, None) == -1
+    assert lib.ccpt_drift_filter(None, 0, 1.5, 0.0, st, None) == -1
+    assert lib.ccpt_drift_filter(None, 0, 0.1, -1.0, st, None) == -1

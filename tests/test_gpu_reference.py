@@ -1,5 +1,5 @@
-"""Offline reference of Sec. III.A (Eq. 8) on the GPU against the FP64
-oracle: the aligned mean for given displacements, and whole passes."""
+"""Reference updates on the GPU against the FP64 oracle: the offline mean of
+aligned frames (Sec. III.A, Eq. 8) and the real-time low-pass (Sec. III.B, Eq. 9)."""
 import sys
 
 import numpy as np
@@ -108,4 +108,50 @@ def test_three_passes_match_the_oracle(mode):
     assert np.array_equal(r["p"], p_o)
     assert eerr <= 1e-4
     assert derr <= 1e-3
+    tr.close()
+
+
+# ---------------------------------------------------------------- real-time reference (Eq. 9)
+@pytest.mark.parametrize("mode", ["ccu", "ccsn"])
+def test_realtime_matches_the_oracle(mode):
+    say(f"case: gauss64_u20 first 60 frames tracked in order with the Eq. 9 update, a0 = 0.1, {mode}")
+    from paper_2310_08770_amd import Tracker, decode
+    from paper_2310_08770_amd.reference import realtime_track
+    w = S.config1()
+    frames = [np.asarray(f) for f in w.frames[:60]]
+    om = O.MODE_CCU if mode == "ccu" else O.MODE_CCSN
+    res_o = O.realtime_track(frames, w.u, 0.1, om, 200.0)
+    tr = Tracker(upsample=w.u, mode=mode, eps=200.0)
+    r = decode(realtime_track(tr, t(np.stack(frames)), 0.1))
+    d_o = np.array([x["d"] for x in res_o])
+    p_o = np.array([x["p"] for x in res_o])
+    err = np.max(np.abs(r["d"] - d_o), axis=1)
+    say(f"  max |dd| {err.max():.2e} px (frame {int(np.argmax(err))}), last {err[-1]:.2e}")
+    assert np.array_equal(r["p"], p_o)
+    assert err.max() <= 1e-3
+    tr.close()
+
+
+def test_realtime_zero_gain_is_plain_tracking():
+    say("case: Eq. 9 with a0 = 0 (reference never changes) equals tracking against frame 0")
+    from paper_2310_08770_amd import Tracker, decode
+    from paper_2310_08770_amd.reference import realtime_track
+    w = S.config1()
+    fr = t(np.stack(w.frames[:20]))
+    tr = Tracker(upsample=w.u)
+    rt = decode(realtime_track(tr, fr, 0.0))
+    tr.set_reference(fr[0].to(torch.float32))
+    plain = decode(torch.cat([tr.track(fr[i:i + 1]) for i in range(20)]))
+    assert rt.tobytes() == plain.tobytes()
+    tr.close()
+
+
+def test_realtime_update_is_rejected_in_fp64_mode():
+    from paper_2310_08770_amd import Tracker
+    from paper_2310_08770_amd.ccpt import CcptError
+    w = S.config1()
+    tr = Tracker(upsample=w.u, precision="fp64")
+    tr.set_reference(t(w.refs[0], np.float64))
+    with pytest.raises(CcptError):
+        tr.track_update(t(w.frames[0]), 0.1)
     tr.close()
