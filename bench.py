@@ -354,6 +354,28 @@ def main():
                               frames=len(lp))
             log(f"[bench] {name}: p50 {legs[name]['p50_ms']:.3f} ms p99 {legs[name]['p99_ms']:.3f} ms")
             trp.close()
+        # the real-time path of Sec. III.B: each call tracks one frame and
+        # low-pass updates the reference (Eq. 9), a0 = 0.01
+        for mode in ("ccu", "ccsn"):
+            name = f"realtime_{mode}"
+            try:
+                trr = Tracker(upsample=w.u, precision="fp32", mode=mode)
+                trr.set_reference(frames_t[0].to(torch.float32))
+                one = torch.empty((1, 72), dtype=torch.uint8, device=dev)
+                lr = []
+                for i in range(min(args.plain_frames, n) + 50):
+                    t0 = time.perf_counter()
+                    trr.track_update(frames_t[i % n], 0.01, out=one)
+                    torch.cuda.synchronize()
+                    lr.append(time.perf_counter() - t0)
+                lr = np.array(lr[50:])
+                legs[name] = dict(frames_per_s=round(len(lr) / lr.sum(), 1),
+                                  p50_ms=round(float(np.median(lr)) * 1e3, 4),
+                                  p99_ms=round(float(np.percentile(lr, 99)) * 1e3, 4), frames=len(lr))
+                log(f"[bench] {name}: p50 {legs[name]['p50_ms']:.3f} ms p99 {legs[name]['p99_ms']:.3f} ms")
+                trr.close()
+            except Exception as e:  # noqa: BLE001
+                legs[name] = dict(error=str(e)[:200])
         # where a plain call spends its GPU time
         trp = Tracker(upsample=w.u, precision="fp32", profile=True)
         trp.set_reference(ref_t)
