@@ -221,6 +221,35 @@ def leg_grad128(dev, torch, Tracker):
                 adam_step_ms=round(adam * 1e3, 3), loss_first=losses[0], loss_last=losses[-1])
 
 
+# Table I of the paper (CC-SN throughput on an RTX 3080, images/s) at the
+# square shapes, for context beside the same settings here
+TABLE1_RTX3080 = {(256, 128): 981, (256, 256): 432, (256, 512): 189, (256, 1024): 67.0,
+                  (512, 128): 348, (512, 256): 169, (512, 512): 93, (512, 1024): 31.1}
+
+
+def leg_table1(dev, torch, Tracker):
+    """CC-SN (eps = 200) batched split-precision throughput at Table I's
+    square shapes, 256x256 and 512x512, for u = 128, 256, 512, 1024
+    (grids of 192 to 1536 points a side); 512 frames per shape."""
+    from synth import frames as S
+    out = {}
+    for N, gen in ((256, S.config2), (512, S.config4)):
+        w = gen(512)
+        fr = torch.from_numpy(np.stack(w.frames)).to(dev)
+        ref = torch.from_numpy(w.refs[0].astype(np.float32)).to(dev)
+        res = torch.empty((fr.shape[0], 72), dtype=torch.uint8, device=dev)
+        for u in (128, 256, 512, 1024):
+            tr = Tracker(upsample=u, precision="bf16x2", mode="ccsn", eps=200.0)
+            tr.set_reference(ref)
+            rois = tr.rois(fr)
+            dt = _sync_time(lambda: tr.track(None, out=res, rois=rois), 3, torch)
+            out[f"{N}x{N}_u{u}"] = dict(frames_per_s=round(fr.shape[0] / dt, 1),
+                                        paper_rtx3080_images_per_s=TABLE1_RTX3080[(N, u)])
+            tr.close()
+        del fr, res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -389,7 +418,7 @@ def main():
     # ---- the other workloads (each guarded: a failure is recorded, not fatal)
     if not args.no_extra:
         for name, fn in (("uneven_rois_u100", leg_uneven_rois), ("gauss512_u200", leg_gauss512),
-                         ("gauss128_grad", leg_grad128)):
+                         ("gauss128_grad", leg_grad128), ("table1_ccsn", leg_table1)):
             t0 = time.perf_counter()
             try:
                 legs[name] = fn(dev, torch, Tracker)

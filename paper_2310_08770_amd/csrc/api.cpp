@@ -149,8 +149,9 @@ bool split(const ccpt_ctx* ctx) { return ctx->o.precision == CCPT_PREC_BF16X2; }
 
 double step_limit(const ccpt_ctx* ctx) {
   const double grid = 1.0 / ctx->o.upsample;
-  // split-precision grids locate the maximum less exactly than one grid step
-  return split(ctx) ? std::max(grid, kSplitStepLimit) : grid;
+  // FP32 and split-precision grids locate the maximum less exactly than one
+  // grid step at large u; FP64 grids keep the bound of one grid step
+  return fp64(ctx) ? grid : std::max(grid, kReducedStepLimit);
 }
 
 template <typename T>

@@ -130,3 +130,28 @@ def test_gauss128_forward_backward_and_template_optimisation():
     say(f"  loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     assert losses[-1] < 0.8 * losses[0]
     tr.close()
+
+
+
+@pytest.mark.parametrize("N,u", [(256, 128), (256, 512), (256, 1024), (512, 1024)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+def test_large_upsampling_ccsn(N, u, prec):
+    M = int(np.ceil(1.5 * u))
+    say(f"case: {N}x{N} frames at u={u} (M={M}), CC-SN eps=200, {prec}; 3 frames vs oracle")
+    from paper_2310_08770_amd import decode
+    w = S.config2(3) if N == 256 else S.config4(3)
+    ref = np.asarray(w.refs[0], np.float32)
+    tr = tracker(upsample=u, precision=prec, mode="ccsn", eps=200.0)
+    tr.set_reference(t(ref))
+    res = decode(tr.track(t(np.stack(w.frames))))
+    errs = []
+    for i in range(3):
+        o = O.track(w.frames[i], ref.astype(np.float64), u, O.MODE_CCSN, 200.0)
+        if not (o["status"] & O.NEAR_TIE):  # else either integer peak is valid
+            assert tuple(res["p"][i]) == tuple(o["p"])
+        if o["status"] & (O.NEWTON_FALLBACK | O.WINDOW_EXIT):
+            continue
+        errs.append(np.max(np.abs(res["d"][i] - o["d"])))
+    say(f"  max err {max(errs):.2e} px over {len(errs)} frames; statuses {[int(x) for x in res['status']]}")
+    assert max(errs) <= 1e-3
+    tr.close()
