@@ -67,11 +67,14 @@ def gaussian_spot(n: int, sigma: float, peak: float, center=None) -> np.ndarray:
     return peak * g / g0
 
 
-def airy_spot(n: int, first_zero_px: float, peak: float) -> np.ndarray:
+def airy_spot(n, first_zero_px: float, peak: float) -> np.ndarray:
     """Airy-like ring pattern peak * [2 J1(v)/v]^2, v = 3.8317 r / first_zero,
-    sampled at pixel centres around (n/2, n/2)."""
-    r = np.arange(n, dtype=np.float64) - n / 2
-    rr = np.hypot(r[:, None], r[None, :])
+    sampled at pixel centres around (ny/2, nx/2); n is the side of a square
+    image or its (ny, nx) shape."""
+    ny, nx = (n, n) if np.isscalar(n) else n
+    ry = np.arange(ny, dtype=np.float64) - ny / 2
+    rx = np.arange(nx, dtype=np.float64) - nx / 2
+    rr = np.hypot(ry[:, None], rx[None, :])
     v = J1_ZERO * rr / first_zero_px
     with np.errstate(invalid="ignore", divide="ignore"):
         a = np.where(v > 0, 2.0 * j1(v) / np.where(v > 0, v, 1.0), 1.0)
@@ -237,6 +240,27 @@ def config5(n_frames: int = 1024) -> Workload:
     frames = _make_frames(spot, 0.0, shifts, 4, None, np.float32)
     return Workload("gauss128_grad", frames, [spot.copy()], np.zeros(n_frames, np.int32),
                     shifts, "f32", 100, dict(sigma=3.0, peak=2000.0, bg=0.0))
+
+
+#: frame shapes (rows, columns) of Table I of the paper
+TABLE1_SHAPES = [(128, 256), (256, 256), (256, 512), (512, 512), (128, 1024)]
+
+
+def table1_frames(ny: int, nx: int, n_frames: int = 512) -> Workload:
+    """Table I shapes: ny x nx 12-bit Airy rings (first zero 8 px, peak 4000,
+    background 50) as in the streaming case, random-walk shifts with
+    N(0, 0.3 px) steps, u = 128 (Table I's smallest factor).  Seeds depend
+    on the shape, so transposed shapes get their own frames."""
+    k = 100 + 64 * (ny // 64) + nx // 64
+    rng = rng_for(k)
+    steps = rng.normal(0.0, 0.3, size=(n_frames, 2))
+    steps[0] = 0.0
+    shifts = np.cumsum(steps, axis=0)
+    spot = zero_nyquist(airy_spot((ny, nx), 8.0, 4000.0))
+    frames = _make_frames(spot, 50.0, shifts, k, 4095.0, np.uint16)
+    ref = spot + 50.0
+    return Workload(f"airy{ny}x{nx}_u128", frames, [ref], np.zeros(n_frames, np.int32),
+                    shifts, "u16", 128, dict(peak=4000.0, bg=50.0, first_zero=8.0))
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

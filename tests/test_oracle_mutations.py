@@ -114,3 +114,28 @@ def test_drift_filter_without_rate_limit_is_caught(monkeypatch):
     good = O.drift_filter
     monkeypatch.setattr(O, "drift_filter", lambda r, a0, rate_limit=0.0: good(r, a0))
     _fails(P.test_p15_rate_limit_bounds_every_step_and_is_inactive_for_small_steps)
+
+
+def test_swapped_axis_lengths_on_rectangles_are_caught(monkeypatch):
+    """Each axis's basis taken with the other axis's length: invisible on
+    squares, caught by the rectangular pins."""
+    good_bl, good_grid = O.bandlimited, O.upsampled_grid
+
+    def bad_bl(X, s, dy=0, dx=0):
+        ny, nx = X.shape
+        vy = O.phi(nx, s[0], dy)[:ny] if nx >= ny else np.resize(O.phi(nx, s[0], dy), ny)
+        vx = O.phi(ny, s[1], dx)[:nx] if ny >= nx else np.resize(O.phi(ny, s[1], dx), nx)
+        return float((vy @ X @ vx).real) / (ny * nx)
+
+    def bad_grid(X, p, u):
+        ny, nx = X.shape
+        off = O.grid_offsets(u)
+        Ky = np.stack([np.resize(O.phi(nx, p[0] + o), ny) for o in off])
+        Kx = np.stack([np.resize(O.phi(ny, p[1] + o), nx) for o in off])
+        return (Ky @ X @ Kx.T).real / (ny * nx)
+
+    monkeypatch.setattr(O, "bandlimited", bad_bl)
+    monkeypatch.setattr(O, "upsampled_grid", bad_grid)
+    _fails(P.test_p16_rectangular_subpixel_shifts_of_a_bandlimited_spot, (32, 16), O.MODE_CCU)
+    monkeypatch.setattr(O, "bandlimited", good_bl)
+    monkeypatch.setattr(O, "upsampled_grid", good_grid)

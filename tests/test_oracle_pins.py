@@ -481,3 +481,53 @@ def test_p15_rate_limited_step_response_is_a_ramp():
     R, _ = O.drift_filter(r, a0, lim)
     assert np.allclose(R[:, 0], lim * np.arange(1, 51), atol=1e-15)
     assert np.all(R[:, 1] == 0.0)
+
+
+# ---------------------------------------------------------------- rectangular frames
+RECT = [(32, 16), (16, 48), (24, 64)]
+
+
+@pytest.mark.parametrize("shape", RECT)
+def test_p16_rectangular_integer_rolls_are_exact(shape):
+    """Every tracked roll of a random ny x nx image (ny != nx) is the roll
+    itself: integer peak exact, refinement at the integer lag."""
+    ny, nx = shape
+    rng = _rng(ny * 100 + nx)
+    ref = rng.random(shape) * 100.0
+    for dy, dx in [(0, 0), (3, -5), (-ny // 2, nx // 2 - 1), (ny // 2 - 1, -nx // 2)]:
+        r = O.track(np.roll(ref, (dy, dx), axis=(0, 1)), ref, 20)
+        assert tuple(r["p"]) == (dy, dx)
+        assert np.max(np.abs(r["d"] - (dy, dx))) <= 1e-9
+
+
+@pytest.mark.parametrize("shape", RECT)
+@pytest.mark.parametrize("mode", [O.MODE_CCU, O.MODE_CCSN])
+def test_p16_rectangular_subpixel_shifts_of_a_bandlimited_spot(shape, mode):
+    """Noiseless phase-ramp shifts of a Nyquist-free spot on a rectangle:
+    CC-U recovers them to FP64 rounding (the band-limited correlation of a
+    translate peaks at the translation); CC-SN on the same spot to its own
+    bias, which vanishes for a symmetric spot shifted along one axis."""
+    ny, nx = shape
+    spot = S.zero_nyquist(S.airy_spot(shape, 3.0, 1000.0) + 20.0)
+    if mode == O.MODE_CCU:
+        for d in [(0.3, -0.45), (-1.2, 0.8), (0.0, 1.37)]:
+            r = O.track(S.phase_ramp_shift(spot, d), spot, 50)
+            assert np.max(np.abs(r["d"] - d)) <= 1e-9, (d, r["d"])
+    else:
+        r = O.track(spot, spot, 50, mode, 200.0)
+        assert np.max(np.abs(r["d"])) <= 1e-9
+
+
+@pytest.mark.parametrize("shape", RECT)
+@pytest.mark.parametrize("mode", [O.MODE_CCU, O.MODE_CCSN])
+def test_p16_transposed_frames_give_transposed_results(shape, mode):
+    """Tracking the transposes of frame and reference swaps the two axes of
+    every output (the method treats the axes alike)."""
+    rng = _rng(7 * shape[0] + shape[1])
+    spot = S.zero_nyquist(S.airy_spot(shape, 4.0, 800.0)) + 10.0
+    frame = rng.poisson(np.maximum(S.phase_ramp_shift(spot, (0.4, -0.7)), 0.0)).astype(np.float64)
+    a = O.track(frame, spot, 30, mode, 200.0)
+    b = O.track(frame.T.copy(), spot.T.copy(), 30, mode, 200.0)
+    assert tuple(b["p"]) == tuple(a["p"][::-1])
+    assert np.max(np.abs(b["d"] - a["d"][::-1])) <= 1e-10
+    assert abs(b["peak"] - a["peak"]) <= 1e-10 * abs(a["peak"])
