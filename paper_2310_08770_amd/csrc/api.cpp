@@ -27,6 +27,32 @@ bool supported_size(int n) {
   return m == 1;
 }
 
+// Shape codes.  A square N x N frame has code N.  A rectangle has code
+// kRectCode | trans | NY << 11 | NX, NY x NX being its tall kernel shape
+// (one of CCPT_FOR_RECT); trans is set when the frame itself is wide (NX rows
+// of NY pixels), which the kernels read transposed.  Tables are shared by
+// both orientations (key without the trans bit).
+constexpr int kRectCode = 1 << 24;
+constexpr int kTransBit = 1 << 23;
+bool is_rect(int code) { return (code & kRectCode) != 0; }
+int code_ny(int code) { return is_rect(code) ? (code >> 11) & 2047 : code; }
+int code_nx(int code) { return is_rect(code) ? code & 2047 : code; }
+int code_trans(int code) { return is_rect(code) && (code & kTransBit) ? 1 : 0; }
+int table_key(int code) { return code & ~kTransBit; }
+
+// The code of an ny x nx frame, 0 if the shape is not supported.
+int shape_code(int ny, int nx) {
+  if (ny == nx) return supported_size(ny) ? ny : 0;
+  const int a = std::max(ny, nx), b = std::min(ny, nx);
+  bool ok = false;
+#define CASE(p, q) \
+  if (a == p && b == q) ok = true;
+  CCPT_FOR_RECT(CASE)
+#undef CASE
+  if (!ok) return 0;
+  return kRectCode | (ny < nx ? kTransBit : 0) | (a << 11) | b;
+}
+
 struct SizeTables {
   float2* tw = nullptr;  // N
   void* ky = nullptr;
@@ -40,7 +66,7 @@ struct SizeTables {
 };
 
 struct Ref {
-  int n = 0;
+  int n = 0;                  // shape code
   float2* spec = nullptr;     // conj F[B], N x (N/2+1) (the adjoint always uses it)
   double2* spec64 = nullptr;  // the same in FP64 (FP64 mode)
   float* img = nullptr;       // E as float (N x N), kept for the CC-SN chain rule
@@ -161,11 +187,13 @@ int upload(ccpt_ctx* ctx, T*& dst, const std::vector<T>& src) {
   return CCPT_OK;
 }
 
-int ensure_tables(ccpt_ctx* ctx, int n) {
-  if (ctx->tables.count(n)) return CCPT_OK;
+int ensure_tables(ccpt_ctx* ctx, int code) {
+  const int key = table_key(code);
+  if (ctx->tables.count(key)) return CCPT_OK;
+  const int n = code_ny(code), nx = code_nx(code);
   SizeTables t;
   // the FP64 mode keeps the FP32 tables too (twiddles of the adjoint and Fisher paths)
-  HostTables h = build_tables(n, ctx->o.upsample, ctx->M, ctx->c,
+  HostTables h = build_tables(n, nx, ctx->o.upsample, ctx->M, ctx->c,
                               fp64(ctx) ? CCPT_PREC_FP32 : ctx->o.precision);
   t.Mp = h.Mp;
   HIP_CHECK(ctx, hipMalloc(&t.tw, h.tw.size() * sizeof(float2)));
@@ -181,7 +209,7 @@ int ensure_tables(ccpt_ctx* ctx, int n) {
     if (!rc) rc = upload(ctx, t.wb64, h64.wb);
     if (rc) return rc;
   }
-  if (split(ctx) && n >= kWideMinN) {
+  if (split(ctx) && nx >= kWideMinN) {
     const size_t words = (size_t)n * 2 * kfold_rows(t.Mp) * xb_pitch(n);
     if (hipMalloc(&t.kfold, words * sizeof(unsigned)) != hipSuccess)
       return fail(ctx, CCPT_E_NOMEM, "folded table of %zu bytes", words * sizeof(unsigned));
@@ -189,7 +217,7 @@ int ensure_tables(ccpt_ctx* ctx, int n) {
       return fail(ctx, CCPT_E_HIP, "folded table launch failed");
     HIP_CHECK(ctx, hipDeviceSynchronize());
   }
-  ctx->tables[n] = t;
+  ctx->tables[key] = t;
   return CCPT_OK;
 }
 
@@ -217,9 +245,10 @@ int ensure_ws(ccpt_ctx* ctx, size_t bytes) {
   return CCPT_OK;
 }
 
-size_t spec_elems(int n) { return (size_t)n * (n / 2 + 1); }
+// Half-spectrum elements and split-precision words of one frame (shape code).
+size_t spec_elems(int code) { return (size_t)code_ny(code) * (code_nx(code) / 2 + 1); }
 
-size_t split_words(int n) { return (size_t)2 * (n / 2) * xb_pitch(n); }
+size_t split_words(int code) { return (size_t)2 * (code_nx(code) / 2) * xb_pitch(code_ny(code)); }
 
 size_t frame_ws_bytes(int n, int precision) {
   if (precision == CCPT_PREC_FP64)
@@ -274,9 +303,9 @@ int check_image(ccpt_ctx* ctx, const void* data, int ny, int nx, int pitch, int 
     return fail(ctx, CCPT_E_INVALID, "%s %d: unknown dtype %d", what, idx, dtype);
   if (ny <= 0 || nx <= 0 || pitch < nx)
     return fail(ctx, CCPT_E_INVALID, "%s %d: bad shape %dx%d pitch %d", what, idx, ny, nx, pitch);
-  if (ny != nx || !supported_size(nx))
-    return fail(ctx, CCPT_E_UNSUPPORTED, "%s %d: %dx%d is not a supported square size", what,
-                idx, ny, nx);
+  if (!shape_code(ny, nx))
+    return fail(ctx, CCPT_E_UNSUPPORTED, "%s %d: %dx%d is not a supported shape", what, idx, ny,
+                nx);
   const size_t align = dtype_bytes(dtype);
   if ((uintptr_t)data % align)
     return fail(ctx, CCPT_E_INVALID, "%s %d: misaligned data", what, idx);
@@ -290,13 +319,23 @@ double pixel(const void* raw, int dtype, size_t k) {
   return (double)((const float*)raw)[k];
 }
 
+// Calls that work on square frames only (the adjoint, the Fisher information
+// and the reference updates).
+int require_square(ccpt_ctx* ctx, int ny, int nx, const char* what) {
+  if (ny != nx)
+    return fail(ctx, CCPT_E_UNSUPPORTED, "%s: %dx%d frames are tracked, but this call takes square "
+                "frames only", what, ny, nx);
+  return CCPT_OK;
+}
+
 GroupParams base_params(ccpt_ctx* ctx, int n) {
   GroupParams g{};
-  g.tw = ctx->tables[n].tw;
+  g.tw = ctx->tables[table_key(n)].tw;
   g.mode = ctx->o.mode;
   g.eps = (float)ctx->o.eps;
   g.eps64 = ctx->o.eps;
-  g.tw64 = ctx->tables[n].tw64;
+  g.tw64 = ctx->tables[table_key(n)].tw64;
+  g.trans = code_trans(n);
   g.u = ctx->o.upsample;
   g.M = ctx->M;
   g.c = ctx->c;
@@ -343,18 +382,19 @@ Marker marker_of(ccpt_ctx* ctx, hipStream_t s) {
 // (0 when the launch is large enough to fill the GPU without splitting).
 size_t split_partials_bytes(const ccpt_ctx* ctx, int n, int count) {
   if (ctx->o.precision != CCPT_PREC_FP32) return 0;
-  auto it = ctx->tables.find(n);
+  auto it = ctx->tables.find(table_key(n));
   if (it == ctx->tables.end()) return 0;
   const int mtiles = it->second.Mp / 32;
   if ((long)count * mtiles >= kSplitMaxBlocks) return 0;
-  return (size_t)count * mtiles * kSplitSlices * 32 * stage_b_k(n) * sizeof(float);
+  return (size_t)count * mtiles * kSplitSlices * 32 * stage_b_k(code_nx(n)) * sizeof(float);
 }
 
 // Launches the whole tracking sequence for one size group, chunk by chunk.
 int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int count,
               ccpt_result* out, hipStream_t s) {
   const int chunk = std::min(count, chunk_for(ctx, n));
-  SizeTables& t = ctx->tables[n];
+  SizeTables& t = ctx->tables[table_key(n)];
+  const int ny = code_ny(n), nx = code_nx(n);
   UpdftTables ut{t.ky, t.wb, t.Mp, ctx->o.precision, t.kfold};
   const Marker mark = marker_of(ctx, s);
   for (int c0 = 0; c0 < count; c0 += chunk) {
@@ -368,14 +408,15 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
     g.ypart = (yb && yb <= ctx->ypart_cap) ? (float*)ctx->ypart : nullptr;
     g.nparts = (double*)ctx->nparts;
     ctx->st_dirty = true;  // until this chunk's Newton launch has gone in
-    if ((fp64(ctx) ? launch_xcorr64(n, g, s, mark) : launch_xcorr(n, g, s, mark)))
+    if ((fp64(ctx) ? launch_xcorr64(n, g, s, mark) : launch_xcorr(ny, nx, g, s, mark)))
       return fail(ctx, CCPT_E_HIP, "correlation launch failed");
     mark(CCPT_STAGE_UPDFT, 1);
-    if ((fp64(ctx) ? launch_updft64(n, g, t.ky64, t.wb64, t.Mp, s) : launch_updft(n, g, ut, s)))
+    if ((fp64(ctx) ? launch_updft64(n, g, t.ky64, t.wb64, t.Mp, s)
+                   : launch_updft(ny, nx, g, ut, s)))
       return fail(ctx, CCPT_E_HIP, "upsampled DFT launch failed");
     mark(CCPT_STAGE_UPDFT, 0);
     mark(CCPT_STAGE_NEWTON, 1);
-    if (launch_newton(n, g, step_limit(ctx), s))
+    if (launch_newton(ny, nx, g, step_limit(ctx), s))
       return fail(ctx, CCPT_E_HIP, "Newton launch failed");
     mark(CCPT_STAGE_NEWTON, 0);
     ctx->st_dirty = false;
@@ -386,29 +427,33 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
 
 // Validated, size-grouped descriptors of a roi array.
 struct Plan {
-  std::vector<FrameDesc> desc;  // grouped by size, largest first
-  std::vector<int> sig;         // (size, count) pairs of the groups
+  std::vector<FrameDesc> desc;  // grouped by shape, largest first
+  std::vector<int> sig;         // (shape code, count) pairs of the groups
 };
 
 // fp32_spec: point the descriptors at the FP32 reference spectra whatever
 // the precision (the adjoint works in FP32).
 int plan_rois(ccpt_ctx* ctx, const ccpt_roi* rois, int n, Plan& plan, bool fp32_spec = false) {
   if (ctx->refs.empty()) return fail(ctx, CCPT_E_NOREF, "no reference set");
+  std::vector<int> code(n);
   for (int i = 0; i < n; ++i) {
     const ccpt_roi& r = rois[i];
     int rc = check_image(ctx, r.data, r.ny, r.nx, r.pitch, r.dtype, "roi", i);
     if (rc) return rc;
     if (r.ref_id < 0 || r.ref_id >= (int)ctx->refs.size())
       return fail(ctx, CCPT_E_NOREF, "roi %d: reference id %d not set", i, r.ref_id);
-    if (ctx->refs[r.ref_id].n != r.nx)
-      return fail(ctx, CCPT_E_INVALID, "roi %d: size %d differs from reference %d (%d)", i, r.nx,
-                  r.ref_id, ctx->refs[r.ref_id].n);
+    code[i] = shape_code(r.ny, r.nx);
+    if (ctx->refs[r.ref_id].n != code[i])
+      return fail(ctx, CCPT_E_INVALID, "roi %d: shape %dx%d differs from reference %d", i, r.ny,
+                  r.nx, r.ref_id);
   }
-  // group by size, largest first (they take longest); stable within a size
+  // group by shape, largest first (they take longest); stable within a shape
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return rois[a].nx > rois[b].nx; });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const long pa = (long)rois[a].ny * rois[a].nx, pb = (long)rois[b].ny * rois[b].nx;
+    return pa != pb ? pa > pb : code[a] > code[b];
+  });
   plan.desc.resize(n);
   plan.sig.clear();
   for (int k = 0; k < n; ++k) {
@@ -422,8 +467,8 @@ int plan_rois(ccpt_ctx* ctx, const ccpt_roi* rois, int n, Plan& plan, bool fp32_
     d.out_idx = order[k];
     d.ref_id = r.ref_id;
     plan.desc[k] = d;
-    if (plan.sig.empty() || plan.sig[plan.sig.size() - 2] != r.nx) {
-      plan.sig.push_back(r.nx);
+    if (plan.sig.empty() || plan.sig[plan.sig.size() - 2] != code[order[k]]) {
+      plan.sig.push_back(code[order[k]]);
       plan.sig.push_back(0);
     }
     plan.sig.back()++;
@@ -634,6 +679,9 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
     rc = check_image(ctx, refs[i].data, refs[i].ny, refs[i].nx, refs[i].pitch, refs[i].dtype,
                      "reference", i);
     if (rc) return rc;
+    if (fp64(ctx) && refs[i].ny != refs[i].nx)
+      return fail(ctx, CCPT_E_UNSUPPORTED, "reference %d: the FP64 mode takes square frames only",
+                  i);
   }
   HIP_CHECK(ctx, hipStreamSynchronize(s));
   // read the references back: the CC-SN domain check and the context's own copy
@@ -667,20 +715,24 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
   // scratch: one spectrum (FP64 size) plus the FP64 image of the FP64 mode
   size_t tmp_need = 0;
   for (int i = 0; i < n_refs; ++i) {
-    const int n = refs[i].nx;
-    tmp_need = std::max(tmp_need, spec_elems(n) * sizeof(double2) + (size_t)n * n * sizeof(double));
-    rc = ensure_tables(ctx, n);
+    const int code = shape_code(refs[i].ny, refs[i].nx);
+    tmp_need = std::max(tmp_need, spec_elems(code) * sizeof(double2) +
+                                      (size_t)refs[i].ny * refs[i].nx * sizeof(double));
+    rc = ensure_tables(ctx, code);
     if (rc) return rc;
   }
   char* tmp = nullptr;
   HIP_CHECK(ctx, hipMalloc(&tmp, tmp_need));
   float2* T = (float2*)tmp;
   for (int i = 0; i < n_refs; ++i) {
-    const int n = refs[i].nx;
+    const int n = refs[i].nx;  // (square frames: the size)
+    const int code = shape_code(refs[i].ny, refs[i].nx);
+    const size_t npx = (size_t)refs[i].ny * refs[i].nx;
+    const SizeTables& st = ctx->tables[table_key(code)];
     Ref r;
-    r.n = n;
-    if (hipMalloc(&r.spec, spec_elems(n) * sizeof(float2)) != hipSuccess ||
-        hipMalloc(&r.img, (size_t)n * n * sizeof(float)) != hipSuccess ||
+    r.n = code;
+    if (hipMalloc(&r.spec, spec_elems(code) * sizeof(float2)) != hipSuccess ||
+        hipMalloc(&r.img, npx * sizeof(float)) != hipSuccess ||
         (fp64(ctx) && hipMalloc(&r.spec64, spec_elems(n) * sizeof(double2)) != hipSuccess)) {
       (void)hipFree(tmp);
       if (r.spec) (void)hipFree(r.spec);
@@ -689,15 +741,15 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
     }
     ctx->refs.push_back(r);
     std::vector<float> img32(host[i].begin(), host[i].end());
-    HIP_CHECK(ctx, hipMemcpy(r.img, img32.data(), (size_t)n * n * sizeof(float),
-                             hipMemcpyHostToDevice));
+    HIP_CHECK(ctx, hipMemcpy(r.img, img32.data(), npx * sizeof(float), hipMemcpyHostToDevice));
     const int weight = ctx->o.mode == CCPT_MODE_CCSN ? 1 : 0;
-    if (launch_spectrum(n, r.img, CCPT_F32, n, 0, 1, weight, (float)ctx->o.eps, 1, T, r.spec,
-                        ctx->tables[n].tw, s)) {
+    // the image is stored as given (pitch nx); a wide one is read transposed
+    if (launch_spectrum(code_ny(code), code_nx(code), r.img, CCPT_F32, refs[i].nx, 0,
+                        code_trans(code), 1, weight, (float)ctx->o.eps, 1, T, r.spec, st.tw, s)) {
       (void)hipFree(tmp);
       return fail(ctx, CCPT_E_HIP, "reference spectrum launch failed");
     }
-    if (ctx->o.mode == CCPT_MODE_CCSN) {
+    if (ctx->o.mode == CCPT_MODE_CCSN && !is_rect(code)) {
       // F[E] itself, the state of real-time updates (B = -1/(E+eps) is not linear in E)
       Ref& rr = ctx->refs.back();
       if (hipMalloc(&rr.espec, spec_elems(n) * sizeof(float2)) != hipSuccess) {
@@ -705,7 +757,7 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
         return fail(ctx, CCPT_E_NOMEM, "reference spectra");
       }
       HIP_CHECK(ctx, hipStreamSynchronize(s));
-      if (launch_spectrum(n, r.img, CCPT_F32, n, 0, 1, 0, 0.f, 0, T, rr.espec, ctx->tables[n].tw, s)) {
+      if (launch_spectrum(n, n, r.img, CCPT_F32, n, 0, 0, 1, 0, 0.f, 0, T, rr.espec, st.tw, s)) {
         (void)hipFree(tmp);
         return fail(ctx, CCPT_E_HIP, "reference spectrum launch failed");
       }
@@ -812,6 +864,10 @@ int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_resul
   int rc = set_device(ctx);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < n; ++i) {
+    rc = require_square(ctx, rois[i].ny, rois[i].nx, "ccpt_track_grad");
+    if (rc) return rc;
+  }
   Plan plan;
   rc = plan_rois(ctx, rois, n, plan, true);
   if (rc) return rc;
@@ -925,6 +981,7 @@ int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* strea
   if (!ctx) return CCPT_E_INVALID;
   if (!mu || !fisher) return fail(ctx, CCPT_E_INVALID, "null argument");
   int rc = check_image(ctx, mu->data, mu->ny, mu->nx, mu->pitch, mu->dtype, "mean image", 0);
+  if (!rc) rc = require_square(ctx, mu->ny, mu->nx, "ccpt_fisher");
   if (rc) return rc;
   rc = set_device(ctx);
   if (rc) return rc;
@@ -957,7 +1014,8 @@ int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* strea
   float* ix = iy + (size_t)n * n;
   double* part = (double*)(((uintptr_t)(ix + (size_t)n * n) + 15) & ~(uintptr_t)15);
   const float2* tw = ctx->tables[n].tw;
-  int bad = launch_spectrum(n, mu->data, mu->dtype, mu->pitch, 0, 1, 0, 0.f, 0, T, F, tw, s) ||
+  int bad = launch_spectrum(n, n, mu->data, mu->dtype, mu->pitch, 0, 0, 1, 0, 0.f, 0, T, F, tw,
+                            s) ||
             launch_fisher_deriv(n, F, Dy, Dx, s) || launch_inverse(n, Dy, 1, 2.0f, T, iy, tw, s) ||
             launch_inverse(n, Dx, 1, 2.0f, T, ix, tw, s) ||
             launch_fisher_reduce(iy, ix, mu->data, mu->dtype, mu->pitch, n, part, nblocks, fisher, s);
@@ -980,6 +1038,7 @@ int ccpt_mean_aligned(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_res
   for (int i = 0; i < n; ++i) {
     const ccpt_roi& r = rois[i];
     rc = check_image(ctx, r.data, r.ny, r.nx, r.pitch, r.dtype, "roi", i);
+    if (!rc) rc = require_square(ctx, r.ny, r.nx, "ccpt_mean_aligned");
     if (rc) return rc;
     if (r.nx != N) return fail(ctx, CCPT_E_INVALID, "roi %d: size %d differs from %d", i, r.nx, N);
     desc[i] = FrameDesc{r.data, nullptr, r.pitch, r.dtype, i, 0};
@@ -1019,7 +1078,9 @@ int ccpt_track_update(ccpt_ctx* ctx, const ccpt_roi* roi, double a0, ccpt_result
   if (!roi || !out || !(a0 >= 0.0 && a0 <= 1.0))
     return fail(ctx, CCPT_E_INVALID, "bad arguments");
   if (fp64(ctx)) return fail(ctx, CCPT_E_UNSUPPORTED, "real-time updates need FP32 or BF16X2 precision");
-  int rc = ccpt_track_batch(ctx, roi, 1, out, stream);  // validates roi and reference id
+  int rc = require_square(ctx, roi->ny, roi->nx, "ccpt_track_update");
+  if (rc) return rc;
+  rc = ccpt_track_batch(ctx, roi, 1, out, stream);  // validates roi and reference id
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   Ref& R = ctx->refs[roi->ref_id];
@@ -1041,7 +1102,8 @@ int ccpt_track_update(ccpt_ctx* ctx, const ccpt_roi* roi, double a0, ccpt_result
     // update F[E], then E, then conj F[-1/(E+eps)]
     if (launch_rt_update(N, out, F, R.espec, fa0, fb1, 0, s) ||
         launch_inverse(N, R.espec, 1, 2.0f / ((float)N * (float)N), T, R.img, tw, s) ||
-        launch_spectrum(N, R.img, CCPT_F32, N, 0, 1, 1, (float)ctx->o.eps, 1, T, R.spec, tw, s))
+        launch_spectrum(N, N, R.img, CCPT_F32, N, 0, 0, 1, 1, (float)ctx->o.eps, 1, T, R.spec, tw,
+                        s))
       return fail(ctx, CCPT_E_HIP, "reference update launch failed");
   }
   return CCPT_OK;

@@ -72,7 +72,22 @@ struct GroupParams {
   double2* X64;
   PeakCand* cand;
   const double2* tw64;
+  int trans;              // 1: the frames are wider than tall and are processed as
+                          // their transposes (NY x NX above is the transposed
+                          // shape); integer-peak and grid indices keep the frame's
+                          // own row-major order and the Newton stage writes the
+                          // result in the frame's own axes
 };
+
+// Frame shapes of the kernels: square N x N for N in CCPT_FOR_SIZES, and the
+// rectangles of CCPT_FOR_RECT, always held tall (NY = 2^k NX rows of NX
+// columns) so that the half-spectrum axis of the real transforms is the short
+// one; a wide frame is read transposed.  The twiddle table of a shape holds
+// exp(-2 pi i m / NY), m < NY (NX divides NY).
+#define CCPT_FOR_SIZES(X)                                                                           \
+  X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
+      X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
+#define CCPT_FOR_RECT(X) X(256, 128) X(512, 256) X(1024, 128)
 
 // Launches of fewer than kNewtonSplitMax frames build the first Newton model
 // over kNewtonParts blocks per frame (ky ranges), for latency.
@@ -118,6 +133,33 @@ __host__ __device__ inline unsigned key_index(unsigned long long k) {
   return 0xFFFFFFFFu - (unsigned)(k & 0xFFFFFFFFull);
 }
 
+// Tall-image coordinates (y, x) of the integer peak from its frame row-major
+// index q (trans: the index in a wide frame of NX rows of NY pixels); an
+// index that was never set (cannot happen for a tracked frame) reads as 0.
+template <int NY, int NX>
+__device__ __forceinline__ void peak_yx(unsigned q, int trans, int& y, int& x) {
+  if (q >= (unsigned)(NY * NX)) q = 0;
+  if (NY != NX && trans) {
+    y = (int)(q % NY);
+    x = (int)(q / NY);
+  } else {
+    y = (int)(q / NX);
+    x = (int)(q % NX);
+  }
+}
+
+// Frame row-major index of point (my, mx) of the M x M grid of the tall image.
+__device__ __forceinline__ unsigned grid_index(int my, int mx, int M, bool trans) {
+  return trans ? (unsigned)(mx * M + my) : (unsigned)(my * M + mx);
+}
+
+// The transpose flag of a kernel for frames of NY x NX: always false for
+// square frames, so their kernels carry no code for it.
+template <int NY, int NX>
+__device__ __forceinline__ bool transposed(int trans) {
+  return NY != NX && trans != 0;
+}
+
 // Optional callback around each kernel launch (stage id, begin/end), used
 // to bracket launches with timing events.
 struct Marker {
@@ -135,14 +177,16 @@ struct Marker {
 int launch_init_state(FrameState* st, int count, hipStream_t s);
 
 // Stages 1-3: forward 2-D r2c FFT with the prologue, cross-power spectrum,
-// inverse 2-D c2r FFT and the integer-peak search.
-int launch_xcorr(int N, const GroupParams& g, hipStream_t s, const Marker& mark);
+// inverse 2-D c2r FFT and the integer-peak search, for frames of the kernel
+// shape ny x nx (g.trans: wide frames read transposed).
+int launch_xcorr(int ny, int nx, const GroupParams& g, hipStream_t s, const Marker& mark);
 
-// Forward 2-D r2c FFT of n images (pitch in elements) into spec
-// [n][N][N/2+1]; weight: 0 = identity, 1 = CC-SN reference (-1/(E+eps)),
-// 2 = CC-SN frame ((I+eps)^2).  If conj_out, stores the conjugate.
-int launch_spectrum(int N, const void* data, int dtype, int pitch, long img_stride, int n,
-                    int weight, float eps, int conj_out, float2* T, float2* spec,
+// Forward 2-D r2c FFT of n images (pitch in elements; trans: each image is
+// nx rows of ny and is read transposed) into spec [n][ny][nx/2+1]; weight:
+// 0 = identity, 1 = CC-SN reference (-1/(E+eps)), 2 = CC-SN frame
+// ((I+eps)^2).  If conj_out, stores the conjugate.
+int launch_spectrum(int ny, int nx, const void* data, int dtype, int pitch, long img_stride,
+                    int trans, int n, int weight, float eps, int conj_out, float2* T, float2* spec,
                     const float2* tw, hipStream_t s);
 
 // FP64 mode: the same two calls with every FFT in FP64 (g.T64, g.X64,
@@ -158,10 +202,10 @@ struct UpdftTables {
   const void* wb;    // Stage B operand table
   int Mp;            // padded grid size (multiple of 32)
   int precision;
-  const void* kfold; // split precision, N >= 256: folded K' table for every peak row
+  const void* kfold; // split precision, NX >= 256: folded K' table for every peak row
 };
 
-// Minimum frame size of the wide split-precision kernel (and its folded table).
+// Minimum row length NX of the wide split-precision kernel (and its folded table).
 constexpr int kWideMinN = 256;
 // 32-row grid tiles per block of the wide kernel.
 constexpr int kWideMT = 5;
@@ -172,10 +216,10 @@ __host__ __device__ constexpr int kfold_rows(int Mp) {
   return (Mp / 32 + kWideMT - 1) / kWideMT * kWideMT * 32;
 }
 
-// Builds the folded split table [N][2][rows][xb_pitch(N)] words on the device
-// (rows = kfold_rows(Mp); rows m >= M are zero).
-int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int rows, hipStream_t s);
-int launch_updft(int N, const GroupParams& g, const UpdftTables& t, hipStream_t s);
+// Builds the folded split table [NY][2][rows][xb_pitch(NY)] words on the
+// device for frames of NY rows (rows = kfold_rows(Mp); rows m >= M are zero).
+int launch_build_kfold(unsigned* out, int NY, int u, int M, int c, int rows, hipStream_t s);
+int launch_updft(int ny, int nx, const GroupParams& g, const UpdftTables& t, hipStream_t s);
 
 // FP64 mode: reduces the peak candidates, then the upsampled DFT in FP64 on
 // the vector units; K [Mp][N] and W [N/2+1][Mp] are complex FP64 tables.
@@ -184,7 +228,7 @@ int launch_updft64(int N, const GroupParams& g, const double2* K, const double2*
 
 // Stage 5: FP64 Newton refinement and the result record (from g.X64 when
 // set, else from g.X).
-int launch_newton(int N, const GroupParams& g, double step_limit, hipStream_t s);
+int launch_newton(int ny, int nx, const GroupParams& g, double step_limit, hipStream_t s);
 
 // Inverse 2-D c2r of n half spectra [n][N][N/2+1] into n N x N float images
 // scaled by `scale` (T is scratch of the same size as the spectra).

@@ -272,10 +272,6 @@ static int fisher_deriv_n(const float2* F, float2* Dy, float2* Dx, hipStream_t s
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-#define CCPT_FOR_SIZES(X) \
-  X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
-  X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
-
 int launch_grad_psi(int N, const FrameDesc* desc, int first, int count, const ccpt_result* fwd,
                     const double* g_d, const double* g_peak, const float2* FA, float2* QA,
                     float2* QB, hipStream_t s) {

@@ -93,42 +93,45 @@ constexpr int pow2_floor(int x) {
   return p;
 }
 
-// Work split of one model pass: each column kx < N/2 is shared by S adjacent
-// lanes (ky segments of length SEG); after their moments are combined, lane
-// `seg` accumulates the coefficients with m = seg, seg + S, ... (QM of them).
-template <int N>
+// Work split of one model pass over a spectrum of NY rows and NX/2+1
+// columns: each column kx < NX/2 is shared by S adjacent lanes (ky segments
+// of length SEG); after their moments are combined, lane `seg` accumulates
+// the coefficients with m = seg, seg + S, ... (QM of them).
+template <int NY, int NX>
 struct ModelSplit {
-  static constexpr int NC = N / 2;
+  static constexpr int NC = NX / 2;
   static constexpr int S0 = kNThreads / NC;
-  static constexpr int S = pow2_floor(S0 < 64 ? (S0 < N ? S0 : N) : 64);
-  static constexpr int SEG = (N + S - 1) / S;
+  static constexpr int S = pow2_floor(S0 < 64 ? (S0 < NY ? S0 : NY) : 64);
+  static constexpr int SEG = (NY + S - 1) / S;
   static constexpr int QM = (kOrder + S) / S;
 };
 
 // One pass: the model coefficients around (sy, sx) into coef (LDS), from
 // the spectrum rows ky_lo <= ky < ky_hi (all rows: the full model; a range:
 // its share, the coefficients being linear in the spectrum).  CX is the
-// spectrum's element type (float2, or double2 in FP64 mode).
-template <int N, typename CX>
+// spectrum's element type (float2, or double2 in FP64 mode).  Frames are
+// NY rows of NX (a_ky = 2 pi ky~ / NY, b_kx = 2 pi kx / NX, 1/N^2 becomes
+// 1/(NY NX)).
+template <int NY, int NX, typename CX>
 __device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, double2* phy,
                             double* ay, double (*red)[kOrder + 1][kOrder + 1],
                             double (*nred)[2 * (kOrder + 1)], double* coef, int ky_lo = 0,
-                            int ky_hi = N) {
-  using MS = ModelSplit<N>;
-  constexpr int H = N / 2 + 1;
+                            int ky_hi = NY) {
+  using MS = ModelSplit<NY, NX>;
+  constexpr int H = NX / 2 + 1;
   constexpr int NC = MS::NC, S = MS::S, QM = MS::QM;
   const double pi = 3.14159265358979323846;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int ky = tid; ky < N; ky += kNThreads) {
-    if (2 * ky == N) {
+  for (int ky = tid; ky < NY; ky += kNThreads) {
+    if (2 * ky == NY) {
       phy[ky] = make_double2(0.0, 0.0);  // the Nyquist row is added separately
       ay[ky] = 0.0;
     } else {
-      const int kt = 2 * ky < N ? ky : ky - N;
+      const int kt = 2 * ky < NY ? ky : ky - NY;
       double sn, cs;
-      sincospi(2.0 * (double)kt * sy / (double)N, &sn, &cs);
+      sincospi(2.0 * (double)kt * sy / (double)NY, &sn, &cs);
       phy[ky] = make_double2(cs, sn);
-      ay[ky] = 2.0 * pi * (double)kt / (double)N;
+      ay[ky] = 2.0 * pi * (double)kt / (double)NY;
     }
   }
   __syncthreads();
@@ -161,8 +164,8 @@ __device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, dou
                                  (double)xf.x * ph.y + (double)xf.y * ph.x),
                  ay[ky]);
     }
-    if (y0 <= N / 2 && N / 2 < y1) {
-      const CX xf = col[(size_t)(N / 2) * H];
+    if (y0 <= NY / 2 && NY / 2 < y1) {
+      const CX xf = col[(size_t)(NY / 2) * H];
 #pragma unroll
       for (int n = 0; n <= kOrder; ++n) {
         M[n].x += (double)xf.x * ry[n];
@@ -184,10 +187,10 @@ __device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, dou
 #pragma unroll
     for (int n = 0; n <= kOrder; ++n) acc[q][n] = 0.0;
   if (kx < NC) {
-    const double b = 2.0 * pi * (double)kx / (double)N;
+    const double b = 2.0 * pi * (double)kx / (double)NX;
     const double w = kx == 0 ? 1.0 : 2.0;
     double sn, cs;
-    sincospi(2.0 * (double)kx * sx / (double)N, &sn, &cs);
+    sincospi(2.0 * (double)kx * sx / (double)NX, &sn, &cs);
     double2 P = make_double2(cs, sn);
     for (int k = 0; k < seg && k <= kOrder; ++k) P = make_double2(-b * P.y, b * P.x);
 #pragma unroll
@@ -218,13 +221,13 @@ __device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, dou
         for (int n = 0; n <= kOrder; ++n) red[wave][m][n] = acc[q][n];
     }
   }
-  // ---- Nyquist column kx = N/2: one row per thread
+  // ---- Nyquist column kx = NX/2: one row per thread
   double2 Mn[kOrder + 1];
 #pragma unroll
   for (int n = 0; n <= kOrder; ++n) Mn[n] = make_double2(0.0, 0.0);
   for (int ky = ky_lo + tid; ky < ky_hi; ky += kNThreads) {
     const CX xf = Xf[(size_t)ky * H + NC];
-    if (2 * ky == N) {
+    if (2 * ky == NY) {
 #pragma unroll
       for (int n = 0; n <= kOrder; ++n) {
         Mn[n].x += (double)xf.x * ry[n];
@@ -269,7 +272,7 @@ __device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, dou
     double2 P = make_double2(cs, sn);
     for (int k = 0; k < m; ++k) P = make_double2(-pi * P.y, pi * P.x);
     v += P.x * mr;
-    coef[coef_index(n, m)] = v / ((double)N * (double)N);
+    coef[coef_index(n, m)] = v / ((double)NY * (double)NX);
   }
   __syncthreads();
 }
@@ -287,32 +290,32 @@ __device__ void write_special(ccpt_result* out, unsigned status) {
   *out = r;
 }
 
-// Integer peak (py, px) and grid estimate (dgy, dgx) of a frame from its state.
-template <int N>
+// Integer peak (py, px) and grid estimate (dgy, dgx) of a frame from its
+// state, in the axes of the tall image.
+template <int NY, int NX>
 __device__ void grid_seed(const GroupParams& g, const FrameState& st, int& py, int& px,
                           double& dgy, double& dgx) {
-  unsigned pk = key_index(st.peak_key);
-  if (pk >= (unsigned)(N * N)) pk = 0;
-  py = pk / N;
-  px = pk % N;
-  if (2 * py >= N) py -= N;
-  if (2 * px >= N) px -= N;
+  peak_yx<NY, NX>(key_index(st.peak_key), g.trans, py, px);
+  if (2 * py >= NY) py -= NY;
+  if (2 * px >= NX) px -= NX;
   unsigned gk = key_index(st.grid_key);
   if (gk >= (unsigned)(g.M * g.M)) gk = (unsigned)(g.c * g.M + g.c);
-  const int my = gk / g.M, mx = gk % g.M;
+  // (the grid index is the frame's row-major one: transposed for a wide frame)
+  const bool tr = transposed<NY, NX>(g.trans);
+  const int my = tr ? gk % g.M : gk / g.M, mx = tr ? gk / g.M : gk % g.M;
   dgy = py + (double)(my - g.c) / g.u;
   dgx = px + (double)(mx - g.c) / g.u;
 }
 
 // Small launches: block b of frame f builds the first model's share of the
-// spectrum rows b N / nb <= ky < (b + 1) N / nb around the grid estimate and
-// stores its coefficients to parts[f][b]; the Newton kernel adds the shares
-// in block order.
-template <int N, typename CX>
+// spectrum rows b NY / nb <= ky < (b + 1) NY / nb around the grid estimate
+// and stores its coefficients to parts[f][b]; the Newton kernel adds the
+// shares in block order.
+template <int NY, int NX, typename CX>
 __global__ void __launch_bounds__(kNThreads) k_newton_part(GroupParams g, double* __restrict__ parts,
                                                            int nb) {
-  __shared__ double2 phy[N];
-  __shared__ double ay[N];
+  __shared__ double2 phy[NY];
+  __shared__ double ay[NY];
   __shared__ double red[kNThreads / 64][kOrder + 1][kOrder + 1];
   __shared__ double nred[kNThreads / 64][2 * (kOrder + 1)];
   __shared__ double coef[kCoef];
@@ -321,18 +324,18 @@ __global__ void __launch_bounds__(kNThreads) k_newton_part(GroupParams g, double
   if ((st.flags & CCPT_ST_NONFINITE) || st.amin == st.amax) return;  // no model needed
   int py, px;
   double dgy, dgx;
-  grid_seed<N>(g, st, py, px, dgy, dgx);
+  grid_seed<NY, NX>(g, st, py, px, dgy, dgx);
   const CX* Xf = (sizeof(CX) == sizeof(float2) ? (const CX*)g.X : (const CX*)g.X64) +
-                 (size_t)f * N * (N / 2 + 1);
-  build_model<N, CX>(Xf, dgy, dgx, phy, ay, red, nred, coef, b * N / nb, (b + 1) * N / nb);
+                 (size_t)f * NY * (NX / 2 + 1);
+  build_model<NY, NX, CX>(Xf, dgy, dgx, phy, ay, red, nred, coef, b * NY / nb, (b + 1) * NY / nb);
   if (tid < kCoef) parts[((size_t)f * nb + b) * kCoef + tid] = coef[tid];
 }
 
-template <int N, typename CX>
+template <int NY, int NX, typename CX>
 __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step_limit,
                                                       const double* __restrict__ parts, int nb) {
-  __shared__ double2 phy[N];
-  __shared__ double ay[N];
+  __shared__ double2 phy[NY];
+  __shared__ double ay[NY];
   __shared__ double red[kNThreads / 64][kOrder + 1][kOrder + 1];
   __shared__ double nred[kNThreads / 64][2 * (kOrder + 1)];
   __shared__ double coef[kCoef];
@@ -370,9 +373,9 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
   reset_state();
   int py, px;
   double dgy, dgx;
-  grid_seed<N>(g, st, py, px, dgy, dgx);
+  grid_seed<NY, NX>(g, st, py, px, dgy, dgx);
   const CX* Xf = (sizeof(CX) == sizeof(float2) ? (const CX*)g.X : (const CX*)g.X64) +
-                 (size_t)f * N * (N / 2 + 1);
+                 (size_t)f * NY * (NX / 2 + 1);
 
   // the iterate and the decisions live in thread 0; the centre is broadcast
   double sy = dgy, sx = dgx;
@@ -391,7 +394,7 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
       }
       __syncthreads();
     } else {
-      build_model<N, CX>(Xf, cy, cx, phy, ay, red, nred, coef);
+      build_model<NY, NX, CX>(Xf, cy, cx, phy, ay, red, nred, coef);
     }
     if (tid == 0) {
       while (!done && it_left > 0) {
@@ -439,24 +442,26 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
     if (!again) break;
   }
   if (tid == 0) {
+    // in the frame's own axes (a wide frame was processed transposed)
+    const int a = transposed<NY, NX>(g.trans) ? 1 : 0, b = 1 - a;
     ccpt_result r;
     r.reserved = 0;
-    r.d[0] = sy;
-    r.d[1] = sx;
+    r.d[a] = sy;
+    r.d[b] = sx;
     r.peak = fin.c;
-    r.hess[0] = fin.hyy;
+    r.hess[2 * a] = fin.hyy;
     r.hess[1] = fin.hxy;
-    r.hess[2] = fin.hxx;
-    r.d_grid[0] = (float)dgy;
-    r.d_grid[1] = (float)dgx;
-    r.p[0] = py;
-    r.p[1] = px;
+    r.hess[2 * b] = fin.hxx;
+    r.d_grid[a] = (float)dgy;
+    r.d_grid[b] = (float)dgx;
+    r.p[a] = py;
+    r.p[b] = px;
     r.status = status;
     *out = r;
   }
 }
 
-template <int N>
+template <int NY, int NX>
 static int newton_n(const GroupParams& g, double step_limit, hipStream_t s) {
   // few frames: the first model is built by kNewtonParts blocks per frame
   const bool split = g.nparts && g.count < kNewtonSplitMax;
@@ -464,32 +469,35 @@ static int newton_n(const GroupParams& g, double step_limit, hipStream_t s) {
   const int nb = split ? kNewtonParts : 0;
   if (g.X64) {
     if (split)
-      hipLaunchKernelGGL((k_newton_part<N, double2>), dim3(nb, g.count), dim3(kNThreads), 0, s, g,
-                         parts, nb);
-    hipLaunchKernelGGL((k_newton<N, double2>), dim3(g.count), dim3(kNThreads), 0, s, g, step_limit,
-                       (const double*)parts, nb);
+      hipLaunchKernelGGL((k_newton_part<NY, NX, double2>), dim3(nb, g.count), dim3(kNThreads), 0,
+                         s, g, parts, nb);
+    hipLaunchKernelGGL((k_newton<NY, NX, double2>), dim3(g.count), dim3(kNThreads), 0, s, g,
+                       step_limit, (const double*)parts, nb);
   } else {
     if (split)
-      hipLaunchKernelGGL((k_newton_part<N, float2>), dim3(nb, g.count), dim3(kNThreads), 0, s, g,
-                         parts, nb);
-    hipLaunchKernelGGL((k_newton<N, float2>), dim3(g.count), dim3(kNThreads), 0, s, g, step_limit,
-                       (const double*)parts, nb);
+      hipLaunchKernelGGL((k_newton_part<NY, NX, float2>), dim3(nb, g.count), dim3(kNThreads), 0,
+                         s, g, parts, nb);
+    hipLaunchKernelGGL((k_newton<NY, NX, float2>), dim3(g.count), dim3(kNThreads), 0, s, g,
+                       step_limit, (const double*)parts, nb);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-#define CCPT_FOR_SIZES(X) \
-  X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
-  X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
-
-int launch_newton(int N, const GroupParams& g, double step_limit, hipStream_t s) {
-  switch (N) {
+int launch_newton(int ny, int nx, const GroupParams& g, double step_limit, hipStream_t s) {
+  if (ny == nx) {
+    switch (ny) {
 #define CASE(n) \
   case n:       \
-    return newton_n<n>(g, step_limit, s);
-    CCPT_FOR_SIZES(CASE)
+    return newton_n<n, n>(g, step_limit, s);
+      CCPT_FOR_SIZES(CASE)
 #undef CASE
+    }
+    return -2;
   }
+#define CASE(a, b) \
+  if (ny == a && nx == b) return newton_n<a, b>(g, step_limit, s);
+  CCPT_FOR_RECT(CASE)
+#undef CASE
   return -2;
 }
 

@@ -140,10 +140,6 @@ static int align_accumulate_n(const FrameDesc* desc, int first, int count, const
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-#define CCPT_FOR_SIZES(X) \
-  X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
-  X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
-
 int launch_align_accumulate(int N, const FrameDesc* desc, int first, int count,
                             const ccpt_result* fwd, float2* F, float2* acc, unsigned* cnt,
                             hipStream_t s) {

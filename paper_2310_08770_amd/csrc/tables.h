@@ -32,7 +32,7 @@ constexpr double kReducedStepLimit = 0.05;
 constexpr int stage_b_k(int n) { return (n + 31) / 32 * 32; }
 
 struct HostTables {
-  std::vector<float2> tw;  // exp(-2 pi i m / N)
+  std::vector<float2> tw;  // exp(-2 pi i m / NY)
   std::vector<char> ky;
   std::vector<char> wb;
   int Mp = 0;
@@ -68,37 +68,39 @@ inline void split_bf16(double x, uint16_t& hi, uint16_t& lo) {
   lo = bf16_rne((float)(x - (double)bf16_to_f(hi)));
 }
 
-inline HostTables build_tables(int n, int u, int M, int c, int precision) {
+// Tables of frames of ny rows of nx pixels (nx divides ny): twiddles of
+// length ny, K over ky < ny, W over kx <= nx/2 with 1/(ny nx).
+inline HostTables build_tables(int ny, int nx, int u, int M, int c, int precision) {
   HostTables t;
   t.Mp = (M + 31) / 32 * 32;
   const int Mp = t.Mp;
-  t.tw.resize(n);
-  for (int m = 0; m < n; ++m) {
-    const double a = 2.0 * M_PI * (double)m / (double)n;
+  t.tw.resize(ny);
+  for (int m = 0; m < ny; ++m) {
+    const double a = 2.0 * M_PI * (double)m / (double)ny;
     t.tw[m] = make_float2((float)std::cos(a), (float)-std::sin(a));
   }
-  std::vector<double> kr((size_t)Mp * n, 0.0), ki((size_t)Mp * n, 0.0);
+  std::vector<double> kr((size_t)Mp * ny, 0.0), ki((size_t)Mp * ny, 0.0);
   for (int m = 0; m < M; ++m)
-    for (int ky = 0; ky < n; ++ky)
-      phi_host(ky, n, (double)(m - c) / u, kr[(size_t)m * n + ky], ki[(size_t)m * n + ky]);
-  const int Kb = stage_b_k(n);
+    for (int ky = 0; ky < ny; ++ky)
+      phi_host(ky, ny, (double)(m - c) / u, kr[(size_t)m * ny + ky], ki[(size_t)m * ny + ky]);
+  const int Kb = stage_b_k(nx);
   std::vector<double> w((size_t)Kb * Mp, 0.0);
-  const double inv = 1.0 / ((double)n * (double)n);
+  const double inv = 1.0 / ((double)ny * (double)nx);
   for (int mx = 0; mx < M; ++mx) {
     const double s = (double)(mx - c) / u;
-    for (int kx = 0; kx <= n / 2; ++kx) {
+    for (int kx = 0; kx <= nx / 2; ++kx) {
       double re, im;
-      phi_host(kx, n, s, re, im);
-      const double wt = (kx == 0 || 2 * kx == n) ? 1.0 : 2.0;
+      phi_host(kx, nx, s, re, im);
+      const double wt = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
       w[(size_t)kx * Mp + mx] = wt * re * inv;
-      if (kx > 0 && 2 * kx < n) w[(size_t)(n / 2 + kx) * Mp + mx] = -2.0 * im * inv;
+      if (kx > 0 && 2 * kx < nx) w[(size_t)(nx / 2 + kx) * Mp + mx] = -2.0 * im * inv;
     }
   }
-  // Stage A operand: FP32 complex [Mp][n] in every precision (the split
+  // Stage A operand: FP32 complex [Mp][ny] in every precision (the split
   // kernels fold the integer-peak phase into it and split it on the fly)
-  t.ky.resize((size_t)Mp * n * sizeof(float2));
+  t.ky.resize((size_t)Mp * ny * sizeof(float2));
   float2* K = (float2*)t.ky.data();
-  for (size_t i = 0; i < (size_t)Mp * n; ++i) K[i] = make_float2((float)kr[i], (float)ki[i]);
+  for (size_t i = 0; i < (size_t)Mp * ny; ++i) K[i] = make_float2((float)kr[i], (float)ki[i]);
   if (precision == CCPT_PREC_FP32) {
     // Stage B operand, transposed W^T[mx][j] (FP32, [Mp][Kb]): a lane reads its
     // K values as contiguous 16-byte runs

@@ -19,6 +19,9 @@
 // The imaginary parts of Y at kx = 0 and N/2 never enter U (their W is real),
 // so Stage B's contraction length is exactly N.
 //
+// For a rectangular frame of NY rows of NX pixels, ky runs over NY, kx over
+// NX/2+1, 1/N^2 becomes 1/(NY NX), and the Stage B contraction length is NX.
+//
 // One block handles one 32-row tile of my for one frame; its grid maximum is
 // merged into the frame's key with a 64-bit atomic max (value, lowest index).
 #include <hip/hip_runtime.h>
@@ -48,22 +51,22 @@ __device__ __forceinline__ bool frame_skipped(const FrameState& s) {
   return (s.flags & CCPT_ST_NONFINITE) || s.amin == s.amax;
 }
 
-// ky-chunk of the Stage A contraction held in LDS: the largest divisor of N
-// not above 32 (16 for the largest sizes, to bound LDS)
-constexpr int a_chunk(int N) {
-  const int cap = N >= 384 ? 16 : 32;
+// ky-chunk of the Stage A contraction held in LDS: the largest divisor of NY
+// not above 32 (16 for the longest rows, to bound LDS)
+constexpr int a_chunk(int NY, int NX) {
+  const int cap = NX >= 384 ? 16 : 32;
   int best = 1;
   for (int d = 1; d <= cap; ++d)
-    if (N % d == 0) best = d;
+    if (NY % d == 0) best = d;
   return best;
 }
 
 // Row stride (floats) of the FP32 path's Ymat in LDS: KB + 1, so the 16 rows
 // and 4 lane groups (16 floats apart) of one Stage B MFMA read fall in
 // distinct banks.
-template <int N>
+template <int NX>
 constexpr int ym_stride() {
-  return (N + 31) / 32 * 32 + 1;
+  return (NX + 31) / 32 * 32 + 1;
 }
 
 // Stage B of the FP32 path for one 32-row tile: U[32][Mp] = ym[32][KB] x
@@ -73,11 +76,12 @@ constexpr int ym_stride() {
 // consecutive k = 16 q4 + i over the block's 16 MFMA steps (the same k for
 // A and B), so a lane loads its W values as four 16-byte runs per block.
 // Every thread of the block calls this.
-template <int N>
+template <int NY, int NX>
 __device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* __restrict__ WtT,
                             int Mp, int m0, int f, unsigned long long* red) {
-  constexpr int KB = (N + 31) / 32 * 32;
-  constexpr int YR = ym_stride<N>();
+  const bool tr = transposed<NY, NX>(g.trans);
+  constexpr int KB = (NX + 31) / 32 * 32;
+  constexpr int YR = ym_stride<NX>();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ntb = 2 * (Mp / 16);
   unsigned long long best = 0;
@@ -121,7 +125,7 @@ __device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* 
       const int my = m0 + mt * 16 + q4 * 4 + v;
       const int mx = nt * 16 + l16;
       if (my < g.M && mx < g.M) {
-        const unsigned long long key = peak_key(acc[v], (unsigned)(my * g.M + mx));
+        const unsigned long long key = peak_key(acc[v], grid_index(my, mx, g.M, tr));
         best = key > best ? key : best;
       }
     }
@@ -136,28 +140,30 @@ __device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* 
 }
 
 // ---------------------------------------------------------------- FP32
-// K table: float2 [Mp][N]  (K[m][ky] = phi_ky((m - c)/u))
-// W table: float  [Mp][Kb] (transposed), Kb = N rounded up to 32 (zero columns past N)
+// Frames of NY rows of NX (the spectrum is NY x (NX/2+1)).
+// K table: float2 [Mp][NY]  (K[m][ky] = phi_ky((m - c)/u))
+// W table: float  [Mp][Kb] (transposed), Kb = NX rounded up to 32 (zero columns past NX)
 // SPLIT (few frames, latency): blockIdx.z is one of `nsl` ky slices; the
 // block stores its partial Ymat to `ypart` and k_updft_f32_sum finishes.
-template <int N, bool SPLIT>
+template <int NY, int NX, bool SPLIT>
 __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const float2* __restrict__ Ktab,
                                                          const float* __restrict__ Wtab, int Mp,
                                                          float* __restrict__ ypart, int nsl) {
-  constexpr int H = N / 2 + 1;
-  constexpr int NC = N / 2;                 // columns on matrix cores
+  constexpr int H = NX / 2 + 1;
+  constexpr int NC = NX / 2;                // columns on matrix cores
   constexpr int NT = (NC + 31) / 32;        // 32-wide column tiles
   constexpr int TPW = (NT + 3) / 4;         // tiles per wave
-  constexpr int KC = a_chunk(N);
+  constexpr int KC = a_chunk(NY, NX);
   constexpr int KCS = KC + 1;               // K chunk row stride (float2): lanes on distinct banks
   constexpr int XS = KC * H;                // folded X' chunk (float2)
   constexpr int KS = 32 * KCS;              // K chunk (float2)
-  constexpr int KB = (N + 31) / 32 * 32;    // Stage B contraction, zero padded
-  constexpr int YR = ym_stride<N>();        // Ymat row stride (floats)
+  constexpr int KB = (NX + 31) / 32 * 32;   // Stage B contraction, zero padded
+  constexpr int YR = ym_stride<NX>();       // Ymat row stride (floats)
   constexpr int YS = 32 * YR / 2;           // Ymat as float2 count
   constexpr int RAW = (XS + KS) > YS ? (XS + KS) : YS;
+  constexpr int RX = NY / NX;               // kx phase index step in the NY table
   __shared__ float2 raw[RAW];
-  __shared__ float2 twf[N];                 // exp(+2 pi i m / N)
+  __shared__ float2 twf[NY];                // exp(+2 pi i m / NY)
   __shared__ float nyq[8][32];
   __shared__ unsigned long long red[kUThreads / 64];
 
@@ -166,14 +172,13 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
   const int m0 = blockIdx.x * 32;
   const FrameState st = g.st[f];
   if (frame_skipped(st)) return;
-  unsigned pk = key_index(st.peak_key);
-  if (pk >= (unsigned)(N * N)) pk = 0;  // never set: cannot happen for a frame that got here
-  const int iy = pk / N, ix = pk % N;
-  for (int i = tid; i < N; i += kUThreads) twf[i] = cconj(g.tw[i]);
+  int iy, ix;
+  peak_yx<NY, NX>(key_index(st.peak_key), g.trans, iy, ix);
+  for (int i = tid; i < NY; i += kUThreads) twf[i] = cconj(g.tw[i]);
 
   float2* xs = raw;
   float2* ks = raw + XS;
-  const float2* Xf = g.X + (size_t)f * N * H;
+  const float2* Xf = g.X + (size_t)f * NY * H;
 
   f32x16 accr[TPW], acci[TPW];
 #pragma unroll
@@ -184,7 +189,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
   const int half = lane >> 5, l32 = lane & 31;
   __syncthreads();
 
-  constexpr int NCH = N / KC;
+  constexpr int NCH = NY / KC;
   const int ch0 = SPLIT ? (int)blockIdx.z * NCH / nsl : 0;
   const int ch1 = SPLIT ? ((int)blockIdx.z + 1) * NCH / nsl : NCH;
   for (int k0 = ch0 * KC; k0 < ch1 * KC; k0 += KC) {
@@ -192,13 +197,13 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
       const int kk = i / H, kx = i - kk * H;
       const int ky = k0 + kk;
       float2 v = Xf[(size_t)ky * H + kx];
-      v = cmul(v, twf[(ky * iy + kx * ix) % N]);
+      v = cmul(v, twf[(ky * iy + kx * ix * RX) % NY]);
       if (ky == 0 && kx == 0) v = make_float2(0.f, 0.f);  // DC only shifts U by a constant
       xs[i] = v;
     }
     for (int i = tid; i < 32 * KC; i += kUThreads) {
       const int m = i / KC, kk = i - m * KC;
-      ks[m * KCS + kk] = Ktab[(size_t)(m0 + m) * N + k0 + kk];
+      ks[m * KCS + kk] = Ktab[(size_t)(m0 + m) * NY + k0 + kk];
     }
     __syncthreads();
 #pragma unroll 4
@@ -218,7 +223,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
         acci[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b, acci[t], 0, 0, 0);
       }
     }
-    // Nyquist column kx = N/2: Yr only
+    // Nyquist column kx = NX/2: Yr only
     {
       const int m = tid & 31, grp = tid >> 5;
       for (int kk = grp; kk < KC; kk += 8) {
@@ -232,8 +237,8 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
   nyq[tid >> 5][tid & 31] = nacc;
   // Ymat[32][KB] (floats) aliases the chunk buffers
   float* ym = (float*)raw;
-  for (int i = tid; i < 32 * (KB - N); i += kUThreads) {
-    const int r = i / (KB - N), j = N + i % (KB - N);
+  for (int i = tid; i < 32 * (KB - NX); i += kUThreads) {
+    const int r = i / (KB - NX), j = NX + i % (KB - NX);
     ym[r * YR + j] = 0.f;
   }
 #pragma unroll
@@ -258,17 +263,17 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
     float* dst = ypart + (((size_t)f * mtiles + blockIdx.x) * nsl + blockIdx.z) * 32 * KB;
     for (int i = tid; i < 32 * KB; i += kUThreads) dst[i] = ym[(i / KB) * YR + i % KB];
   } else {
-    stage_b_f32<N>(g, ym, Wtab, Mp, m0, f, red);
+    stage_b_f32<NY, NX>(g, ym, Wtab, Mp, m0, f, red);
   }
 }
 
 // Sums the ky-slice partials of one 32-row tile in a fixed order, then Stage B.
-template <int N>
+template <int NY, int NX>
 __global__ void __launch_bounds__(kUThreads) k_updft_f32_sum(GroupParams g, const float* __restrict__ Wtab,
                                                              int Mp, const float* __restrict__ ypart,
                                                              int nsl) {
-  constexpr int KB = (N + 31) / 32 * 32;
-  constexpr int YR = ym_stride<N>();
+  constexpr int KB = (NX + 31) / 32 * 32;
+  constexpr int YR = ym_stride<NX>();
   __shared__ float ym[32 * YR];
   __shared__ unsigned long long red[kUThreads / 64];
   const int f = blockIdx.y;
@@ -296,7 +301,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32_sum(GroupParams g, cons
     ym[(i / KB) * YR + i % KB] = v[e];
   }
   __syncthreads();
-  stage_b_f32<N>(g, ym, Wtab, Mp, blockIdx.x * 32, f, red);
+  stage_b_f32<NY, NX>(g, ym, Wtab, Mp, blockIdx.x * 32, f, red);
 }
 
 
@@ -317,18 +322,19 @@ __device__ __forceinline__ u32x4 neg_im(u32x4 w) { return w ^ 0x80000000u; }
 __device__ __forceinline__ u32x4 swap_ri(u32x4 w) { return (w >> 16) | (w << 16); }
 
 // Stage B operand: W^T as bf16 planes [2][Mp][KB] (hi, lo)
-template <int N>
+template <int NY, int NX>
 __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const float2* __restrict__ Ktab,
                                                             const unsigned short* __restrict__ WbT, int Mp) {
-  constexpr int H = N / 2 + 1;
-  constexpr int NC = N / 2;
+  constexpr int H = NX / 2 + 1;
+  constexpr int NC = NX / 2;
   constexpr int NT = (NC + 31) / 32;
   constexpr int TPW = (NT + 3) / 4;
-  constexpr int P = xb_pitch(N);
-  constexpr int KC = N >= 384 ? 16 : 32;   // ky per LDS chunk (multiple of 8)
+  constexpr int P = xb_pitch(NY);
+  constexpr int KC = NX >= 384 ? 16 : 32;  // ky per LDS chunk (multiple of 8)
   constexpr int KCS = KC + 4;              // LDS row stride, words
   constexpr int XROWS = NT * 32;
-  constexpr int KB = (N + 31) / 32 * 32;
+  constexpr int KB = (NX + 31) / 32 * 32;
+  constexpr int RX = NY / NX;              // kx phase index step in the NY table
   constexpr int YST = KB + 8;              // Ymat row stride, bf16 elements
   constexpr int XW = 2 * XROWS * KCS;
   constexpr int KW = 2 * 32 * KCS;
@@ -336,7 +342,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
   constexpr int RAWW = (XW + KW) > YW ? (XW + KW) : YW;
   __shared__ __attribute__((aligned(16))) unsigned raw[RAWW];
   __shared__ float2 kf[32][KC + 1];
-  __shared__ float2 twf[N];
+  __shared__ float2 twf[NY];
   __shared__ float nyq[8][32];
   __shared__ unsigned long long red[kUThreads / 64];
 
@@ -345,10 +351,10 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
   const int m0 = blockIdx.x * 32;
   const FrameState st = g.st[f];
   if (frame_skipped(st)) return;
-  unsigned pk = key_index(st.peak_key);
-  if (pk >= (unsigned)(N * N)) pk = 0;
-  const int iy = pk / N, ix = pk % N;
-  for (int i = tid; i < N; i += kUThreads) twf[i] = cconj(g.tw[i]);
+  int iy, ix;
+  peak_yx<NY, NX>(key_index(st.peak_key), g.trans, iy, ix);
+  const bool tr = transposed<NY, NX>(g.trans);
+  for (int i = tid; i < NY; i += kUThreads) twf[i] = cconj(g.tw[i]);
 
   unsigned* xs_hi = raw;
   unsigned* xs_lo = raw + XROWS * KCS;
@@ -356,7 +362,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
   unsigned* ks_lo = ks_hi + 32 * KCS;
   const unsigned* Xbh = g.Xb + (size_t)f * 2 * NC * P;
   const unsigned* Xbl = Xbh + (size_t)NC * P;
-  const float2* Xf = g.X + (size_t)f * N * H;
+  const float2* Xf = g.X + (size_t)f * NY * H;
 
   f32x16 accr[TPW], acci[TPW];
 #pragma unroll
@@ -382,7 +388,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
       const int m = i / KC, kk = i - m * KC;
       const int ky = k0 + kk;
       float2 kv = make_float2(0.f, 0.f);
-      if (ky < N) kv = cmul(Ktab[(size_t)(m0 + m) * N + ky], twf[(ky * iy) % N]);
+      if (ky < NY) kv = cmul(Ktab[(size_t)(m0 + m) * NY + ky], twf[(ky * iy) % NY]);
       kf[m][kk] = kv;
       unsigned wh, wl;
       split_pair(kv, wh, wl);
@@ -412,11 +418,11 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
         }
       }
     }
-    {  // Nyquist column kx = N/2 in FP32 on the VALU
+    {  // Nyquist column kx = NX/2 in FP32 on the VALU
       const int m = tid & 31, grp = tid >> 5;
       for (int kk = grp; kk < KC; kk += 8) {
         const int ky = k0 + kk;
-        if (ky < N) {
+        if (ky < NY) {
           const float2 kv = kf[m][kk];
           const float2 xv = Xf[(size_t)ky * H + NC];
           nacc += kv.x * xv.x - kv.y * xv.y;
@@ -431,7 +437,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
   for (int t = 0; t < TPW; ++t) {
     if (wave + 4 * t < NT) {
       const int kx = (wave + 4 * t) * 32 + j;
-      const float2 ph = twf[(kx * ix) % N];
+      const float2 ph = twf[(kx * ix * RX) % NY];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const float yr = accr[t][v], yi = acci[t][v];
@@ -442,8 +448,8 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
   }
   unsigned short* ymh = (unsigned short*)raw;
   unsigned short* yml = ymh + 32 * YST;
-  for (int i = tid; i < 32 * (KB - N); i += kUThreads) {
-    const int r = i / (KB - N), c = N + i % (KB - N);
+  for (int i = tid; i < 32 * (KB - NX); i += kUThreads) {
+    const int r = i / (KB - NX), c = NX + i % (KB - NX);
     ymh[r * YST + c] = 0;
     yml[r * YST + c] = 0;
   }
@@ -503,7 +509,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
       const int my = m0 + mt * 16 + q4 * 4 + v;
       const int mx = nt * 16 + l16;
       if (my < g.M && mx < g.M) {
-        const unsigned long long key = peak_key(acc[v], (unsigned)(my * g.M + mx));
+        const unsigned long long key = peak_key(acc[v], grid_index(my, mx, g.M, tr));
         best = key > best ? key : best;
       }
     }
@@ -518,7 +524,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
 }
 
 
-// Wide variant for N >= 256: one block per frame and group of up to MT
+// Wide variant for rows of NX >= 256: one block per frame and group of up to MT
 // 32-row m-tiles, one wave per 32-column kx tile.  Each frame's split
 // spectrum is streamed once from memory straight into the B operands (each
 // fragment feeds 6 MT matrix instructions).  The A operands come from the
@@ -528,35 +534,36 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
 // Nyquist column in its imaginary part, so Yi(., 0) is the Nyquist output.
 // The three products of each K step are issued pass by pass over all tiles
 // so consecutive matrix instructions never depend on each other.  Where a
-// block's waves fit one per SIMD (N <= 256) Stage A is software pipelined:
+// block's waves fit one per SIMD (NX <= 256) Stage A is software pipelined:
 // the next chunk's B fragments and K' rows are loaded while the current
 // chunk's MFMAs run, and K' chunks alternate between two LDS buffers.
 // Stage B converts Y to bf16 hi/lo for up to GB row tiles at a time into
 // LDS, so every W fragment a wave loads from L2 serves 2*GB row halves (W
 // is read 2 times per frame instead of 2*MT).
-template <int N, int MT>
-__global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
+template <int NY, int NX, int MT>
+__global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
     k_updft_bf16x2_wide(GroupParams g, const unsigned* __restrict__ kfold,
                         const unsigned short* __restrict__ WbT, int Mp) {
-  constexpr int NC = N / 2;
+  constexpr int NC = NX / 2;
   constexpr int NW = (NC + 31) / 32;  // waves = kx tiles
   constexpr int NTH = 64 * NW;
-  constexpr int P = xb_pitch(N);
+  constexpr int P = xb_pitch(NY);
   constexpr int KC = 32;
   constexpr int KCS = KC + 4;
   constexpr int ROWS = MT * 32;
-  constexpr int KB = (N + 31) / 32 * 32;
+  constexpr int KB = (NX + 31) / 32 * 32;
+  constexpr int RX = NY / NX;  // kx phase index step in the NY table
   constexpr int YST = KB + 8;
   constexpr int KW = 2 * ROWS * KCS;
   constexpr int YW = 32 * YST;
   // the pipelined Stage A needs registers for a second chunk of operands:
-  // used where a block's waves fit one per SIMD (N <= 256)
+  // used where a block's waves fit one per SIMD (NX <= 256)
   constexpr bool PIPE = NW <= 4;
   constexpr int GB = 3 * YW * 4 <= 120000 ? 3 : 2;  // row tiles per Stage B group
   constexpr int KWT = PIPE ? 2 * KW : KW;
   constexpr int RAWW = KWT > GB * YW ? KWT : GB * YW;
   __shared__ __attribute__((aligned(16))) unsigned raw[RAWW];
-  __shared__ float2 twf[N];
+  __shared__ float2 twf[NY];
   __shared__ unsigned long long red[NW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -564,10 +571,10 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   const int m0 = blockIdx.x * ROWS;  // the folded table has rows up to a whole block
   const FrameState st = g.st[f];
   if (frame_skipped(st)) return;
-  unsigned pk = key_index(st.peak_key);
-  if (pk >= (unsigned)(N * N)) pk = 0;
-  const int iy = pk / N, ix = pk % N;
-  for (int i = tid; i < N; i += NTH) twf[i] = cconj(g.tw[i]);
+  int iy, ix;
+  peak_yx<NY, NX>(key_index(st.peak_key), g.trans, iy, ix);
+  const bool tr = transposed<NY, NX>(g.trans);
+  for (int i = tid; i < NY; i += NTH) twf[i] = cconj(g.tw[i]);
 
   const size_t kplane = (size_t)kfold_rows(Mp) * P;
   const unsigned* Kh = kfold + (size_t)iy * 2 * kplane;
@@ -703,7 +710,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
   }
   // kx phase of the fold; column 0 holds (Y[., 0], Y[., N/2]) and its phase is 1
   if ((BFULL || bvalid) && kxrow > 0) {
-    const float2 ph = twf[(kxrow * ix) % N];
+    const float2 ph = twf[(kxrow * ix * RX) % NY];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
@@ -730,8 +737,8 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
     for (int t = t0; t < t0 + GB && t < MT; ++t) {
       unsigned short* ymh = ybase + (t - t0) * SLOT;
       unsigned short* yml = ymh + 32 * YST;
-      for (int i = tid; i < 32 * (KB - N); i += NTH) {
-        const int r = i / (KB - N), c = N + i % (KB - N);
+      for (int i = tid; i < 32 * (KB - NX); i += NTH) {
+        const int r = i / (KB - NX), c = NX + i % (KB - NX);
         ymh[r * YST + c] = 0;
         yml[r * YST + c] = 0;
       }
@@ -784,7 +791,7 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
             const int my = m0 + (t0 + (r >> 1)) * 32 + (r & 1) * 16 + q4 * 4 + v;
             const int mx = nt * 16 + l16;
             if (my < g.M && mx < g.M) {
-              const unsigned long long key = peak_key(uval, (unsigned)(my * g.M + mx));
+              const unsigned long long key = peak_key(uval, grid_index(my, mx, g.M, tr));
               best = key > best ? key : best;
             }
           }
@@ -802,8 +809,9 @@ __global__ void __launch_bounds__(64 * ((N / 2 + 31) / 32))
 }
 
 // Folded split table for the wide kernel: K'_p[m, ky] = phi_ky(p + (m - c)/u)
-// for every integer peak row p, as bf16 hi/lo words (re | im << 16),
-// [N][2][Mp][xb_pitch(N)], computed in FP64 with exactly reduced phases.
+// for every integer peak row p of frames of N rows, as bf16 hi/lo words
+// (re | im << 16), [N][2][Mp][xb_pitch(N)], computed in FP64 with exactly
+// reduced phases.
 __global__ void k_build_kfold(unsigned* __restrict__ out, int N, int u, int M, int c, int rows, int P) {
   const size_t plane = (size_t)rows * P;
   const size_t total = (size_t)N * plane;
@@ -843,33 +851,33 @@ int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int rows, hipS
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int N>
+template <int NY, int NX>
 static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
   const int mtiles = t.Mp / 32;
   if (t.precision == CCPT_PREC_FP32) {
-    constexpr int NCH = N / a_chunk(N);
+    constexpr int NCH = NY / a_chunk(NY, NX);
     const int nsl = NCH < kSplitSlices ? NCH : kSplitSlices;
     if (g.ypart && g.count * mtiles < kSplitMaxBlocks && nsl > 1) {
-      hipLaunchKernelGGL((k_updft_f32<N, true>), dim3(mtiles, g.count, nsl), dim3(kUThreads), 0, s,
-                         g, (const float2*)t.ky, (const float*)t.wb, t.Mp, g.ypart, nsl);
-      hipLaunchKernelGGL((k_updft_f32_sum<N>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
+      hipLaunchKernelGGL((k_updft_f32<NY, NX, true>), dim3(mtiles, g.count, nsl), dim3(kUThreads),
+                         0, s, g, (const float2*)t.ky, (const float*)t.wb, t.Mp, g.ypart, nsl);
+      hipLaunchKernelGGL((k_updft_f32_sum<NY, NX>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
                          (const float*)t.wb, t.Mp, (const float*)g.ypart, nsl);
     } else {
-      hipLaunchKernelGGL((k_updft_f32<N, false>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
-                         (const float2*)t.ky, (const float*)t.wb, t.Mp, (float*)nullptr, 1);
+      hipLaunchKernelGGL((k_updft_f32<NY, NX, false>), dim3(mtiles, g.count), dim3(kUThreads), 0,
+                         s, g, (const float2*)t.ky, (const float*)t.wb, t.Mp, (float*)nullptr, 1);
     }
   } else if (t.precision == CCPT_PREC_BF16X2) {
     if (!g.Xb) return -1;
-    if constexpr (N >= kWideMinN) {
+    if constexpr (NX >= kWideMinN) {
       constexpr int MT = kWideMT;
-      constexpr int NW = (N / 2 + 31) / 32;
+      constexpr int NW = (NX / 2 + 31) / 32;
       if (!t.kfold) return -1;
-      hipLaunchKernelGGL((k_updft_bf16x2_wide<N, MT>), dim3((mtiles + MT - 1) / MT, g.count),
+      hipLaunchKernelGGL((k_updft_bf16x2_wide<NY, NX, MT>), dim3((mtiles + MT - 1) / MT, g.count),
                          dim3(64 * NW), 0, s, g, (const unsigned*)t.kfold,
                          (const unsigned short*)t.wb, t.Mp);
     } else {
-      hipLaunchKernelGGL((k_updft_bf16x2<N>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
-                         (const float2*)t.ky, (const unsigned short*)t.wb, t.Mp);
+      hipLaunchKernelGGL((k_updft_bf16x2<NY, NX>), dim3(mtiles, g.count), dim3(kUThreads), 0, s,
+                         g, (const float2*)t.ky, (const unsigned short*)t.wb, t.Mp);
     }
   } else {
     return -2;
@@ -877,18 +885,21 @@ static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-#define CCPT_FOR_SIZES(X) \
-  X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
-  X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
-
-int launch_updft(int N, const GroupParams& g, const UpdftTables& t, hipStream_t s) {
-  switch (N) {
+int launch_updft(int ny, int nx, const GroupParams& g, const UpdftTables& t, hipStream_t s) {
+  if (ny == nx) {
+    switch (ny) {
 #define CASE(n) \
   case n:       \
-    return updft_n<n>(g, t, s);
-    CCPT_FOR_SIZES(CASE)
+    return updft_n<n, n>(g, t, s);
+      CCPT_FOR_SIZES(CASE)
 #undef CASE
+    }
+    return -2;
   }
+#define CASE(a, b) \
+  if (ny == a && nx == b) return updft_n<a, b>(g, t, s);
+  CCPT_FOR_RECT(CASE)
+#undef CASE
   return -2;
 }
 

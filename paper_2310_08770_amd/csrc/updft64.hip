@@ -167,10 +167,6 @@ static int updft64_n(const GroupParams& g, const double2* K, const double2* W, i
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-#define CCPT_FOR_SIZES(X) \
-  X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
-  X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
-
 int launch_updft64(int N, const GroupParams& g, const double2* K, const double2* W, int Mp,
                    hipStream_t s) {
   switch (N) {

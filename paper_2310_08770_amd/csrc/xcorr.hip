@@ -18,42 +18,45 @@ namespace ccpt {
 // and LDS, so more resident waves per CU (16 to 32) hide more of it
 constexpr int kThreads = 512;
 
-// largest divisor of N whose block of rows holds at most `budget` complex values
-constexpr int rows_per_block(int N, int budget) {
+// Frames are NY rows of NX pixels (NY = NX, or NY = 2^k NX).
+
+// largest divisor of NY whose block of rows (NX/2 complex values each) holds
+// at most `budget` complex values
+constexpr int rows_per_block(int NY, int NX, int budget) {
   int best = 1;
-  for (int r = 1; r <= N; ++r)
-    if (N % r == 0 && r * (N / 2) <= budget) best = r;
+  for (int r = 1; r <= NY; ++r)
+    if (NY % r == 0 && r * (NX / 2) <= budget) best = r;
   return best;
 }
 
 // columns per block of the column pass: at most 2048 complex values per
 // LDS buffer (8 columns of 256: 37 KB of LDS, so four blocks share a CU),
-// no wider than the N/2+1 columns need
-constexpr int cols_per_block(int N) {
+// no wider than the NX/2+1 columns need
+constexpr int cols_per_block(int NY, int NX) {
   int cb = 1;
-  while (cb * 2 * N <= 2048 && cb < N / 2) cb *= 2;
+  while (cb * 2 * NY <= 2048 && cb < NX / 2) cb *= 2;
   return cb;
 }
 
 // rows per block of the row passes: 16 rows (128-byte runs of the
-// column-major intermediate) when they fit, else the largest divisor of N
-constexpr int row_block(int N) {
-  return (N % 16 == 0 && 16 * (N / 2 + 1) <= 4200) ? 16 : rows_per_block(N, 2048);
+// column-major intermediate) when they fit, else the largest divisor of NY
+constexpr int row_block(int NY, int NX) {
+  return (NY % 16 == 0 && 16 * (NX / 2 + 1) <= 4200) ? 16 : rows_per_block(NY, NX, 2048);
 }
 
-// the same choices for FP64 data (half the values per LDS buffer)
+// the same choices for FP64 data (square frames; half the values per LDS buffer)
 constexpr int cols_per_block64(int N) {
   int cb = 1;
   while (cb * 2 * N <= 2048 && cb < N / 2) cb *= 2;
   return cb;
 }
 template <typename C>
-constexpr int row_block_of(int N) {
-  return sizeof(C) == sizeof(float2) ? row_block(N) : row_block64(N);
+constexpr int row_block_of(int NY, int NX) {
+  return sizeof(C) == sizeof(float2) ? row_block(NY, NX) : row_block64(NY);
 }
 template <typename C>
-constexpr int cols_block_of(int N) {
-  return sizeof(C) == sizeof(float2) ? cols_per_block(N) : cols_per_block64(N);
+constexpr int cols_block_of(int NY, int NX) {
+  return sizeof(C) == sizeof(float2) ? cols_per_block(NY, NX) : cols_per_block64(NY);
 }
 
 template <typename R>
@@ -71,6 +74,7 @@ struct ImgSrc {
   int dtype;
   int pitch;
   long img_stride;
+  int trans;  // read each image transposed (a wide frame held tall)
 };
 
 __device__ __forceinline__ void img_of(const ImgSrc& s, int f, const void*& data, int& dtype,
@@ -123,25 +127,25 @@ __global__ void k_init_state(FrameState* st, int count) {
 }
 
 // Row pass, forward.  weight: 0 A = I, 1 B = -1/(E+eps), 2 A = (I+eps)^2.
-// Writes T[f][y][k], k < N/2+1.  With st != null records min/max of A (as
-// FP32 keys) and non-finite pixels per frame.  C = float2 or double2 sets
-// the arithmetic.
-template <int N, int RPB, typename C>
+// Writes T[f][k][y] (column-major), k < NX/2+1.  With st != null records
+// min/max of A (as FP32 keys) and non-finite pixels per frame.  C = float2
+// or double2 sets the arithmetic.
+template <int NY, int NX, int RPB, typename C>
 __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, double eps_in,
                                                        C* __restrict__ T, FrameState* st,
                                                        const C* __restrict__ gtw) {
   using R = real_t<C>;
-  constexpr int L = N / 2, H = N / 2 + 1;
+  constexpr int L = NX / 2, H = NX / 2 + 1;
   constexpr int LS = lds_len(L) + 1;  // row stride in LDS
   const R eps = (R)eps_in;
-  __shared__ C tw[N];
+  __shared__ C tw[NX];
   __shared__ C bufA[RPB * LS];
   __shared__ C bufB[RPB * LS];
   __shared__ unsigned red[3][kThreads / 64];
   const int tid = threadIdx.x;
   const int f = blockIdx.y;
   const int y0 = blockIdx.x * RPB;
-  for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
+  for (int i = tid; i < NX; i += kThreads) tw[i] = gtw[i * (NY / NX)];
   const void* data;
   int dtype, pitch;
   img_of(src, f, data, dtype, pitch);
@@ -154,14 +158,15 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, d
     kmax = max(kmax, f2key((float)a));
     return a;
   };
-  const bool vec16 = dtype == CCPT_U16 && N % 8 == 0 && pitch % 8 == 0 &&
+  const bool trans = transposed<NY, NX>(src.trans);
+  const bool vec16 = !trans && dtype == CCPT_U16 && NX % 8 == 0 && pitch % 8 == 0 &&
                      ((uintptr_t)data & 15) == 0;
-  const bool vec32 = dtype == CCPT_F32 && N % 4 == 0 && pitch % 4 == 0 &&
+  const bool vec32 = !trans && dtype == CCPT_F32 && NX % 4 == 0 && pitch % 4 == 0 &&
                      ((uintptr_t)data & 15) == 0;
   if (vec16) {
     // 8 pixels (16 bytes) per load
-    for (int i = tid; i < RPB * (N / 8); i += kThreads) {
-      const int r = i / (N / 8), q = i - r * (N / 8);
+    for (int i = tid; i < RPB * (NX / 8); i += kThreads) {
+      const int r = i / (NX / 8), q = i - r * (NX / 8);
       const uint4 v = *(const uint4*)((const unsigned short*)data + (long)(y0 + r) * pitch + 8 * q);
       const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -169,11 +174,21 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, d
         bufA[r * LS + lds_idx(4 * q + e)] = mkc<C>(pro((R)(w[e] & 0xFFFFu)), pro((R)(w[e] >> 16)));
     }
   } else if (vec32) {
-    for (int i = tid; i < RPB * (N / 4); i += kThreads) {
-      const int r = i / (N / 4), q = i - r * (N / 4);
+    for (int i = tid; i < RPB * (NX / 4); i += kThreads) {
+      const int r = i / (NX / 4), q = i - r * (NX / 4);
       const float4 v = *(const float4*)((const float*)data + (long)(y0 + r) * pitch + 4 * q);
       bufA[r * LS + lds_idx(2 * q)] = mkc<C>(pro((R)v.x), pro((R)v.y));
       bufA[r * LS + lds_idx(2 * q + 1)] = mkc<C>(pro((R)v.z), pro((R)v.w));
+    }
+  } else if (trans) {
+    // row y of the tall image is column y of the wide frame: adjacent threads
+    // take adjacent columns of one frame row
+    for (int i = tid; i < RPB * L; i += kThreads) {
+      const int c = i / RPB, r = i - c * RPB;
+      const long idx = (long)(2 * c) * pitch + (y0 + r);
+      const R a0 = pro(load_px<R>(data, dtype, idx));
+      const R a1 = pro(load_px<R>(data, dtype, idx + pitch));
+      bufA[r * LS + lds_idx(c)] = mkc<C>(a0, a1);
     }
   } else {
     for (int i = tid; i < RPB * L; i += kThreads) {
@@ -205,11 +220,11 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, d
     atomicMax(&st[f].amax, kmax);
     if (bad) atomicOr(&st[f].flags, (unsigned)CCPT_ST_NONFINITE);
   }
-  C* z = fft_lds<L, -1, N>(bufA, bufB, RPB, LS, tw);
+  C* z = fft_lds<L, -1, NX>(bufA, bufB, RPB, LS, tw);
   // unpack: X[k] = E[k] + W^k O[k], E = (Z[k] + conj Z[L-k]) / 2,
-  // O = (Z[k] - conj Z[L-k]) / (2i), W = exp(-2 pi i / N); stored column-major
+  // O = (Z[k] - conj Z[L-k]) / (2i), W = exp(-2 pi i / NX); stored column-major
   // T[k][y] so each column k receives RPB consecutive rows
-  C* Tf = T + (size_t)f * N * H;
+  C* Tf = T + (size_t)f * NY * H;
   const R half = R(0.5);
   for (int i = tid; i < RPB * H; i += kThreads) {
     const int k = i / RPB, r = i - k * RPB;
@@ -218,30 +233,31 @@ __global__ void __launch_bounds__(kThreads) k_rows_fwd(ImgSrc src, int weight, d
     const C e = cscale(cadd(zk, zc), half);
     const C d = csub(zk, zc);
     const C o = mkc<C>(half * d.y, -half * d.x);  // d / (2i)
-    Tf[(size_t)k * N + y0 + r] = cadd(e, cmul(tw[k], o));
+    Tf[(size_t)k * NY + y0 + r] = cadd(e, cmul(tw[k], o));
   }
 }
 
 enum ColKind { COL_XCORR = 0, COL_FWD = 1, COL_FWD_CONJ = 2, COL_INV = 3 };
 
-// Column pass over the N/2+1 columns: block b takes columns b*CB .. b*CB+CB-1
-// of the first N/2, and block 0 also takes the Nyquist column N/2 (so no
+// Column pass over the NX/2+1 columns of length NY: block b takes columns
+// b*CB .. b*CB+CB-1 of the first NX/2, and block 0 also takes the Nyquist
+// column NX/2 (so no
 // block is left with a single column, and block 0 holds both real-output
 // columns 0 and N/2 for the packed split-precision copy).
 //  COL_XCORR:    forward FFT, X = F[A] * rspec (stored to X), inverse FFT back into T
 //  COL_FWD:      forward FFT stored to `spec`
 //  COL_FWD_CONJ: conjugate of the forward FFT stored to `spec`
 //  COL_INV:      inverse FFT of `spec` stored to T
-template <int N, int CB, int KIND, typename C>
+template <int NY, int NX, int CB, int KIND, typename C>
 __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__ desc, int first,
                                                    C* __restrict__ T, C* __restrict__ X,
                                                    unsigned* __restrict__ Xb,
                                                    C* __restrict__ spec, long spec_stride,
                                                    const C* __restrict__ gtw) {
-  constexpr int H = N / 2 + 1, S = lds_len(N) + 1, NC = N / 2;
+  constexpr int H = NX / 2 + 1, S = lds_len(NY) + 1, NC = NX / 2;
   constexpr int CS = CB + 1;  // column slots: CB regular + the Nyquist slot of block 0
   const C zero = mkc<C>(0, 0);
-  __shared__ C tw[N];
+  __shared__ C tw[NY];
   __shared__ C bufA[CS * S];
   __shared__ C bufB[CS * S];
   const int tid = threadIdx.x;
@@ -252,36 +268,36 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
   const int nseq = has_nyq ? CS : CB;
   // slot -> column index (-1 when empty)
   auto col_of = [&](int c) { return c < nreg ? c0 + c : (c == CB && has_nyq ? NC : -1); };
-  for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
-  // T is column-major: column kx holds N consecutive rows
-  C* Tf = T + (size_t)f * N * H;
+  for (int i = tid; i < NY; i += kThreads) tw[i] = gtw[i];
+  // T is column-major: column kx holds NY consecutive rows
+  C* Tf = T + (size_t)f * NY * H;
   if constexpr (KIND == COL_INV) {
     const C* inp = spec + (size_t)f * spec_stride;  // row-major spectrum
-    for (int i = tid; i < N * nseq; i += kThreads) {
+    for (int i = tid; i < NY * nseq; i += kThreads) {
       const int y = i / nseq, c = i - y * nseq;
       const int kx = col_of(c);
       bufA[c * S + lds_idx(y)] = kx >= 0 ? inp[(size_t)y * H + kx] : mkc<C>(0, 0);
     }
   } else {
-    for (int i = tid; i < N * nseq; i += kThreads) {
-      const int c = i / N, y = i - c * N;
+    for (int i = tid; i < NY * nseq; i += kThreads) {
+      const int c = i / NY, y = i - c * NY;
       const int kx = col_of(c);
-      bufA[c * S + lds_idx(y)] = kx >= 0 ? Tf[(size_t)kx * N + y] : mkc<C>(0, 0);
+      bufA[c * S + lds_idx(y)] = kx >= 0 ? Tf[(size_t)kx * NY + y] : mkc<C>(0, 0);
     }
   }
   __syncthreads();
   if constexpr (KIND == COL_INV) {
-    C* r = fft_lds<N, +1, N>(bufA, bufB, nseq, S, tw);
-    for (int i = tid; i < N * nseq; i += kThreads) {
-      const int c = i / N, y = i - c * N;
+    C* r = fft_lds<NY, +1, NY>(bufA, bufB, nseq, S, tw);
+    for (int i = tid; i < NY * nseq; i += kThreads) {
+      const int c = i / NY, y = i - c * NY;
       const int kx = col_of(c);
-      if (kx >= 0) Tf[(size_t)kx * N + y] = r[c * S + lds_idx(y)];
+      if (kx >= 0) Tf[(size_t)kx * NY + y] = r[c * S + lds_idx(y)];
     }
   } else {
-    C* r = fft_lds<N, -1, N>(bufA, bufB, nseq, S, tw);
+    C* r = fft_lds<NY, -1, NY>(bufA, bufB, nseq, S, tw);
     if constexpr (KIND == COL_FWD || KIND == COL_FWD_CONJ) {
       C* out = spec + (size_t)f * spec_stride;
-      for (int i = tid; i < N * nseq; i += kThreads) {
+      for (int i = tid; i < NY * nseq; i += kThreads) {
         const int y = i / nseq, c = i - y * nseq;
         const int kx = col_of(c);
         if (kx >= 0) {
@@ -292,8 +308,8 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
       }
     } else {
       const C* R = (const C*)desc[first + f].rspec;
-      C* Xf = X + (size_t)f * N * H;
-      for (int i = tid; i < N * nseq; i += kThreads) {
+      C* Xf = X + (size_t)f * NY * H;
+      for (int i = tid; i < NY * nseq; i += kThreads) {
         const int y = i / nseq, c = i - y * nseq;
         const int kx = col_of(c);
         if (kx >= 0) {
@@ -308,18 +324,18 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
       if constexpr (sizeof(C) == sizeof(float2)) {
       if (Xb) {
         // bf16 hi/lo split of X for the matrix cores: one row per column
-        // kx < N/2, ky contiguous, rows padded to xb_pitch(N) with zeros.  Row
-        // 0 carries Z = X[., 0] + i X[., N/2]: both columns give real Stage A
-        // outputs, so Re and Im of the product with Z are the two of them.
-        // The DC term X[0, 0] is dropped.
-        constexpr int P = xb_pitch(N);
+        // kx < NX/2, ky contiguous, rows padded to xb_pitch(NY) with zeros.
+        // Row 0 carries Z = X[., 0] + i X[., NX/2]: both columns give real
+        // Stage A outputs, so Re and Im of the product with Z are the two of
+        // them.  The DC term X[0, 0] is dropped.
+        constexpr int P = xb_pitch(NY);
         unsigned* hi = Xb + (size_t)f * 2 * NC * P;
         unsigned* lo = hi + (size_t)NC * P;
         for (int i = tid; i < nreg * P; i += kThreads) {
           const int c = i / P, y = i - c * P;
           const int kx = c0 + c;
           float2 v = make_float2(0.f, 0.f);
-          if (y < N) {
+          if (y < NY) {
             v = r[c * S + lds_idx(y)];
             if (kx == 0) {
               if (y == 0) v.x = 0.f;
@@ -335,34 +351,35 @@ __global__ void __launch_bounds__(kThreads) k_cols(const FrameDesc* __restrict__
       }
       }
       C* o = (r == bufA) ? bufB : bufA;
-      C* q = fft_lds<N, +1, N>(r, o, nseq, S, tw);
-      for (int i = tid; i < N * nseq; i += kThreads) {
-        const int c = i / N, y = i - c * N;
+      C* q = fft_lds<NY, +1, NY>(r, o, nseq, S, tw);
+      for (int i = tid; i < NY * nseq; i += kThreads) {
+        const int c = i / NY, y = i - c * NY;
         const int kx = col_of(c);
-        if (kx >= 0) Tf[(size_t)kx * N + y] = q[c * S + lds_idx(y)];
+        if (kx >= 0) Tf[(size_t)kx * NY + y] = q[c * S + lds_idx(y)];
       }
     }
   }
 }
 
-// Row pass, inverse (c2r).  Each row's N/2+1 bins are packed into N/2
+// Row pass, inverse (c2r).  Each row's NX/2+1 bins are packed into NX/2
 // complex values Z = E + i O with E = (X[k] + conj X[L-k]) / 2 and
-// O = (X[k] - conj X[L-k]) W^-k / 2, transformed, and read out as the N reals
-// z[n] = a[2n] + i a[2n+1].
-// ARGMAX: per-frame maximum with ties to the lowest row-major index: in FP32
-// one 64-bit atomic key per frame, in FP64 one candidate per row block
-// (cand[f][blockIdx.x]).  Otherwise the real row is scaled and stored to img
-// (N x N per frame, FP32 only).
-template <int N, int RPB, bool ARGMAX, typename C>
+// O = (X[k] - conj X[L-k]) W^-k / 2, transformed, and read out as the NX
+// reals z[n] = a[2n] + i a[2n+1].
+// ARGMAX: per-frame maximum with ties to the lowest row-major index of the
+// frame (trans: of the wide frame, whose row-major order is the tall image's
+// column-major order): in FP32 one 64-bit atomic key per frame, in FP64 one
+// candidate per row block (cand[f][blockIdx.x]).  Otherwise the real row is
+// scaled and stored to img (NY x NX per frame, FP32 only).
+template <int NY, int NX, int RPB, bool ARGMAX, typename C>
 __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, FrameState* st,
                                                        float* img, float scale,
                                                        const C* __restrict__ gtw,
-                                                       PeakCand* __restrict__ cand) {
+                                                       PeakCand* __restrict__ cand, int trans_in) {
   using R = real_t<C>;
   constexpr bool FP64 = sizeof(C) != sizeof(float2);
-  constexpr int L = N / 2, H = N / 2 + 1;
+  constexpr int L = NX / 2, H = NX / 2 + 1;
   constexpr int LS = lds_len(L) + 1;
-  __shared__ C tw[N];
+  __shared__ C tw[NX];
   __shared__ C raw[RPB * H];
   __shared__ C bufA[RPB * LS];
   __shared__ C bufB[RPB * LS];
@@ -371,13 +388,19 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
   const int tid = threadIdx.x;
   const int f = blockIdx.y;
   const int y0 = blockIdx.x * RPB;
-  for (int i = tid; i < N; i += kThreads) tw[i] = gtw[i];
+  for (int i = tid; i < NX; i += kThreads) tw[i] = gtw[i * (NY / NX)];
   // column-major T: column k holds rows y0..y0+RPB-1 consecutively
-  const C* Tf = T + (size_t)f * N * H + y0;
+  const C* Tf = T + (size_t)f * NY * H + y0;
   for (int i = tid; i < RPB * H; i += kThreads) {
     const int k = i / RPB, r = i - k * RPB;
-    raw[r * H + k] = Tf[(size_t)k * N + r];
+    raw[r * H + k] = Tf[(size_t)k * NY + r];
   }
+  // frame row-major index of tall pixel (y, x), and the step to (y, x + 1)
+  const bool trans = transposed<NY, NX>(trans_in);
+  auto flat_of = [&](int y, int x) {
+    return trans ? (unsigned)(x * NY + y) : (unsigned)(y * NX + x);
+  };
+  const unsigned xstep = trans ? (unsigned)NY : 1u;
   __syncthreads();
   const R half = R(0.5);
   for (int i = tid; i < RPB * L; i += kThreads) {
@@ -389,15 +412,15 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
     bufA[r * LS + lds_idx(k)] = mkc<C>(e.x - o.y, e.y + o.x);  // e + i o
   }
   __syncthreads();
-  C* z = fft_lds<L, +1, N>(bufA, bufB, RPB, LS, tw);
+  C* z = fft_lds<L, +1, NX>(bufA, bufB, RPB, LS, tw);
   if constexpr (ARGMAX && !FP64) {
     unsigned long long best = 0;
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
       const C v = z[r * LS + lds_idx(n)];
-      const unsigned flat = (unsigned)((y0 + r) * N + 2 * n);
+      const unsigned flat = flat_of(y0 + r, 2 * n);
       unsigned long long k0 = peak_key(v.x, flat);
-      unsigned long long k1 = peak_key(v.y, flat + 1);
+      unsigned long long k1 = peak_key(v.y, flat + xstep);
       best = k0 > best ? k0 : best;
       best = k1 > best ? k1 : best;
     }
@@ -422,9 +445,9 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
       const C v = z[r * LS + lds_idx(n)];
-      const unsigned flat = (unsigned)((y0 + r) * N + 2 * n);
+      const unsigned flat = flat_of(y0 + r, 2 * n);
       take(v.x, flat);
-      take(v.y, flat + 1);
+      take(v.y, flat + xstep);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) take(__shfl_xor(bv, o, 64), (unsigned)__shfl_xor((int)bi, o, 64));
@@ -442,33 +465,34 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
       cand[(size_t)f * gridDim.x + blockIdx.x] = pc;
     }
   } else if constexpr (!FP64) {
-    float* out = img + (size_t)f * N * N + (size_t)y0 * N;
+    float* out = img + (size_t)f * NY * NX + (size_t)y0 * NX;
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
       const C v = z[r * LS + lds_idx(n)];
-      out[r * N + 2 * n] = v.x * scale;
-      out[r * N + 2 * n + 1] = v.y * scale;
+      out[r * NX + 2 * n] = v.x * scale;
+      out[r * NX + 2 * n + 1] = v.y * scale;
     }
   }
 }
 
-template <int N>
+template <int NY, int NX>
 static int xcorr_n(const GroupParams& g, hipStream_t s, const Marker& mark) {
-  constexpr int RPB = row_block(N);
-  constexpr int CB = cols_per_block(N);
-  ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0};
+  constexpr int RPB = row_block(NY, NX);
+  constexpr int CB = cols_per_block(NY, NX);
+  ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0, g.trans};
   mark(CCPT_STAGE_ROWS_FWD, 1);
-  hipLaunchKernelGGL((k_rows_fwd<N, RPB, float2>), dim3(N / RPB, g.count), dim3(kThreads), 0, s,
-                     src, g.mode == CCPT_MODE_CCSN ? 2 : 0, (double)g.eps, g.T, g.st, g.tw);
+  hipLaunchKernelGGL((k_rows_fwd<NY, NX, RPB, float2>), dim3(NY / RPB, g.count), dim3(kThreads), 0,
+                     s, src, g.mode == CCPT_MODE_CCSN ? 2 : 0, (double)g.eps, g.T, g.st, g.tw);
   mark(CCPT_STAGE_ROWS_FWD, 0);
   mark(CCPT_STAGE_COLS, 1);
-  hipLaunchKernelGGL((k_cols<N, CB, COL_XCORR, float2>), dim3((N / 2 + CB - 1) / CB, g.count),
+  hipLaunchKernelGGL((k_cols<NY, NX, CB, COL_XCORR, float2>), dim3((NX / 2 + CB - 1) / CB, g.count),
                      dim3(kThreads), 0, s, g.desc, g.first, g.T, g.X, g.Xb, (float2*)nullptr, 0L,
                      g.tw);
   mark(CCPT_STAGE_COLS, 0);
   mark(CCPT_STAGE_ROWS_INV, 1);
-  hipLaunchKernelGGL((k_rows_inv<N, RPB, true, float2>), dim3(N / RPB, g.count), dim3(kThreads), 0,
-                     s, g.T, g.st, (float*)nullptr, 1.0f, g.tw, (PeakCand*)nullptr);
+  hipLaunchKernelGGL((k_rows_inv<NY, NX, RPB, true, float2>), dim3(NY / RPB, g.count),
+                     dim3(kThreads), 0, s, g.T, g.st, (float*)nullptr, 1.0f, g.tw,
+                     (PeakCand*)nullptr, g.trans);
   mark(CCPT_STAGE_ROWS_INV, 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -477,53 +501,55 @@ template <int N>
 static int xcorr64_n(const GroupParams& g, hipStream_t s, const Marker& mark) {
   constexpr int RPB = row_block64(N);
   constexpr int CB = cols_per_block64(N);
-  ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0};
+  ImgSrc src{g.desc, g.first, nullptr, 0, 0, 0, 0};
   mark(CCPT_STAGE_ROWS_FWD, 1);
-  hipLaunchKernelGGL((k_rows_fwd<N, RPB, double2>), dim3(N / RPB, g.count), dim3(kThreads), 0, s,
-                     src, g.mode == CCPT_MODE_CCSN ? 2 : 0, g.eps64, g.T64, g.st, g.tw64);
+  hipLaunchKernelGGL((k_rows_fwd<N, N, RPB, double2>), dim3(N / RPB, g.count), dim3(kThreads), 0,
+                     s, src, g.mode == CCPT_MODE_CCSN ? 2 : 0, g.eps64, g.T64, g.st, g.tw64);
   mark(CCPT_STAGE_ROWS_FWD, 0);
   mark(CCPT_STAGE_COLS, 1);
-  hipLaunchKernelGGL((k_cols<N, CB, COL_XCORR, double2>), dim3((N / 2 + CB - 1) / CB, g.count),
+  hipLaunchKernelGGL((k_cols<N, N, CB, COL_XCORR, double2>), dim3((N / 2 + CB - 1) / CB, g.count),
                      dim3(kThreads), 0, s, g.desc, g.first, g.T64, g.X64, (unsigned*)nullptr,
                      (double2*)nullptr, 0L, g.tw64);
   mark(CCPT_STAGE_COLS, 0);
   mark(CCPT_STAGE_ROWS_INV, 1);
-  hipLaunchKernelGGL((k_rows_inv<N, RPB, true, double2>), dim3(N / RPB, g.count), dim3(kThreads),
-                     0, s, g.T64, g.st, (float*)nullptr, 1.0f, g.tw64, g.cand);
+  hipLaunchKernelGGL((k_rows_inv<N, N, RPB, true, double2>), dim3(N / RPB, g.count),
+                     dim3(kThreads), 0, s, g.T64, g.st, (float*)nullptr, 1.0f, g.tw64, g.cand, 0);
   mark(CCPT_STAGE_ROWS_INV, 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int N, typename C>
-static int spectrum_n(const void* data, int dtype, int pitch, long img_stride, int n, int weight,
-                      double eps, int conj_out, C* T, C* spec, const C* tw, hipStream_t s) {
-  constexpr int RPB = row_block_of<C>(N);
-  constexpr int CB = cols_block_of<C>(N);
-  constexpr int H = N / 2 + 1;
-  ImgSrc src{nullptr, 0, data, dtype, pitch, img_stride};
-  hipLaunchKernelGGL((k_rows_fwd<N, RPB, C>), dim3(N / RPB, n), dim3(kThreads), 0, s, src, weight,
-                     eps, T, (FrameState*)nullptr, tw);
+template <int NY, int NX, typename C>
+static int spectrum_n(const void* data, int dtype, int pitch, long img_stride, int trans, int n,
+                      int weight, double eps, int conj_out, C* T, C* spec, const C* tw,
+                      hipStream_t s) {
+  constexpr int RPB = row_block_of<C>(NY, NX);
+  constexpr int CB = cols_block_of<C>(NY, NX);
+  constexpr int H = NX / 2 + 1;
+  ImgSrc src{nullptr, 0, data, dtype, pitch, img_stride, trans};
+  hipLaunchKernelGGL((k_rows_fwd<NY, NX, RPB, C>), dim3(NY / RPB, n), dim3(kThreads), 0, s, src,
+                     weight, eps, T, (FrameState*)nullptr, tw);
   if (conj_out)
-    hipLaunchKernelGGL((k_cols<N, CB, COL_FWD_CONJ, C>), dim3((N / 2 + CB - 1) / CB, n),
+    hipLaunchKernelGGL((k_cols<NY, NX, CB, COL_FWD_CONJ, C>), dim3((NX / 2 + CB - 1) / CB, n),
                        dim3(kThreads), 0, s, (const FrameDesc*)nullptr, 0, T, (C*)nullptr,
-                       (unsigned*)nullptr, spec, (long)N * H, tw);
+                       (unsigned*)nullptr, spec, (long)NY * H, tw);
   else
-    hipLaunchKernelGGL((k_cols<N, CB, COL_FWD, C>), dim3((N / 2 + CB - 1) / CB, n), dim3(kThreads),
-                       0, s, (const FrameDesc*)nullptr, 0, T, (C*)nullptr, (unsigned*)nullptr,
-                       spec, (long)N * H, tw);
+    hipLaunchKernelGGL((k_cols<NY, NX, CB, COL_FWD, C>), dim3((NX / 2 + CB - 1) / CB, n),
+                       dim3(kThreads), 0, s, (const FrameDesc*)nullptr, 0, T, (C*)nullptr,
+                       (unsigned*)nullptr, spec, (long)NY * H, tw);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int N>
 static int frame_spectra_n(const FrameDesc* desc, int first, int count, int mode, float eps,
                            float2* T, float2* spec, const float2* tw, hipStream_t s) {
-  constexpr int RPB = row_block(N);
-  constexpr int CB = cols_per_block(N);
+  constexpr int RPB = row_block(N, N);
+  constexpr int CB = cols_per_block(N, N);
   constexpr int H = N / 2 + 1;
-  ImgSrc src{desc, first, nullptr, 0, 0, 0};
-  hipLaunchKernelGGL((k_rows_fwd<N, RPB, float2>), dim3(N / RPB, count), dim3(kThreads), 0, s, src,
-                     mode == CCPT_MODE_CCSN ? 2 : 0, (double)eps, T, (FrameState*)nullptr, tw);
-  hipLaunchKernelGGL((k_cols<N, CB, COL_FWD, float2>), dim3((N / 2 + CB - 1) / CB, count),
+  ImgSrc src{desc, first, nullptr, 0, 0, 0, 0};
+  hipLaunchKernelGGL((k_rows_fwd<N, N, RPB, float2>), dim3(N / RPB, count), dim3(kThreads), 0, s,
+                     src, mode == CCPT_MODE_CCSN ? 2 : 0, (double)eps, T, (FrameState*)nullptr,
+                     tw);
+  hipLaunchKernelGGL((k_cols<N, N, CB, COL_FWD, float2>), dim3((N / 2 + CB - 1) / CB, count),
                      dim3(kThreads), 0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr,
                      (unsigned*)nullptr, spec, (long)N * H, tw);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -532,29 +558,32 @@ static int frame_spectra_n(const FrameDesc* desc, int first, int count, int mode
 template <int N>
 static int inverse_n(const float2* spec, int n, float scale, float2* T, float* img,
                      const float2* tw, hipStream_t s) {
-  constexpr int RPB = row_block(N);
-  constexpr int CB = cols_per_block(N);
+  constexpr int RPB = row_block(N, N);
+  constexpr int CB = cols_per_block(N, N);
   constexpr int H = N / 2 + 1;
-  hipLaunchKernelGGL((k_cols<N, CB, COL_INV, float2>), dim3((N / 2 + CB - 1) / CB, n),
+  hipLaunchKernelGGL((k_cols<N, N, CB, COL_INV, float2>), dim3((N / 2 + CB - 1) / CB, n),
                      dim3(kThreads), 0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr,
                      (unsigned*)nullptr, (float2*)spec, (long)N * H, tw);
-  hipLaunchKernelGGL((k_rows_inv<N, RPB, false, float2>), dim3(N / RPB, n), dim3(kThreads), 0, s,
-                     T, (FrameState*)nullptr, img, scale, tw, (PeakCand*)nullptr);
+  hipLaunchKernelGGL((k_rows_inv<N, N, RPB, false, float2>), dim3(N / RPB, n), dim3(kThreads), 0,
+                     s, T, (FrameState*)nullptr, img, scale, tw, (PeakCand*)nullptr, 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-#define CCPT_FOR_SIZES(X) \
-  X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) X(192) \
-  X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
-
-int launch_xcorr(int N, const GroupParams& g, hipStream_t s, const Marker& mark) {
-  switch (N) {
+int launch_xcorr(int ny, int nx, const GroupParams& g, hipStream_t s, const Marker& mark) {
+  if (ny == nx) {
+    switch (ny) {
 #define CASE(n) \
   case n:       \
-    return xcorr_n<n>(g, s, mark);
-    CCPT_FOR_SIZES(CASE)
+    return xcorr_n<n, n>(g, s, mark);
+      CCPT_FOR_SIZES(CASE)
 #undef CASE
+    }
+    return -2;
   }
+#define CASE(a, b) \
+  if (ny == a && nx == b) return xcorr_n<a, b>(g, s, mark);
+  CCPT_FOR_RECT(CASE)
+#undef CASE
   return -2;
 }
 
@@ -575,17 +604,26 @@ int launch_xcorr64(int N, const GroupParams& g, hipStream_t s, const Marker& mar
   return -2;
 }
 
-int launch_spectrum(int N, const void* data, int dtype, int pitch, long img_stride, int n,
-                    int weight, float eps, int conj_out, float2* T, float2* spec,
+int launch_spectrum(int ny, int nx, const void* data, int dtype, int pitch, long img_stride,
+                    int trans, int n, int weight, float eps, int conj_out, float2* T, float2* spec,
                     const float2* tw, hipStream_t s) {
-  switch (N) {
-#define CASE(nn)                                                                                \
-  case nn:                                                                                      \
-    return spectrum_n<nn, float2>(data, dtype, pitch, img_stride, n, weight, (double)eps,       \
-                                  conj_out, T, spec, tw, s);
-    CCPT_FOR_SIZES(CASE)
+  if (ny == nx) {
+    switch (ny) {
+#define CASE(nn)                                                                                 \
+  case nn:                                                                                       \
+    return spectrum_n<nn, nn, float2>(data, dtype, pitch, img_stride, 0, n, weight, (double)eps, \
+                                      conj_out, T, spec, tw, s);
+      CCPT_FOR_SIZES(CASE)
 #undef CASE
+    }
+    return -2;
   }
+#define CASE(a, b)                                                                            \
+  if (ny == a && nx == b)                                                                     \
+    return spectrum_n<a, b, float2>(data, dtype, pitch, img_stride, trans, n, weight,         \
+                                    (double)eps, conj_out, T, spec, tw, s);
+  CCPT_FOR_RECT(CASE)
+#undef CASE
   return -2;
 }
 
@@ -593,10 +631,10 @@ int launch_spectrum64(int N, const void* data, int dtype, int pitch, long img_st
                       int weight, double eps, int conj_out, double2* T, double2* spec,
                       const double2* tw, hipStream_t s) {
   switch (N) {
-#define CASE(nn)                                                                                 \
-  case nn:                                                                                       \
-    return spectrum_n<nn, double2>(data, dtype, pitch, img_stride, n, weight, eps, conj_out, T,  \
-                                   spec, tw, s);
+#define CASE(nn)                                                                                \
+  case nn:                                                                                      \
+    return spectrum_n<nn, nn, double2>(data, dtype, pitch, img_stride, 0, n, weight, eps,       \
+                                       conj_out, T, spec, tw, s);
     CCPT_FOR_SIZES(CASE)
 #undef CASE
   }
