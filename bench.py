@@ -221,34 +221,48 @@ def leg_grad128(dev, torch, Tracker):
                 adam_step_ms=round(adam * 1e3, 3), loss_first=losses[0], loss_last=losses[-1])
 
 
-# Table I of the paper (CC-SN throughput on an RTX 3080, images/s) at the
-# square shapes, for context beside the same settings here
-TABLE1_RTX3080 = {(256, 128): 981, (256, 256): 432, (256, 512): 189, (256, 1024): 67.0,
-                  (512, 128): 348, (512, 256): 169, (512, 512): 93, (512, 1024): 31.1}
+# Table I of the paper: CC-SN throughput on an RTX 3080 (images/s) for its
+# image sizes (width x height) and u = 128, 256, 512, 1024; context for the
+# same settings here.  Keys are (rows, columns).
+TABLE1_RTX3080 = {
+    (128, 256): {128: 1636, 256: 811, 512: 325, 1024: 91.9},
+    (256, 256): {128: 981, 256: 432, 512: 189, 1024: 67.0},
+    (256, 512): {128: 670, 256: 322, 512: 168, 1024: 58.6},
+    (512, 512): {128: 348, 256: 169, 512: 93, 1024: 31.1},
+    (128, 1024): {128: 717, 256: 360, 512: 227, 1024: 85.3},
+}
 
 
 def leg_table1(dev, torch, Tracker):
-    """CC-SN (eps = 200) batched split-precision throughput at Table I's
-    square shapes, 256x256 and 512x512, for u = 128, 256, 512, 1024
-    (grids of 192 to 1536 points a side); 512 frames per shape."""
+    """CC-SN (eps = 200) batched split-precision throughput at Table I's five
+    image sizes (rows x columns 128x256, 256x256, 256x512, 512x512,
+    128x1024: the paper's width x height) for u = 128 .. 1024 (grids of 192
+    to 1536 points a side), 512 Airy-ring frames each; the rectangles also
+    held tall (transposed input) at u = 128."""
     from synth import frames as S
     out = {}
-    for N, gen in ((256, S.config2), (512, S.config4)):
-        w = gen(512)
-        fr = torch.from_numpy(np.stack(w.frames)).to(dev)
-        ref = torch.from_numpy(w.refs[0].astype(np.float32)).to(dev)
+    cases = [(shape, u) for shape in TABLE1_RTX3080 for u in (128, 256, 512, 1024)]
+    cases += [((nx, ny), 128) for (ny, nx) in TABLE1_RTX3080 if ny != nx]
+    made = {}
+    for (ny, nx), u in cases:
+        if (ny, nx) not in made:
+            made.clear()
+            w = S.table1_frames(ny, nx, 512)
+            made[(ny, nx)] = (torch.from_numpy(np.stack(w.frames)).to(dev),
+                              torch.from_numpy(w.refs[0].astype(np.float32)).to(dev))
+        fr, ref = made[(ny, nx)]
         res = torch.empty((fr.shape[0], 72), dtype=torch.uint8, device=dev)
-        for u in (128, 256, 512, 1024):
-            tr = Tracker(upsample=u, precision="bf16x2", mode="ccsn", eps=200.0)
-            tr.set_reference(ref)
-            rois = tr.rois(fr)
-            dt = _sync_time(lambda: tr.track(None, out=res, rois=rois), 3, torch)
-            out[f"{N}x{N}_u{u}"] = dict(frames_per_s=round(fr.shape[0] / dt, 1),
-                                        paper_rtx3080_images_per_s=TABLE1_RTX3080[(N, u)])
-            tr.close()
-        del fr, res
+        tr = Tracker(upsample=u, precision="bf16x2", mode="ccsn", eps=200.0)
+        tr.set_reference(ref)
+        rois = tr.rois(fr)
+        dt = _sync_time(lambda: tr.track(None, out=res, rois=rois), 3, torch)
+        rec = dict(frames_per_s=round(fr.shape[0] / dt, 1))
+        paper = TABLE1_RTX3080.get((ny, nx), {}).get(u)
+        if paper is not None:
+            rec["paper_rtx3080_images_per_s"] = paper
+        out[f"{ny}x{nx}_u{u}"] = rec
+        tr.close()
     return out
-
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
