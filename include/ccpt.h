@@ -25,8 +25,19 @@
  *    offsets (m - floor(M/2))/u; ties go to the lowest row-major index;
  *  - integer lags are reported in [-N/2, N/2).
  *
- * Supported sizes: square N x N frames with N = 2^a 3^b, a >= 1,
- * 16 <= N <= 512.  Other shapes return CCPT_E_UNSUPPORTED.
+ * Supported shapes (ny rows x nx columns): square N x N frames with
+ * N = 2^a 3^b, a >= 1, 16 <= N <= 512, and the rectangles of the paper's
+ * Table I, 256x128, 512x256 and 1024x128, in either orientation (the
+ * longer side as rows or as columns).  Rectangles are tracked by
+ * ccpt_set_reference / ccpt_track_batch in FP32 and BF16X2 precision; the
+ * adjoint, the Fisher information, the reference updates and the FP64
+ * precision take square frames only.  Other shapes, and rectangles where
+ * only squares are taken, return CCPT_E_UNSUPPORTED.
+ *
+ * Rectangles: the Nyquist conventions above apply per axis (N/2 of that
+ * axis); integer lags are in [-ny/2, ny/2) x [-nx/2, nx/2); C is
+ * normalised by 1/(ny nx); ties go to the lowest row-major index of the
+ * frame as given.
  *
  * Memory: every image/frame pointer, `out`, the gradient inputs and
  * outputs are DEVICE pointers owned by the caller.  The small descriptor
@@ -66,8 +77,11 @@ extern "C" {
 #define CCPT_ST_NONFINITE 1u       /* NaN/Inf pixel: d, d_grid, peak are NaN */
 #define CCPT_ST_FLAT 2u            /* constant frame: everything is zero */
 #define CCPT_ST_NEAR_TIE 4u        /* reserved: top two integer lags within 1e-5 */
-#define CCPT_ST_NEWTON_FALLBACK 8u /* Hessian not negative definite or step > 1/u:
-                                      d = d_grid */
+#define CCPT_ST_NEWTON_FALLBACK 8u /* Hessian not negative definite, or a step
+                                      longer than 1/u (FP64 precision) or
+                                      max(1/u, 0.05 px) (FP32, BF16X2, whose
+                                      grid maximum can sit a few grid points
+                                      off at large u): d = d_grid */
 #define CCPT_ST_WINDOW_EXIT 16u    /* Newton left the 0.75-px half window:
                                       d = d_grid */
 
@@ -142,7 +156,7 @@ typedef struct ccpt_roi {
 /* one tracking result, 72 bytes, written to device memory */
 typedef struct ccpt_result {
   double d[2];     /* refined displacement (y, x), px */
-  double peak;     /* C(d) = band-limited correlation at d, normalised by 1/N^2 */
+  double peak;     /* C(d) = band-limited correlation at d, normalised by 1/(ny nx) */
   double hess[3];  /* d2C/dy2, d2C/dydx, d2C/dx2 at d (used by the adjoint) */
   float d_grid[2]; /* maximum of the upsampled grid (the paper's estimate) */
   int p[2];        /* integer-lag correlation maximum (y, x) */
