@@ -264,6 +264,21 @@ def leg_table1(dev, torch, Tracker):
         tr.close()
     return out
 
+
+def leg_fig1(dev, torch, Tracker):
+    """The accuracy study of Fig. 1 at its centre point: 512x512 frames,
+    u = 512, w0 = 32, the three image types, 256 frames each; the spread of
+    CC-U and CC-SN over the Cramer-Rao bound and the tracking rate."""
+    from paper_2310_08770_amd.accuracy import run_condition
+    from synth import frames as S
+    out = {}
+    for kind in S.FIG1_KINDS:
+        r = run_condition(kind, 32, 1.0, 256, device=dev.index or 0)
+        out[kind] = {m: dict(over_crb=round(r[m]["over_crb"], 3), over_snl=round(r[m]["over_snl"], 3),
+                             frames_per_s=r[m]["frames_per_s"]) for m in ("ccu", "ccsn")}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,7 +291,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-frame legs")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the other workloads (mixed ROIs, 512x512 u=200, 128x128 gradients)")
+                    help="skip the other workloads (mixed ROIs, 512x512 u=200, 128x128 gradients, Table I, Fig. 1)")
     ap.add_argument("--no-tune", action="store_true", help="skip the chunk autotuner")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (counter calibration)")
@@ -432,7 +447,8 @@ def main():
     # ---- the other workloads (each guarded: a failure is recorded, not fatal)
     if not args.no_extra:
         for name, fn in (("uneven_rois_u100", leg_uneven_rois), ("gauss512_u200", leg_gauss512),
-                         ("gauss128_grad", leg_grad128), ("table1_ccsn", leg_table1)):
+                         ("gauss128_grad", leg_grad128), ("table1_ccsn", leg_table1),
+                         ("fig1_w32", leg_fig1)):
             t0 = time.perf_counter()
             try:
                 legs[name] = fn(dev, torch, Tracker)

@@ -79,9 +79,10 @@ extern "C" {
 #define CCPT_ST_NEAR_TIE 4u        /* reserved: top two integer lags within 1e-5 */
 #define CCPT_ST_NEWTON_FALLBACK 8u /* Hessian not negative definite, or a step
                                       longer than 1/u (FP64 precision) or
-                                      max(1/u, 0.05 px) (FP32, BF16X2, whose
-                                      grid maximum can sit a few grid points
-                                      off at large u): d = d_grid */
+                                      than half the window (FP32, BF16X2,
+                                      whose grid maximum can sit well off
+                                      the true one where the correlation is
+                                      flat): d = d_grid */
 #define CCPT_ST_WINDOW_EXIT 16u    /* Newton left the 0.75-px half window:
                                       d = d_grid */
 

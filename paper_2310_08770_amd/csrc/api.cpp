@@ -173,11 +173,17 @@ int set_device(ccpt_ctx* ctx) {
 bool fp64(const ccpt_ctx* ctx) { return ctx->o.precision == CCPT_PREC_FP64; }
 bool split(const ccpt_ctx* ctx) { return ctx->o.precision == CCPT_PREC_BF16X2; }
 
+// Longest Newton step before the result falls back to the grid estimate.
+// An FP64 grid locates the maximum to a grid step, so a longer step means
+// Newton and grid disagree.  FP32 and split-precision grids do not: where
+// the correlation is flat near its maximum relative to its size (broad
+// spots, the large constant term of CC-SN, large u) neighbouring grid values
+// differ by less than their rounding, and the grid maximum can sit tenths of
+// a pixel from the true one; their steps are bounded by the half window
+// only (the Hessian test and the window test still apply).
 double step_limit(const ccpt_ctx* ctx) {
   const double grid = 1.0 / ctx->o.upsample;
-  // FP32 and split-precision grids locate the maximum less exactly than one
-  // grid step at large u; FP64 grids keep the bound of one grid step
-  return fp64(ctx) ? grid : std::max(grid, kReducedStepLimit);
+  return fp64(ctx) ? grid : std::max(grid, 0.5 * ctx->o.window);
 }
 
 template <typename T>

@@ -22,12 +22,6 @@
 
 namespace ccpt {
 
-// Newton step bound (px) when the grid was computed in FP32 or split
-// precision: near the maximum the grid values differ by less than their
-// rounding once u reaches a few hundred, so the grid maximum can sit several
-// grid points from the FP64 one.
-constexpr double kReducedStepLimit = 0.05;
-
 // Stage B contraction length, padded for the matrix-core K step.
 constexpr int stage_b_k(int n) { return (n + 31) / 32 * 32; }
 

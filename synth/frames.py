@@ -263,4 +263,52 @@ def table1_frames(ny: int, nx: int, n_frames: int = 512) -> Workload:
                     shifts, "u16", 128, dict(peak=4000.0, bg=50.0, first_zero=8.0))
 
 
+#: sensor constants of the paper's synthetic study (Sec. IV): full-well
+#: capacity and dark noise of the Sony IMX250, in electrons
+SATURATION_E = 10700.0
+DARK_NOISE_E = 2.4
+
+#: image types of Fig. 1: (a) bright spot, no dark noise; (b) bright spot
+#: with dark noise; (c) dark spot on a bright background with dark noise
+FIG1_KINDS = ("bright", "bright_dark", "dark_spot")
+
+
+def fig1_mean(kind: str, w0: float, n: int = 512) -> tuple:
+    """Noiseless mean image of a Fig. 1 condition and its spot photon count.
+
+    A pixel-integrated Gaussian of width w0 = 2 sigma at the image centre.
+    Dark noise is a constant b = 2.4^2 e- added before the Poisson draw (so
+    its standard deviation is 2.4 e-).  The brightest pixel is at the
+    saturation capacity: bright spots have amplitude S - b on b (b = 0 when
+    there is no dark noise); the dark spot is a full-depth dip
+    b + (S - b)(1 - g).  Returns (mu, N_gamma) with N_gamma the photons in
+    the Gaussian (bright) or missing from it (dark spot)."""
+    b = 0.0 if kind == "bright" else DARK_NOISE_E ** 2
+    g = gaussian_spot(n, w0 / 2.0, 1.0)
+    g = g / g.max()
+    amp = SATURATION_E - b
+    if kind == "dark_spot":
+        mu = b + amp * (1.0 - g)
+    elif kind in ("bright", "bright_dark"):
+        mu = b + amp * g
+    else:
+        raise ValueError(kind)
+    return zero_nyquist(mu), float(amp * g.sum())
+
+
+def fig1_frames(kind: str, w0: float, n_frames: int, gain: float = 1.0, n: int = 512) -> Workload:
+    """Frames of one Fig. 1 condition: the mean image shifted by exactly
+    known displacements uniform in +-2 px, then gain * Poisson(mu / gain)
+    (a noise gain g leaves the mean and multiplies the variance by g).
+    Float32 frames; the reference is the unshifted mean; u = 512."""
+    k = 200 + 10 * FIG1_KINDS.index(kind) + int(round(math.log2(w0))) + 1000 * int(round(math.log2(gain)))
+    rng = rng_for(k)
+    shifts = rng.uniform(-2.0, 2.0, size=(n_frames, 2))
+    mu, n_gamma = fig1_mean(kind, w0, n)
+    lam = _make_frames(mu / gain, 0.0, shifts, k, None, np.float64, chunk=8)
+    frames = [(gain * f).astype(np.float32) for f in lam]
+    return Workload(f"fig1_{kind}_w{w0:g}_g{gain:g}", frames, [mu], np.zeros(n_frames, np.int32),
+                    shifts, "f32", 512, dict(kind=kind, w0=w0, gain=gain, n_gamma=n_gamma))
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
