@@ -61,13 +61,30 @@ __device__ __forceinline__ unsigned bf16_bits(float f) {
 }
 __device__ __forceinline__ float bf16_float(unsigned h) { return __uint_as_float(h << 16); }
 
+typedef __bf16 bf16x2_v __attribute__((ext_vector_type(2)));
+typedef float f32x2_v __attribute__((ext_vector_type(2)));
+
+// bf16 (round to nearest even) of two floats, packed a | b << 16: the same
+// bits as bf16_bits for finite values, in one conversion instruction
+__device__ __forceinline__ unsigned bf16_pack(float a, float b) {
+  const f32x2_v v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_v));
+}
+// the low and high halves of a packed pair as floats
+__device__ __forceinline__ float bf16_lo_float(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi_float(unsigned w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// bf16 hi + lo split of two floats (x ~ hi + lo to about 16 significant
+// bits), each packed as a | b << 16.
+__device__ __forceinline__ void split2(float a, float b, unsigned& hi, unsigned& lo) {
+  hi = bf16_pack(a, b);
+  lo = bf16_pack(a - bf16_lo_float(hi), b - bf16_hi_float(hi));
+}
+
 // Splits a complex value into bf16 hi + lo words (re in the low half, im in
 // the high half of each word): v ~ hi + lo to about 16 significant bits.
 __device__ __forceinline__ void split_pair(float2 v, unsigned& hi, unsigned& lo) {
-  const unsigned hr = bf16_bits(v.x), hm = bf16_bits(v.y);
-  const unsigned lr = bf16_bits(v.x - bf16_float(hr)), lm = bf16_bits(v.y - bf16_float(hm));
-  hi = hr | (hm << 16);
-  lo = lr | (lm << 16);
+  split2(v.x, v.y, hi, lo);
 }
 
 // LDS layout of an FFT sequence: element i sits at lds_idx(i), with one

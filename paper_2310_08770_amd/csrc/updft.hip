@@ -457,17 +457,23 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
   for (int t = 0; t < TPW; ++t) {
     const int kx = (wave + 4 * t) * 32 + j;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = (v >> 2) * 8 + h * 4 + (v & 3);
+    for (int v = 0; v < 16; v += 2) {
+      const int i = (v >> 2) * 8 + h * 4 + (v & 3);  // rows i and i + 1
       if (kx < NC) {
-        const unsigned a = bf16_bits(accr[t][v]);
+        unsigned a, al;
+        split2(accr[t][v], accr[t][v + 1], a, al);
         ymh[i * YST + kx] = (unsigned short)a;
-        yml[i * YST + kx] = (unsigned short)bf16_bits(accr[t][v] - bf16_float(a));
+        ymh[(i + 1) * YST + kx] = (unsigned short)(a >> 16);
+        yml[i * YST + kx] = (unsigned short)al;
+        yml[(i + 1) * YST + kx] = (unsigned short)(al >> 16);
       }
       if (kx >= 1 && kx < NC) {
-        const unsigned b = bf16_bits(acci[t][v]);
+        unsigned b, bl;
+        split2(acci[t][v], acci[t][v + 1], b, bl);
         ymh[i * YST + NC + kx] = (unsigned short)b;
-        yml[i * YST + NC + kx] = (unsigned short)bf16_bits(acci[t][v] - bf16_float(b));
+        ymh[(i + 1) * YST + NC + kx] = (unsigned short)(b >> 16);
+        yml[i * YST + NC + kx] = (unsigned short)bl;
+        yml[(i + 1) * YST + NC + kx] = (unsigned short)(bl >> 16);
       }
     }
   }
@@ -476,9 +482,10 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
     float sacc = 0.f;
     for (int q = 0; q < 8; ++q) sacc += nyq[q][tid];
     if (ix & 1) sacc = -sacc;  // exp(i pi p_x)
-    const unsigned a = bf16_bits(sacc);
+    unsigned a, al;
+    split2(sacc, 0.f, a, al);
     ymh[tid * YST + NC] = (unsigned short)a;
-    yml[tid * YST + NC] = (unsigned short)bf16_bits(sacc - bf16_float(a));
+    yml[tid * YST + NC] = (unsigned short)al;
   }
   __syncthreads();
 
@@ -743,18 +750,23 @@ __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
         yml[r * YST + c] = 0;
       }
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int i = (v >> 2) * 8 + h * 4 + (v & 3);
+      for (int v = 0; v < 16; v += 2) {
+        const int i = (v >> 2) * 8 + h * 4 + (v & 3);  // rows i and i + 1
         if (BFULL || bvalid) {
-          const float yr = accr[t][v];
-          const unsigned a = bf16_bits(yr);
+          unsigned a, al;
+          split2(accr[t][v], accr[t][v + 1], a, al);
           ymh[i * YST + kxrow] = (unsigned short)a;
-          yml[i * YST + kxrow] = (unsigned short)bf16_bits(yr - bf16_float(a));
-          const float yi = kxrow == 0 ? nyq_sign * acci[t][v] : acci[t][v];
+          ymh[(i + 1) * YST + kxrow] = (unsigned short)(a >> 16);
+          yml[i * YST + kxrow] = (unsigned short)al;
+          yml[(i + 1) * YST + kxrow] = (unsigned short)(al >> 16);
+          const float sg = kxrow == 0 ? nyq_sign : 1.f;
           const int col = NC + kxrow;  // Yi of kx, or the Nyquist output for kx = 0
-          const unsigned b = bf16_bits(yi);
+          unsigned b, bl;
+          split2(sg * acci[t][v], sg * acci[t][v + 1], b, bl);
           ymh[i * YST + col] = (unsigned short)b;
-          yml[i * YST + col] = (unsigned short)bf16_bits(yi - bf16_float(b));
+          ymh[(i + 1) * YST + col] = (unsigned short)(b >> 16);
+          yml[i * YST + col] = (unsigned short)bl;
+          yml[(i + 1) * YST + col] = (unsigned short)(bl >> 16);
         }
       }
     }
