@@ -778,7 +778,7 @@ __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
       for (int r = 0; r < 2 * GB; ++r) acc[r] = acc2[r] = acc3[r] = f32x4{0.f, 0.f, 0.f, 0.f};
       const unsigned short* bh_p = WbT + (size_t)(nt * 16 + l16) * KB + 8 * q4;
       const unsigned short* bl_p = WbL + (size_t)(nt * 16 + l16) * KB + 8 * q4;
-#pragma unroll 2
+#pragma unroll 4
       for (int k = 0; k < KB; k += 32) {
         const bf16x8 w_h = as_bf(*(const u32x4*)(bh_p + k));
         const bf16x8 w_l = as_bf(*(const u32x4*)(bl_p + k));
