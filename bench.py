@@ -400,6 +400,24 @@ def main():
         r2 = None
         legs[f"batched_{other}"] = dict(error=str(e)[:200])
 
+    # the headline precision with alternate chunks on two streams (CCPT_FLAG_STREAMS):
+    # the DFT of one chunk overlaps the FFTs of the next; results are bit-identical
+    try:
+        tr3 = Tracker(upsample=w.u, precision=args.precision, streams=2)
+        tr3.set_reference(ref_t)
+        chunk3 = tr3.chunk(N) if args.no_tune else tr3.autotune(N, n)
+        out3 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
+        k3 = max(3, args.steps // 3)
+        tot3, lat3 = time_batched(tr3, frames_t, tr3.rois(frames_t), out3, k3, 2, torch)
+        legs[f"batched_{args.precision}_two_streams"] = dict(
+            frames_per_s=round(n * k3 / tot3, 1), chunk=chunk3,
+            p50_ms=round(float(np.median(lat3)) * 1e3, 3),
+            bit_identical=bool(torch.equal(out3, out)))
+        log(f"[bench] two streams: {n * k3 / tot3:,.0f} frames/s (chunk {chunk3})")
+        tr3.close()
+    except Exception as e:  # noqa: BLE001
+        legs[f"batched_{args.precision}_two_streams"] = dict(error=str(e)[:200])
+
     if not args.no_plain:
         for name, graph in (("plain", False), ("graph_stream", True)):
             trp = Tracker(upsample=w.u, precision="fp32", graph=graph)

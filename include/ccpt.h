@@ -108,7 +108,14 @@ enum ccpt_dtype { CCPT_U16 = 0, CCPT_F32 = 1, CCPT_F64 = 2 };
 #define CCPT_FLAG_GRAPH 1   /* capture each batch shape once in a hipGraph and
                                replay it on later calls */
 #define CCPT_FLAG_PROFILE 2 /* bracket every kernel launch with HIP events on the
-                               call's stream (measurement; disables graphs) */
+                               call's stream (measurement; disables graphs and
+                               CCPT_FLAG_STREAMS) */
+#define CCPT_FLAG_STREAMS 4 /* run the chunks of a batch alternately on the call's
+                               stream and a second stream owned by the context
+                               (default priority), forked from and joined back
+                               into the call's stream, so one chunk's matrix-core
+                               work overlaps the next chunk's FFTs; results are
+                               bit-identical, the workspace doubles */
 
 /* stage ids of ccpt_stage_times */
 enum ccpt_stage {

@@ -37,6 +37,7 @@ PRECISIONS = {"fp32": 0, "bf16x2": 1, "fp16x2": 2, "fp64": 3}
 U16, F32, F64 = 0, 1, 2
 FLAG_GRAPH = 1
 FLAG_PROFILE = 2
+FLAG_STREAMS = 4
 STAGES = ["init", "rows_fwd", "cols", "rows_inv", "updft", "newton", "grad"]
 
 RESULT_DTYPE = np.dtype([
@@ -148,7 +149,7 @@ class Tracker:
     """A library context: options, references and workspaces on one GPU."""
 
     def __init__(self, mode="ccu", eps=200.0, upsample=100, window=1.5, precision="fp32",
-                 newton_iters=3, graph=False, profile=False, device=None):
+                 newton_iters=3, graph=False, profile=False, device=None, streams=1):
         L = lib()
         o = Options()
         L.ccpt_default_options(ctypes.byref(o))
@@ -158,7 +159,8 @@ class Tracker:
         o.window = float(window)
         o.precision = PRECISIONS[precision]
         o.newton_iters = int(newton_iters)
-        o.flags = (FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0)
+        o.flags = ((FLAG_GRAPH if graph else 0) | (FLAG_PROFILE if profile else 0) |
+                   (FLAG_STREAMS if streams == 2 else 0))
         self.options = o
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         h = c_void_p()

@@ -134,6 +134,12 @@ struct ccpt_ctx {
   // partial Newton models of small launches
   void* nparts = nullptr;
   size_t nparts_cap = 0;
+  // chunk slots: a group of several chunks runs them alternately on the
+  // caller's stream and `aux`, each slot with its own part of the workspace,
+  // frame states, split-K and Newton partials (strides below, per slot)
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_evt = nullptr, join_evt = nullptr;
+  size_t slot_ws = 0, slot_st = 0, slot_ypart = 0;
   // real-time updates: scratch spectra T and F
   void* rt_buf = nullptr;
   size_t rt_cap = 0;
@@ -279,18 +285,19 @@ int chunk_for(const ccpt_ctx* ctx, int n) {
 
 // Carves the workspace for a chunk of `chunk` frames of size n (every part
 // 16-byte aligned: spectra rows hold an even number of float2).
-void carve(ccpt_ctx* ctx, int n, int chunk, GroupParams& g) {
+void carve(ccpt_ctx* ctx, int n, int chunk, int slot, GroupParams& g) {
   const size_t spec = spec_elems(n);
+  char* ws = ctx->ws + slot * ctx->slot_ws;
+  g.st = ctx->st_buf + slot * ctx->slot_st;
   if (fp64(ctx)) {
     g.T = g.X = nullptr;
     g.Xb = nullptr;
-    g.T64 = (double2*)ctx->ws;
+    g.T64 = (double2*)ws;
     g.X64 = g.T64 + spec * chunk;
     g.cand = (PeakCand*)(g.X64 + spec * chunk);
-    g.st = ctx->st_buf;
     return;
   }
-  g.T = (float2*)ctx->ws;
+  g.T = (float2*)ws;
   g.X = g.T + spec * chunk;
   char* p = (char*)(g.X + spec * chunk);
   g.Xb = nullptr;
@@ -299,7 +306,6 @@ void carve(ccpt_ctx* ctx, int n, int chunk, GroupParams& g) {
     p += split_words(n) * sizeof(unsigned) * chunk;
   }
   (void)p;
-  g.st = ctx->st_buf;
 }
 
 int check_image(ccpt_ctx* ctx, const void* data, int ny, int nx, int pitch, int dtype,
@@ -395,6 +401,13 @@ size_t split_partials_bytes(const ccpt_ctx* ctx, int n, int count) {
   return (size_t)count * mtiles * kSplitSlices * 32 * stage_b_k(code_nx(n)) * sizeof(float);
 }
 
+// With CCPT_FLAG_STREAMS the chunks of one group run on two streams (not
+// when launches are being timed, which needs them in sequence).
+bool use_slots(const ccpt_ctx* ctx) {
+  return ctx->aux != nullptr && (ctx->o.flags & CCPT_FLAG_STREAMS) &&
+         !(ctx->o.flags & CCPT_FLAG_PROFILE);
+}
+
 // Launches the whole tracking sequence for one size group, chunk by chunk.
 int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int count,
               ccpt_result* out, hipStream_t s) {
@@ -403,29 +416,43 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
   const int ny = code_ny(n), nx = code_nx(n);
   UpdftTables ut{t.ky, t.wb, t.Mp, ctx->o.precision, t.kfold};
   const Marker mark = marker_of(ctx, s);
-  for (int c0 = 0; c0 < count; c0 += chunk) {
+  // several chunks: alternate between the two slots (streams s and aux),
+  // forked from and joined back into s
+  const bool two = count > chunk && use_slots(ctx);
+  if (two) {
+    HIP_CHECK(ctx, hipEventRecord(ctx->fork_evt, s));
+    HIP_CHECK(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_evt, 0));
+  }
+  for (int c0 = 0, ci = 0; c0 < count; c0 += chunk, ++ci) {
+    const int slot = two ? (ci & 1) : 0;
+    hipStream_t cs = slot ? ctx->aux : s;
     GroupParams g = base_params(ctx, n);
     g.desc = d_desc;
     g.first = first + c0;
     g.count = std::min(chunk, count - c0);
     g.out = out;
-    carve(ctx, n, chunk, g);
+    carve(ctx, n, chunk, slot, g);
     const size_t yb = split_partials_bytes(ctx, n, g.count);
-    g.ypart = (yb && yb <= ctx->ypart_cap) ? (float*)ctx->ypart : nullptr;
-    g.nparts = (double*)ctx->nparts;
+    g.ypart = (yb && yb <= ctx->slot_ypart) ? (float*)((char*)ctx->ypart + slot * ctx->slot_ypart)
+                                            : nullptr;
+    g.nparts = (double*)ctx->nparts + (size_t)slot * kNewtonSplitMax * kNewtonParts * kNewtonCoef;
     ctx->st_dirty = true;  // until this chunk's Newton launch has gone in
-    if ((fp64(ctx) ? launch_xcorr64(n, g, s, mark) : launch_xcorr(ny, nx, g, s, mark)))
+    if ((fp64(ctx) ? launch_xcorr64(n, g, cs, mark) : launch_xcorr(ny, nx, g, cs, mark)))
       return fail(ctx, CCPT_E_HIP, "correlation launch failed");
     mark(CCPT_STAGE_UPDFT, 1);
-    if ((fp64(ctx) ? launch_updft64(n, g, t.ky64, t.wb64, t.Mp, s)
-                   : launch_updft(ny, nx, g, ut, s)))
+    if ((fp64(ctx) ? launch_updft64(n, g, t.ky64, t.wb64, t.Mp, cs)
+                   : launch_updft(ny, nx, g, ut, cs)))
       return fail(ctx, CCPT_E_HIP, "upsampled DFT launch failed");
     mark(CCPT_STAGE_UPDFT, 0);
     mark(CCPT_STAGE_NEWTON, 1);
-    if (launch_newton(ny, nx, g, step_limit(ctx), s))
+    if (launch_newton(ny, nx, g, step_limit(ctx), cs))
       return fail(ctx, CCPT_E_HIP, "Newton launch failed");
     mark(CCPT_STAGE_NEWTON, 0);
     ctx->st_dirty = false;
+  }
+  if (two) {
+    HIP_CHECK(ctx, hipEventRecord(ctx->join_evt, ctx->aux));
+    HIP_CHECK(ctx, hipStreamWaitEvent(s, ctx->join_evt, 0));
   }
   return CCPT_OK;
 }
@@ -547,7 +574,8 @@ int ensure_state(ccpt_ctx* ctx, size_t count, hipStream_t s) {
     ctx->st_dirty = true;
   }
   if (!ctx->nparts) {
-    const size_t bytes = (size_t)kNewtonSplitMax * kNewtonParts * kNewtonCoef * sizeof(double);
+    // one share per chunk slot
+    const size_t bytes = (size_t)2 * kNewtonSplitMax * kNewtonParts * kNewtonCoef * sizeof(double);
     int rc = ensure_buf(ctx, ctx->nparts, ctx->nparts_cap, bytes);
     if (rc) return rc;
   }
@@ -627,8 +655,11 @@ int ccpt_create(ccpt_ctx** out, int device, const ccpt_options* opts) {
   ctx->c = M / 2;
   if (hipSetDevice(device) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->desc_evt, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->fork_evt, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->join_evt, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->small_evt, hipEventDisableTiming) != hipSuccess) {
-    delete ctx;
+    ccpt_destroy(ctx);
     return CCPT_E_HIP;
   }
   *out = ctx;
@@ -664,6 +695,9 @@ void ccpt_destroy(ccpt_ctx* ctx) {
   if (ctx->d_desc) (void)hipFree(ctx->d_desc);
   if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
   if (ctx->desc_evt) (void)hipEventDestroy(ctx->desc_evt);
+  if (ctx->fork_evt) (void)hipEventDestroy(ctx->fork_evt);
+  if (ctx->join_evt) (void)hipEventDestroy(ctx->join_evt);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   if (ctx->small_evt) (void)hipEventDestroy(ctx->small_evt);
   if (ctx->gsmall) (void)hipFree(ctx->gsmall);
   if (ctx->acc_buf) (void)hipFree(ctx->acc_buf);
@@ -799,19 +833,25 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
   rc = plan_rois(ctx, rois, n, plan);
   if (rc) return rc;
   const std::vector<int>& sig = plan.sig;
+  // per-slot needs; two slots when some group has several chunks
   size_t ws_need = 0;
+  int nslots = 1;
   for (size_t gi = 0; gi < sig.size(); gi += 2) {
     const int nn = sig[gi], cnt = sig[gi + 1];
     const int chunk = std::min(cnt, chunk_for(ctx, nn));
     ws_need = std::max(ws_need, frame_ws_bytes(nn, ctx->o.precision) * (size_t)chunk + 256);
+    if (cnt > chunk && use_slots(ctx)) nslots = 2;
   }
-  rc = ensure_ws(ctx, ws_need);
+  ws_need = (ws_need + 255) / 256 * 256;
+  rc = ensure_ws(ctx, ws_need * nslots);
   if (rc) return rc;
+  ctx->slot_ws = ws_need;
   size_t st_need = 0;
   for (size_t gi = 0; gi < sig.size(); gi += 2)
     st_need = std::max(st_need, (size_t)std::min(sig[gi + 1], chunk_for(ctx, sig[gi])));
-  rc = ensure_state(ctx, st_need, s);
+  rc = ensure_state(ctx, st_need * nslots, s);
   if (rc) return rc;
+  ctx->slot_st = st_need;
   size_t ypart_need = 0;
   for (size_t gi = 0; gi < sig.size(); gi += 2) {
     const int nn = sig[gi], cnt = sig[gi + 1];
@@ -819,11 +859,13 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
     ypart_need = std::max(ypart_need, split_partials_bytes(ctx, nn, ch));
     ypart_need = std::max(ypart_need, split_partials_bytes(ctx, nn, cnt % ch));
   }
-  if (ypart_need > ctx->ypart_cap) {
+  ypart_need = (ypart_need + 255) / 256 * 256;
+  if (ypart_need * nslots > ctx->ypart_cap) {
     drop_graphs(ctx);
-    rc = ensure_buf(ctx, ctx->ypart, ctx->ypart_cap, ypart_need);
+    rc = ensure_buf(ctx, ctx->ypart, ctx->ypart_cap, ypart_need * nslots);
     if (rc) return rc;
   }
+  ctx->slot_ypart = ypart_need;
   rc = upload_desc(ctx, plan.desc, s);
   if (rc) return rc;
 

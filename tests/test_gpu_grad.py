@@ -273,3 +273,38 @@ def test_profile_stage_times():
     for k in ("rows_fwd", "cols", "rows_inv", "updft", "newton"):
         assert st[k][1] >= 1 and st[k][0] > 0
     tr.close()
+
+
+def test_chunks_on_two_streams_match_one_stream():
+    say("case: airy256_u100, 2000 frames in chunks of 256 alternating on two streams vs the same "
+        "launches in sequence on one, bf16x2 and fp32; then three replays of a graph of the "
+        "two-stream launches")
+    from paper_2310_08770_amd import decode
+    w = S.config2(2000)
+    fr = t(np.stack(w.frames))
+    want = {}
+    for prec in ("bf16x2", "fp32"):
+        outs = []
+        for streams in (2, 1):
+            tr = tracker(upsample=100, precision=prec, streams=streams)
+            tr.set_reference(t(w.refs[0].astype(np.float32)))
+            tr.set_chunk(256, 256)
+            outs.append(decode(tr.track(fr)).tobytes())
+            tr.close()
+        assert outs[0] == outs[1], prec
+        want[prec] = outs[1]
+    # the second stream joins the capture through the fork and join events
+    tr = tracker(upsample=100, precision="bf16x2", streams=2, graph=True)
+    tr.set_reference(t(w.refs[0].astype(np.float32)))
+    tr.set_chunk(256, 256)
+    rois = tr.rois(fr)
+    res = torch.empty((fr.shape[0], 72), dtype=torch.uint8, device=DEV)
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            res.zero_()
+            tr.track(None, out=res, rois=rois, stream=side)
+        side.synchronize()
+        assert decode(res).tobytes() == want["bf16x2"], rep
+        _ = (fr[:4].float() * 2.0).sum().item()  # unrelated eager work between replays
+    tr.close()
