@@ -423,6 +423,11 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
     HIP_CHECK(ctx, hipEventRecord(ctx->fork_evt, s));
     HIP_CHECK(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_evt, 0));
   }
+  // a failed launch leaves no work of this call running on the second stream
+  auto failed = [&](const char* what) {
+    if (two) (void)hipStreamSynchronize(ctx->aux);
+    return fail(ctx, CCPT_E_HIP, "%s launch failed", what);
+  };
   for (int c0 = 0, ci = 0; c0 < count; c0 += chunk, ++ci) {
     const int slot = two ? (ci & 1) : 0;
     hipStream_t cs = slot ? ctx->aux : s;
@@ -438,15 +443,15 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
     g.nparts = (double*)ctx->nparts + (size_t)slot * kNewtonSplitMax * kNewtonParts * kNewtonCoef;
     ctx->st_dirty = true;  // until this chunk's Newton launch has gone in
     if ((fp64(ctx) ? launch_xcorr64(n, g, cs, mark) : launch_xcorr(ny, nx, g, cs, mark)))
-      return fail(ctx, CCPT_E_HIP, "correlation launch failed");
+      return failed("correlation");
     mark(CCPT_STAGE_UPDFT, 1);
     if ((fp64(ctx) ? launch_updft64(n, g, t.ky64, t.wb64, t.Mp, cs)
                    : launch_updft(ny, nx, g, ut, cs)))
-      return fail(ctx, CCPT_E_HIP, "upsampled DFT launch failed");
+      return failed("upsampled DFT");
     mark(CCPT_STAGE_UPDFT, 0);
     mark(CCPT_STAGE_NEWTON, 1);
     if (launch_newton(ny, nx, g, step_limit(ctx), cs))
-      return fail(ctx, CCPT_E_HIP, "Newton launch failed");
+      return failed("Newton");
     mark(CCPT_STAGE_NEWTON, 0);
     ctx->st_dirty = false;
   }
