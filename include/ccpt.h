@@ -210,8 +210,8 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
    each, row-major, no pitch), or NULL; g_ref: device floats, one ny*nx
    block per reference in id order, summed over all rois using it, or
    NULL.  Frames whose forward status has NONFINITE, FLAT,
-   NEWTON_FALLBACK or WINDOW_EXIT get zero gradient.  The reference set
-   must be the one used by the forward call. */
+   NEWTON_FALLBACK or WINDOW_EXIT get zero gradient (n = 0 sets g_ref to
+   zeros).  The reference set must be the one used by the forward call. */
 int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_result* fwd,
                     const double* g_d, const double* g_peak, float* g_frames, float* g_ref,
                     void* stream);

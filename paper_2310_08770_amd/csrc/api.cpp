@@ -913,10 +913,18 @@ int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_resul
   if (!ctx) return CCPT_E_INVALID;
   if (n < 0 || (n > 0 && (!rois || !fwd || !g_d)))
     return fail(ctx, CCPT_E_INVALID, "bad gradient arguments");
-  if (n == 0 || (!g_frames && !g_ref)) return CCPT_OK;
+  if (!g_frames && !g_ref) return CCPT_OK;
   int rc = set_device(ctx);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if (n == 0) {
+    // no rois: every reference gradient is an empty sum
+    size_t total = 0;
+    for (const Ref& r : ctx->refs) total += (size_t)code_ny(r.n) * code_nx(r.n);
+    if (g_ref && total && launch_zero(g_ref, total * sizeof(float), s))
+      return fail(ctx, CCPT_E_HIP, "zero launch failed");
+    return CCPT_OK;
+  }
   for (int i = 0; i < n; ++i) {
     rc = require_square(ctx, rois[i].ny, rois[i].nx, "ccpt_track_grad");
     if (rc) return rc;
