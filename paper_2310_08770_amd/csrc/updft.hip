@@ -546,7 +546,9 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
 // chunk's MFMAs run, and K' chunks alternate between two LDS buffers.
 // Stage B converts Y to bf16 hi/lo for up to GB row tiles at a time into
 // LDS, so every W fragment a wave loads from L2 serves 2*GB row halves (W
-// is read 2 times per frame instead of 2*MT).
+// is read 2 times per frame instead of 2*MT); its three products accumulate
+// into one register tile per row half (separate ones per product left the
+// compiler shuffling accumulators beside the pending Stage A tiles).
 template <int NY, int NX, int MT>
 __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
     k_updft_bf16x2_wide(GroupParams g, const unsigned* __restrict__ kfold,
@@ -773,24 +775,54 @@ __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
     __syncthreads();
     // this wave's 16-column W tiles nt = wave, wave + NW, ...; every row half of the group
     for (int nt = wave; nt < nnt; nt += NW) {
-      f32x4 acc[2 * GB], acc2[2 * GB], acc3[2 * GB];
+      f32x4 acc[2 * GB];
 #pragma unroll
-      for (int r = 0; r < 2 * GB; ++r) acc[r] = acc2[r] = acc3[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int r = 0; r < 2 * GB; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
       const unsigned short* bh_p = WbT + (size_t)(nt * 16 + l16) * KB + 8 * q4;
       const unsigned short* bl_p = WbL + (size_t)(nt * 16 + l16) * KB + 8 * q4;
-#pragma unroll 4
-      for (int k = 0; k < KB; k += 32) {
-        const bf16x8 w_h = as_bf(*(const u32x4*)(bh_p + k));
-        const bf16x8 w_l = as_bf(*(const u32x4*)(bl_p + k));
+      // Y fragments of the group's row halves for a k step (LDS).  Where waves
+      // share SIMDs (NW > 4) the next step's load during this step's MFMAs,
+      // which also keeps those sizes from spilling registers.
+      constexpr bool YPRE = NW > 4;
+      bf16x8 a_h[2 * GB], a_l[2 * GB], n_h[2 * GB], n_l[2 * GB];
+      auto load_a = [&](int k, bf16x8* dh, bf16x8* dl) {
 #pragma unroll
         for (int r = 0; r < 2 * GB; ++r) {
           if (r < 2 * gn) {
             const unsigned short* ah_p = ybase + (r >> 1) * SLOT + ((r & 1) * 16 + l16) * YST + 8 * q4;
-            const bf16x8 a_h = as_bf(*(const u32x4*)(ah_p + k));
-            const bf16x8 a_l = as_bf(*(const u32x4*)(ah_p + 32 * YST + k));
-            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_h, acc[r], 0, 0, 0);
-            acc2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, w_l, acc2[r], 0, 0, 0);
-            acc3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, w_h, acc3[r], 0, 0, 0);
+            dh[r] = as_bf(*(const u32x4*)(ah_p + k));
+            dl[r] = as_bf(*(const u32x4*)(ah_p + 32 * YST + k));
+          }
+        }
+      };
+      if constexpr (YPRE) load_a(0, a_h, a_l);
+#pragma unroll 4
+      for (int k = 0; k < KB; k += 32) {
+        const bf16x8 w_h = as_bf(*(const u32x4*)(bh_p + k));
+        const bf16x8 w_l = as_bf(*(const u32x4*)(bl_p + k));
+        if constexpr (YPRE) {
+          if (k + 32 < KB) load_a(k + 32, n_h, n_l);
+          __builtin_amdgcn_sched_barrier(0);
+        } else {
+          load_a(k, a_h, a_l);
+        }
+        // the three products pass by pass over the row halves, into one
+        // accumulator per half (consecutive MFMAs never depend on each other)
+#pragma unroll
+        for (int r = 0; r < 2 * GB; ++r)
+          if (r < 2 * gn) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[r], w_h, acc[r], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 2 * GB; ++r)
+          if (r < 2 * gn) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h[r], w_l, acc[r], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 2 * GB; ++r)
+          if (r < 2 * gn) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l[r], w_h, acc[r], 0, 0, 0);
+        if constexpr (YPRE) {
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int r = 0; r < 2 * GB; ++r) {
+            a_h[r] = n_h[r];
+            a_l[r] = n_l[r];
           }
         }
       }
@@ -799,7 +831,7 @@ __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
         if (r < 2 * gn) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const float uval = acc[r][v] + (acc2[r][v] + acc3[r][v]);
+            const float uval = acc[r][v];
             const int my = m0 + (t0 + (r >> 1)) * 32 + (r & 1) * 16 + q4 * 4 + v;
             const int mx = nt * 16 + l16;
             if (my < g.M && mx < g.M) {
