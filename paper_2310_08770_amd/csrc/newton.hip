@@ -113,7 +113,7 @@ struct ModelSplit {
 // NY rows of NX (a_ky = 2 pi ky~ / NY, b_kx = 2 pi kx / NX, 1/N^2 becomes
 // 1/(NY NX)).
 template <int NY, int NX, typename CX>
-__device__ void build_model(const CX* __restrict__ Xf, double sy, double sx, double2* phy,
+__device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy, double sx, double2* phy,
                             double* ay, double (*red)[kOrder + 1][kOrder + 1],
                             double (*nred)[2 * (kOrder + 1)], double* coef, int ky_lo = 0,
                             int ky_hi = NY) {
