@@ -291,7 +291,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-frame legs")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the other workloads (mixed ROIs, 512x512 u=200, 128x128 gradients, Table I, Fig. 1)")
+                    help="skip the two-stream leg and the other workloads (mixed ROIs, 512x512 u=200, "
+                         "128x128 gradients, Table I, Fig. 1)")
     ap.add_argument("--no-tune", action="store_true", help="skip the chunk autotuner")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (counter calibration)")
@@ -402,21 +403,23 @@ def main():
 
     # the headline precision with alternate chunks on two streams (CCPT_FLAG_STREAMS):
     # the DFT of one chunk overlaps the FFTs of the next; results are bit-identical
-    try:
-        tr3 = Tracker(upsample=w.u, precision=args.precision, streams=2)
-        tr3.set_reference(ref_t)
-        chunk3 = tr3.chunk(N) if args.no_tune else tr3.autotune(N, n)
-        out3 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
-        k3 = max(3, args.steps // 3)
-        tot3, lat3 = time_batched(tr3, frames_t, tr3.rois(frames_t), out3, k3, 2, torch)
-        legs[f"batched_{args.precision}_two_streams"] = dict(
-            frames_per_s=round(n * k3 / tot3, 1), chunk=chunk3,
-            p50_ms=round(float(np.median(lat3)) * 1e3, 3),
-            bit_identical=bool(torch.equal(out3, out)))
-        log(f"[bench] two streams: {n * k3 / tot3:,.0f} frames/s (chunk {chunk3})")
-        tr3.close()
-    except Exception as e:  # noqa: BLE001
-        legs[f"batched_{args.precision}_two_streams"] = dict(error=str(e)[:200])
+    # (an extra leg: its overlapping launches would also blur per-kernel traces)
+    if not args.no_extra:
+        try:
+            tr3 = Tracker(upsample=w.u, precision=args.precision, streams=2)
+            tr3.set_reference(ref_t)
+            chunk3 = tr3.chunk(N) if args.no_tune else tr3.autotune(N, n)
+            out3 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
+            k3 = max(3, args.steps // 3)
+            tot3, lat3 = time_batched(tr3, frames_t, tr3.rois(frames_t), out3, k3, 2, torch)
+            legs[f"batched_{args.precision}_two_streams"] = dict(
+                frames_per_s=round(n * k3 / tot3, 1), chunk=chunk3,
+                p50_ms=round(float(np.median(lat3)) * 1e3, 3),
+                bit_identical=bool(torch.equal(out3, out)))
+            log(f"[bench] two streams: {n * k3 / tot3:,.0f} frames/s (chunk {chunk3})")
+            tr3.close()
+        except Exception as e:  # noqa: BLE001
+            legs[f"batched_{args.precision}_two_streams"] = dict(error=str(e)[:200])
 
     if not args.no_plain:
         for name, graph in (("plain", False), ("graph_stream", True)):
