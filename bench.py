@@ -84,6 +84,30 @@ def _oracle_worker(args):
     return out, dt
 
 
+def gpu_clocks():
+    """The GPU's current clocks as rocm-smi reports them (a read-only query in a
+    child process), or None where the tool is missing or prints no JSON."""
+    import shutil
+    import subprocess
+    exe = shutil.which("rocm-smi") or "/opt/rocm/bin/rocm-smi"
+    try:
+        r = subprocess.run([exe, "--showclocks", "--json"], capture_output=True, text=True, timeout=30)
+        data = json.loads(r.stdout)
+    except Exception:  # noqa: BLE001
+        return None
+    cards = [v for k, v in sorted(data.items()) if k.startswith("card") and isinstance(v, dict)]
+    if not cards:
+        return None
+    import re
+    keep = {}
+    for k, v in cards[0].items():  # e.g. "sclk clock speed:": "(2388Mhz)"
+        m = re.search(r"(\d+)\s*mhz", str(v), re.I)
+        name = k.split()[0].lower() if k else ""
+        if m and "speed" in k.lower() and name in ("sclk", "mclk", "fclk", "socclk"):
+            keep[f"{name}_mhz"] = int(m.group(1))
+    return keep or None
+
+
 def cpu_baseline(frames, ref, u, sample, cores):
     from concurrent.futures import ProcessPoolExecutor
     import multiprocessing as mp
@@ -348,6 +372,8 @@ def main():
     res = decode(out)
     value = n * args.steps / total
     log(f"[bench] batched {args.precision}: {value:,.0f} frames/s, step p50 {np.median(lat)*1e3:.2f} ms")
+    clocks = gpu_clocks()  # right after the timed steps, while the clocks are still up
+    log(f"[bench] clocks {clocks}")
     tr.close()
 
     # ---- the same launches, each bracketed by HIP events on the call's stream:
@@ -531,6 +557,7 @@ def main():
         "cpu_baseline": cpu_json,
         "accuracy": accuracy,
         "hbm_bytes_per_frame": int(N * N * 2),
+        "gpu_clocks": clocks,
     }
     print(json.dumps(line), flush=True)
 
