@@ -205,27 +205,29 @@ __device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy
       for (int k = 0; k < S && k <= kOrder; ++k) P = make_double2(-b * P.y, b * P.x);
     }
   }
-  // sum over the columns of the wave (lanes with the same seg)
+  // sum over the columns of each 16-lane row (lanes with the same seg); the
+  // rows' partials (RP per wave) are added in the final sums
+  constexpr int RW = S <= 16 ? 16 : 64, RP = 64 / RW;
 #pragma unroll
-  for (int off = S; off < 64; off <<= 1)
+  for (int off = S; off < RW; off <<= 1)
 #pragma unroll
     for (int q = 0; q < QM; ++q)
 #pragma unroll
       for (int n = 0; n <= kOrder; ++n) acc[q][n] += __shfl_xor(acc[q][n], off, 64);
-  if (lane < S) {
+  if (lane % RW < S) {
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
-      const int m = lane + S * q;
+      const int m = lane % RW + S * q;
       if (m <= kOrder)
 #pragma unroll
-        for (int n = 0; n <= kOrder; ++n) red[wave][m][n] = acc[q][n];
+        for (int n = 0; n <= kOrder; ++n) red[wave * RP + lane / RW][m][n] = acc[q][n];
     }
   }
-  // ---- Nyquist column kx = NX/2: one row per thread
+  // ---- Nyquist column kx = NX/2: wave 0, one row per lane at a time
   double2 Mn[kOrder + 1];
 #pragma unroll
   for (int n = 0; n <= kOrder; ++n) Mn[n] = make_double2(0.0, 0.0);
-  for (int ky = ky_lo + tid; ky < ky_hi; ky += kNThreads) {
+  for (int ky = ky_lo + (wave == 0 ? lane : ky_hi); ky < ky_hi; ky += 64) {
     const CX xf = Xf[(size_t)ky * H + NC];
     if (2 * ky == NY) {
 #pragma unroll
@@ -240,13 +242,15 @@ __device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy
                  ay[ky]);
     }
   }
+  if (wave == 0) {  // (the other waves hold zeros)
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1)
+    for (int off = 1; off < 64; off <<= 1)
 #pragma unroll
-    for (int n = 0; n <= kOrder; ++n) {
-      Mn[n].x += __shfl_xor(Mn[n].x, off, 64);
-      Mn[n].y += __shfl_xor(Mn[n].y, off, 64);
-    }
+      for (int n = 0; n <= kOrder; ++n) {
+        Mn[n].x += __shfl_xor(Mn[n].x, off, 64);
+        Mn[n].y += __shfl_xor(Mn[n].y, off, 64);
+      }
+  }
   if (lane == 0)
 #pragma unroll
     for (int n = 0; n <= kOrder; ++n) {
@@ -262,10 +266,8 @@ __device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy
       ++n;
     }
     double v = 0.0, mr = 0.0;
-    for (int w = 0; w < kNThreads / 64; ++w) {
-      v += red[w][m][n];
-      mr += nred[w][2 * n];
-    }
+    for (int w = 0; w < kNThreads / 64 * RP; ++w) v += red[w][m][n];
+    for (int w = 0; w < kNThreads / 64; ++w) mr += nred[w][2 * n];
     // Nyquist column: P_m = Re[exp(i pi sx) (i pi)^m], weight 1, real part of M_n
     double sn, cs;
     sincospi(sx, &sn, &cs);
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(kNThreads) k_newton_part(GroupParams g, double
                                                            int nb) {
   __shared__ double2 phy[NY];
   __shared__ double ay[NY];
-  __shared__ double red[kNThreads / 64][kOrder + 1][kOrder + 1];
+  __shared__ double red[kNThreads / 16][kOrder + 1][kOrder + 1];
   __shared__ double nred[kNThreads / 64][2 * (kOrder + 1)];
   __shared__ double coef[kCoef];
   const int f = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
@@ -336,7 +338,7 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
                                                       const double* __restrict__ parts, int nb) {
   __shared__ double2 phy[NY];
   __shared__ double ay[NY];
-  __shared__ double red[kNThreads / 64][kOrder + 1][kOrder + 1];
+  __shared__ double red[kNThreads / 16][kOrder + 1][kOrder + 1];
   __shared__ double nred[kNThreads / 64][2 * (kOrder + 1)];
   __shared__ double coef[kCoef];
   __shared__ double ctl[3];  // next centre y, x; another pass?
