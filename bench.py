@@ -89,6 +89,10 @@ def gpu_clocks():
     child process), or None where the tool is missing or prints no JSON."""
     import shutil
     import subprocess
+    # not under rocprofv3: its preloaded tool would initialise the GPU in the
+    # child before the tool's own program starts
+    if any(k.startswith("ROCPROF") for k in os.environ) or "rocprof" in os.environ.get("LD_PRELOAD", ""):
+        return None
     exe = shutil.which("rocm-smi") or "/opt/rocm/bin/rocm-smi"
     try:
         r = subprocess.run([exe, "--showclocks", "--json"], capture_output=True, text=True, timeout=30)

@@ -87,6 +87,43 @@ __device__ __forceinline__ void add_powers(double2* M, double2 t, double a) {
   }
 }
 
+// Lane moves inside rows of 16 lanes by DPP (VALU operand modifiers, no
+// LDS traffic), on doubles.  CTRL: 0xB1 / 0x4E quad permutations [1,0,3,2] /
+// [2,3,0,1], 0x141 half-row mirror, 0x140 row mirror, 0x120 + d rotation by d.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each aligned group of G adjacent lanes, every lane of the group
+// receiving it; the same additions in the same order as an xor butterfly
+// (at the mirror steps the partner lane holds the value the xor partner
+// would, the quads or half-rows being uniform by then).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_f64<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_f64<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_f64<0x141>(v);
+  if constexpr (G >= 16) v += dpp_f64<0x140>(v);
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Sum over the lanes of a 16-lane row that agree modulo S (S a power of two
+// up to 16), every such lane receiving it: rotations by S, 2S, ..., 8.
+template <int S>
+__device__ __forceinline__ double row_residue_sum(double v) {
+  if constexpr (S <= 1) v += dpp_f64<0x120 + 1>(v);
+  if constexpr (S <= 2) v += dpp_f64<0x120 + 2>(v);
+  if constexpr (S <= 4) v += dpp_f64<0x120 + 4>(v);
+  if constexpr (S <= 8) v += dpp_f64<0x120 + 8>(v);
+  return v;
+}
+
 constexpr int pow2_floor(int x) {
   int p = 1;
   while (2 * p <= x) p *= 2;
@@ -174,12 +211,10 @@ __device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy
     }
   }
 #pragma unroll
-  for (int off = 1; off < S; off <<= 1)
-#pragma unroll
-    for (int n = 0; n <= kOrder; ++n) {
-      M[n].x += __shfl_xor(M[n].x, off, 64);
-      M[n].y += __shfl_xor(M[n].y, off, 64);
-    }
+  for (int n = 0; n <= kOrder; ++n) {
+    M[n].x = group_sum<S>(M[n].x);
+    M[n].y = group_sum<S>(M[n].y);
+  }
   // ---- this lane's share of the coefficients: m = seg + S q
   double acc[QM][kOrder + 1];
 #pragma unroll
@@ -208,12 +243,19 @@ __device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy
   // sum over the columns of each 16-lane row (lanes with the same seg); the
   // rows' partials (RP per wave) are added in the final sums
   constexpr int RW = S <= 16 ? 16 : 64, RP = 64 / RW;
-#pragma unroll
-  for (int off = S; off < RW; off <<= 1)
+  if constexpr (RW == 16) {
 #pragma unroll
     for (int q = 0; q < QM; ++q)
 #pragma unroll
-      for (int n = 0; n <= kOrder; ++n) acc[q][n] += __shfl_xor(acc[q][n], off, 64);
+      for (int n = 0; n <= kOrder; ++n) acc[q][n] = row_residue_sum<S>(acc[q][n]);
+  } else {
+#pragma unroll
+    for (int off = S; off < RW; off <<= 1)
+#pragma unroll
+      for (int q = 0; q < QM; ++q)
+#pragma unroll
+        for (int n = 0; n <= kOrder; ++n) acc[q][n] += __shfl_xor(acc[q][n], off, 64);
+  }
   if (lane % RW < S) {
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
