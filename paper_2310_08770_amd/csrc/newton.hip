@@ -90,6 +90,8 @@ __device__ __forceinline__ void add_powers(double2* M, double2 t, double a) {
 // Lane moves inside rows of 16 lanes by DPP (VALU operand modifiers, no
 // LDS traffic), on doubles.  CTRL: 0xB1 / 0x4E quad permutations [1,0,3,2] /
 // [2,3,0,1], 0x141 half-row mirror, 0x140 row mirror, 0x120 + d rotation by d.
+// Every lane of the wave must be active (a lane reading an inactive one
+// would receive 0); the callers below run in wave-uniform control flow.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
