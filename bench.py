@@ -327,8 +327,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every box here has one GPU "
-              "and the multi-GPU path is not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the path runs one GPU's share "
+              "of the frames, and sharding frames across GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     from synth import frames as S
