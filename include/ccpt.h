@@ -76,7 +76,11 @@ extern "C" {
 /* ---- per-frame status bits (ccpt_result.status) ---------------------- */
 #define CCPT_ST_NONFINITE 1u       /* NaN/Inf pixel: d, d_grid, peak are NaN */
 #define CCPT_ST_FLAT 2u            /* constant frame: everything is zero */
-#define CCPT_ST_NEAR_TIE 4u        /* reserved: top two integer lags within 1e-5 */
+#define CCPT_ST_NEAR_TIE 4u        /* the two largest integer-lag correlation
+                                      values differ by at most 1e-5 of the
+                                      largest's magnitude (p is then decided
+                                      by rounding; it is still the lowest-index
+                                      maximum of the computed correlation) */
 #define CCPT_ST_NEWTON_FALLBACK 8u /* Hessian not negative definite, or a step
                                       longer than 1/u (FP64 precision) or
                                       than half the window (FP32, BF16X2,
@@ -262,13 +266,16 @@ int ccpt_track_update(ccpt_ctx* ctx, const ccpt_roi* roi, double a0, ccpt_result
 
 /* Drift correction of Sec. III.B (Eq. 10-12) on a stream of displacements
    (host arrays r and out of n (y, x) pairs; they may be the same array):
-   Eq. 10  R_n = a0 r_n + (1 - a0) R_{n-1};
+   Eq. 10  R_0 = a0 r_0, R_n = a0 r_n + (1 - a0) R_{n-1};
    or, with rate_limit > 0 (alpha/u; the paper suggests alpha = 0.5),
-   Eq. 11-12  dR_n = a0 r_n - a0 R_{n-1}, a step longer than rate_limit cut
-   to that length along dR_n, R_n = R_{n-1} + dR_n;
-   out_n = r_n - R_n.  state[2] holds R_{n-1} (y, x) and is updated, so a
-   stream can be processed in pieces; zeros to start (R_0 = a0 r_0).  Pure
-   host computation (no context).  CCPT_E_INVALID for bad arguments. */
+   Eq. 11-12 from n = 1 on: dR_n = a0 r_n - a0 R_{n-1}, a step longer than
+   rate_limit cut to that length along dR_n, R_n = R_{n-1} + dR_n (the
+   first offset is Eq. 10's R_0 in both forms);
+   out_n = r_n - R_n.  state[3] = {R_{n-1} y, R_{n-1} x, number of samples
+   already filtered} is read and updated, so a stream can be processed in
+   pieces; three zeros start a new stream.  Pure host computation (no
+   context).  CCPT_E_INVALID for bad arguments (null state, a0 outside
+   [0, 1], negative rate_limit or sample count). */
 int ccpt_drift_filter(const double* r, int n, double a0, double rate_limit, double* state,
                       double* out);
 

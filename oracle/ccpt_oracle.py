@@ -100,17 +100,6 @@ def weights(frame, ref, mode=MODE_CCU, eps=200.0):
     raise ValueError("unknown mode")
 
 
-def reference_weight(ref, mode=MODE_CCU, eps=200.0):
-    """B alone (see weights)."""
-    E = np.asarray(ref, dtype=np.float64)
-    if mode == MODE_CCU:
-        return E
-    Ep = E + eps
-    if np.any(Ep <= 0):
-        raise ValueError("CC-SN reference needs E + eps > 0 everywhere")
-    return -1.0 / Ep
-
-
 # --------------------------------------------------------------------------
 # O2, O3  cross-power spectrum and circular correlation (Eq. 4 / Eq. 7)
 # --------------------------------------------------------------------------
@@ -471,16 +460,20 @@ def realtime_track(frames, u, a0, mode=MODE_CCU, eps=200.0):
 # --------------------------------------------------------------------------
 def drift_filter(r, a0, rate_limit=0.0):
     """Offsets R_n and corrected displacements r_n - R_n for a sequence of
-    displacements r ([n, 2]).  Eq. (10): R_n = a0 r_n + b1 R_{n-1} with
-    R_{-1} = 0 (so R_0 = a0 r_0).  With rate_limit = alpha/u > 0, Eq. (11)-(12):
+    displacements r ([n, 2]).  Eq. (10): R_0 = a0 r_0 and
+    R_n = a0 r_n + b1 R_{n-1} for n >= 1.  With rate_limit = alpha/u > 0,
+    Eq. (11)-(12) replace the update from n = 1 on:
     dR_n = a0 r_n + (b1 - 1) R_{n-1}, and a step longer than rate_limit is
-    cut to that length along dR_n."""
+    cut to that length along dR_n.  The first offset is Eq. (10)'s R_0 in
+    both forms (the rate limit acts on steps between offsets)."""
     r = np.asarray(r, dtype=np.float64)
     b1 = 1.0 - a0
     R = np.zeros(2)
     offsets = np.zeros_like(r)
     for n, rn in enumerate(r):
-        if rate_limit > 0.0:
+        if n == 0:
+            R = a0 * rn
+        elif rate_limit > 0.0:
             dR = a0 * rn + (b1 - 1.0) * R
             L = math.hypot(dR[0], dR[1])
             R = R + (rate_limit * dR / L if L > rate_limit else dR)

@@ -350,7 +350,7 @@ def drift_filter(r, a0, rate_limit=0.0, state=None):
     returns (r - R, state); pass the returned state to continue a stream."""
     r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1, 2)
     out = np.empty_like(r)
-    st = np.zeros(2) if state is None else np.array(state, dtype=np.float64)
+    st = np.zeros(3) if state is None else np.array(state, dtype=np.float64).reshape(3)
     rc = lib().ccpt_drift_filter(r.ctypes.data, r.shape[0], float(a0), float(rate_limit),
                                  st.ctypes.data, out.ctypes.data)
     if rc != OK:

@@ -1173,13 +1173,18 @@ int ccpt_track_update(ccpt_ctx* ctx, const ccpt_roi* roi, double a0, ccpt_result
 int ccpt_drift_filter(const double* r, int n, double a0, double rate_limit, double* state,
                       double* out) {
   if (n < 0 || (n > 0 && (!r || !out)) || !state || !(a0 >= 0.0 && a0 <= 1.0) ||
-      !(rate_limit >= 0.0))
+      !(rate_limit >= 0.0) || !(state[2] >= 0.0))
     return CCPT_E_INVALID;
   const double b1 = 1.0 - a0;
   double Ry = state[0], Rx = state[1];
+  bool first = state[2] == 0.0;
   for (int i = 0; i < n; ++i) {
     const double ry = r[2 * i], rx = r[2 * i + 1];
-    if (rate_limit > 0.0) {
+    if (first) {  // Eq. 10 with R_{-1} = 0: R_0 = a0 r_0, never rate-limited
+      Ry = a0 * ry;
+      Rx = a0 * rx;
+      first = false;
+    } else if (rate_limit > 0.0) {  // Eq. 11-12
       double dy = a0 * ry + (b1 - 1.0) * Ry, dx = a0 * rx + (b1 - 1.0) * Rx;
       const double L = std::hypot(dy, dx);
       if (L > rate_limit) {
@@ -1188,7 +1193,7 @@ int ccpt_drift_filter(const double* r, int n, double a0, double rate_limit, doub
       }
       Ry += dy;
       Rx += dx;
-    } else {
+    } else {  // Eq. 10
       Ry = a0 * ry + b1 * Ry;
       Rx = a0 * rx + b1 * Rx;
     }
@@ -1197,6 +1202,7 @@ int ccpt_drift_filter(const double* r, int n, double a0, double rate_limit, doub
   }
   state[0] = Ry;
   state[1] = Rx;
+  state[2] += (double)n;
   return CCPT_OK;
 }
 

@@ -25,10 +25,12 @@ struct FrameDesc {
 // to it by the Newton kernel, the last of a chunk, for every frame: no reset
 // launch is needed per chunk.
 struct FrameState {
-  unsigned long long peak_key;  // integer-lag maximum: value key << 32 | ~flat index
-  unsigned long long grid_key;  // upsampled-grid maximum, same encoding
-  unsigned amin, amax;          // order-preserving keys of min/max of A
-  unsigned flags;               // CCPT_ST_NONFINITE
+  unsigned long long peak_key;    // integer-lag maximum: value key << 32 | ~flat index
+  unsigned long long grid_key;    // upsampled-grid maximum, same encoding
+  unsigned long long second_key;  // runner-up of the integer-lag correlation, same
+                                  // encoding (0 until set; FP32 and split paths)
+  unsigned amin, amax;            // order-preserving keys of min/max of A
+  unsigned flags;                 // CCPT_ST_NONFINITE; CCPT_ST_NEAR_TIE (FP64 mode)
   unsigned pad;
 };
 
@@ -36,10 +38,15 @@ struct FrameState {
 // row-major index (ties to the lower index); reduced per frame before the
 // upsampled DFT, since an FP64 value and an index do not fit one 64-bit key.
 struct PeakCand {
-  double v;
+  double v;     // best value of the block
+  double v2;    // its runner-up value (a value equal to v at another index counts)
   unsigned idx;
   unsigned pad;
 };
+
+// Relative gap under which the two largest integer-lag correlation values
+// count as a near tie (CCPT_ST_NEAR_TIE): v1 - v2 <= kNearTieRel |v1|.
+constexpr double kNearTieRel = 1e-5;
 
 // Scalar parameters of a launch group (passed by value to every kernel).
 struct GroupParams {
@@ -127,6 +134,19 @@ __host__ __device__ inline unsigned f2key(float v) {
 
 __host__ __device__ inline unsigned long long peak_key(float v, unsigned flat) {
   return ((unsigned long long)f2key(v) << 32) | (unsigned long long)(0xFFFFFFFFu - flat);
+}
+
+// The float value of a peak key (inverse of f2key on its high half).
+__host__ __device__ inline float key_value(unsigned long long k) {
+  const unsigned h = (unsigned)(k >> 32);
+  const unsigned b = (h & 0x80000000u) ? (h & 0x7FFFFFFFu) : ~h;
+  float v;
+  __builtin_memcpy(&v, &b, 4);
+  return v;
+}
+
+__host__ __device__ inline bool near_tie(double v1, double v2) {
+  return v1 - v2 <= kNearTieRel * (v1 < 0.0 ? -v1 : v1);
 }
 
 __host__ __device__ inline unsigned key_index(unsigned long long k) {

@@ -399,6 +399,7 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
       FrameState z;
       z.peak_key = 0;
       z.grid_key = 0;
+      z.second_key = 0;
       z.amin = 0xFFFFFFFFu;
       z.amax = 0;
       z.flags = 0;
@@ -425,12 +426,20 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
 
   // the iterate and the decisions live in thread 0; the centre is broadcast
   double sy = dgy, sx = dgx;
-  unsigned status = 0;
+  // near tie of the integer peak: flagged by the FP64 reduction, or from
+  // the two largest FP32 keys
+  unsigned status = st.flags & CCPT_ST_NEAR_TIE;
+  if (st.second_key && near_tie((double)key_value(st.peak_key), (double)key_value(st.second_key)))
+    status |= CCPT_ST_NEAR_TIE;
   bool done = false;
+  bool checked = false;  // window test applied
   int it_left = g.newton_iters;
   double cy = dgy, cx = dgx;
   Deriv fin{0, 0, 0, 0, 0, 0};
-  for (int pass = 0; pass < kMaxPasses; ++pass) {
+  // iterations run in the first kMaxPasses model passes; one more pass may
+  // re-centre the model on the final point (a window exit, or an iterate
+  // still moving when the passes ran out) for C and the Hessian there
+  for (int pass = 0; pass <= kMaxPasses; ++pass) {
     if (pass == 0 && parts) {
       // the first model from the blocks of k_newton_part, added in block order
       if (tid < kCoef) {
@@ -467,14 +476,18 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
         --it_left;
         if (fmax(fabs(sy - cy), fabs(sx - cx)) > kModelRadius) break;  // rebuild around sy, sx
       }
-      if (it_left == 0) done = true;
-      if (done && fmax(fabs(sy - py), fabs(sx - px)) > g.half_window) {
-        status |= CCPT_ST_WINDOW_EXIT;
-        sy = dgy;
-        sx = dgx;
+      // out of steps or out of iterating passes: the iterate is final, and
+      // the window test applies to it whether or not it converged
+      if (it_left == 0 || pass >= kMaxPasses - 1) done = true;
+      if (done && !checked) {
+        checked = true;
+        if (fmax(fabs(sy - py), fabs(sx - px)) > g.half_window) {
+          status |= CCPT_ST_WINDOW_EXIT;
+          sy = dgy;
+          sx = dgx;
+        }
       }
-      bool again = !done || fmax(fabs(sy - cy), fabs(sx - cx)) > kModelRadius;
-      if (pass == kMaxPasses - 1) again = false;  // out of passes: use the last model
+      const bool again = !done || fmax(fabs(sy - cy), fabs(sx - cx)) > kModelRadius;
       if (!again) fin = model_eval(coef, sy - cy, sx - cx);
       ctl[0] = sy;
       ctl[1] = sx;

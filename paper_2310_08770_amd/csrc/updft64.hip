@@ -78,8 +78,22 @@ __global__ void __launch_bounds__(updft64_threads<N>())
 
   if (tid == 0) {
     const PeakCand* cd = g.cand + (size_t)f * nb;
-    for (int j = 0; j < nb; ++j) take(cd[j].v, cd[j].idx);
+    // runner-up: the largest block runner-up or a block maximum that lost
+    double sv = -__builtin_inf();
+    for (int j = 0; j < nb; ++j) {
+      const double v = cd[j].v;
+      const unsigned i = cd[j].idx;
+      if (v > bv || (v == bv && i < bi)) {
+        sv = bv > sv ? bv : sv;
+        bv = v;
+        bi = i;
+      } else if (v > sv) {
+        sv = v;
+      }
+      sv = cd[j].v2 > sv ? cd[j].v2 : sv;
+    }
     st->peak_key = peak_key((float)bv, bi);
+    if (near_tie(bv, sv)) st->flags |= CCPT_ST_NEAR_TIE;
     const unsigned q = bi < (unsigned)(N * N) ? bi : 0u;
     int py = (int)(q / N), px = (int)(q % N);
     if (2 * py >= N) py -= N;

@@ -118,6 +118,7 @@ __global__ void k_init_state(FrameState* st, int count) {
     FrameState s;
     s.peak_key = 0;
     s.grid_key = 0;
+    s.second_key = 0;
     s.amin = 0xFFFFFFFFu;
     s.amax = 0;
     s.flags = 0;
@@ -383,8 +384,8 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
   __shared__ C raw[RPB * H];
   __shared__ C bufA[RPB * LS];
   __shared__ C bufB[RPB * LS];
-  __shared__ unsigned long long red[kThreads / 64];
-  __shared__ double redv[kThreads / 64];
+  __shared__ unsigned long long red[kThreads / 64], red2[kThreads / 64];
+  __shared__ double redv[kThreads / 64], redv2[kThreads / 64];
   const int tid = threadIdx.x;
   const int f = blockIdx.y;
   const int y0 = blockIdx.x * RPB;
@@ -414,32 +415,59 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
   __syncthreads();
   C* z = fft_lds<L, +1, NX>(bufA, bufB, RPB, LS, tw);
   if constexpr (ARGMAX && !FP64) {
-    unsigned long long best = 0;
+    // the two largest keys of the block (keys are unique: they hold the index)
+    unsigned long long best = 0, second = 0;
+    auto push = [&](unsigned long long k) {
+      if (k > best) {
+        second = best;
+        best = k;
+      } else if (k > second) {
+        second = k;
+      }
+    };
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;
       const C v = z[r * LS + lds_idx(n)];
       const unsigned flat = flat_of(y0 + r, 2 * n);
-      unsigned long long k0 = peak_key(v.x, flat);
-      unsigned long long k1 = peak_key(v.y, flat + xstep);
-      best = k0 > best ? k0 : best;
-      best = k1 > best ? k1 : best;
+      push(peak_key(v.x, flat));
+      push(peak_key(v.y, flat + xstep));
     }
-    best = wave_max_u64(best);
-    if ((tid & 63) == 0) red[tid >> 6] = best;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long b1 = __shfl_xor(best, o, 64), b2 = __shfl_xor(second, o, 64);
+      const unsigned long long lo = b1 < best ? b1 : best;
+      second = second > b2 ? second : b2;
+      second = second > lo ? second : lo;
+      best = b1 > best ? b1 : best;
+    }
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = best;
+      red2[tid >> 6] = second;
+    }
     __syncthreads();
     if (tid == 0) {
-      for (int w = 1; w < kThreads / 64; ++w) best = red[w] > best ? red[w] : best;
-      atomicMax(&st[f].peak_key, best);
+      for (int w = 1; w < kThreads / 64; ++w) {
+        push(red[w]);
+        push(red2[w]);
+      }
+      // the frame's runner-up is some block's second or the smaller of two
+      // block maxima meeting in the atomic: submit both
+      const unsigned long long old = atomicMax(&st[f].peak_key, best);
+      const unsigned long long lose = old < best ? old : best;
+      atomicMax(&st[f].second_key, second > lose ? second : lose);
     }
   } else if constexpr (ARGMAX) {
     // (value, index) pairs: larger value wins, equal values go to the lower
-    // index; NaN never wins
-    double bv = -__builtin_inf();
+    // index; NaN never wins.  sv: the runner-up value.
+    double bv = -__builtin_inf(), sv = -__builtin_inf();
     unsigned bi = 0xFFFFFFFFu;
     auto take = [&](double v, unsigned i) {
       if (v > bv || (v == bv && i < bi)) {
+        sv = bv;
         bv = v;
         bi = i;
+      } else if (v > sv) {
+        sv = v;
       }
     };
     for (int i = tid; i < RPB * L; i += kThreads) {
@@ -450,16 +478,26 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
       take(v.y, flat + xstep);
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) take(__shfl_xor(bv, o, 64), (unsigned)__shfl_xor((int)bi, o, 64));
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64), os = __shfl_xor(sv, o, 64);
+      const unsigned oi = (unsigned)__shfl_xor((int)bi, o, 64);
+      take(ov, oi);
+      sv = os > sv ? os : sv;
+    }
     if ((tid & 63) == 0) {
       redv[tid >> 6] = bv;
+      redv2[tid >> 6] = sv;
       red[tid >> 6] = bi;
     }
     __syncthreads();
     if (tid == 0) {
-      for (int w = 1; w < kThreads / 64; ++w) take(redv[w], (unsigned)red[w]);
+      for (int w = 1; w < kThreads / 64; ++w) {
+        take(redv[w], (unsigned)red[w]);
+        sv = redv2[w] > sv ? redv2[w] : sv;
+      }
       PeakCand pc;
       pc.v = bv;
+      pc.v2 = sv;
       pc.idx = bi;
       pc.pad = 0;
       cand[(size_t)f * gridDim.x + blockIdx.x] = pc;

@@ -74,7 +74,9 @@ def test_drift_filter_rejects_bad_arguments():
     lib = ctypes.CDLL(LIB)
     lib.ccpt_drift_filter.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
-    st = (ctypes.c_double * 2)()
+    st = (ctypes.c_double * 3)()
     assert lib.ccpt_drift_filter(None, 3, 0.1, 0.0, st, None) == -1
     assert lib.ccpt_drift_filter(None, 0, 1.5, 0.0, st, None) == -1
     assert lib.ccpt_drift_filter(None, 0, 0.1, -1.0, st, None) == -1
+    st[2] = -1.0
+    assert lib.ccpt_drift_filter(None, 0, 0.1, 0.0, st, None) == -1

@@ -369,6 +369,129 @@ def test_window_exit_on_two_equal_spots():
     assert np.max(np.abs(res["d"] - np.array(res["p"]))) <= O.HALF_WINDOW
 
 
+# ---------------------------------------------------------------- near ties of the integer peak
+def _delta_ref(shape):
+    """A reference with one unit pixel at the origin: the CC-U correlation of
+    any frame with it is the frame itself, sum_r I(r+s) delta(r) = I(s)."""
+    E = np.zeros(shape)
+    E[0, 0] = 1.0
+    return E
+
+
+def _planted(v1, v2, pos1=(3, 5), pos2=(9, 2), n=16, floor=None):
+    """A frame whose correlation with the delta reference has its maximum v1
+    at pos1, its runner-up v2 at pos2 and everything else far below."""
+    base = (v1 - 10.0 * abs(v1) - 1.0) if floor is None else floor
+    f = np.full((n, n), base) + np.arange(n * n).reshape(n, n) * 1e-3
+    f[pos1] = v1
+    f[pos2] = v2
+    return f
+
+
+def test_near_tie_correlation_of_the_delta_reference_is_the_frame():
+    f = _planted(1000.0, 999.0)
+    cc = O.correlation(O.cross_power(*O.weights(f, _delta_ref(f.shape))))
+    assert np.max(np.abs(cc - f)) <= 1e-9
+
+
+@pytest.mark.parametrize("gap_rel,tie", [(0.0, True), (0.5e-5, True), (0.999e-5, True),
+                                         (1.001e-5, False), (2e-5, False), (1e-3, False)])
+def test_near_tie_flag_follows_the_relative_gap(gap_rel, tie):
+    """The flag is set exactly when the two largest correlation values lie
+    within 1e-5 of the largest's magnitude; the third value is far below."""
+    v1 = 1000.0
+    f = _planted(v1, v1 * (1.0 - gap_rel))
+    r = O.track(f, _delta_ref(f.shape), 10)
+    assert bool(r["status"] & O.NEAR_TIE) == tie
+    assert tuple(r["p"]) == (3, 5)  # the maximum, or the lower index of an exact tie
+
+
+def test_near_tie_threshold_scales_with_the_maximum_not_the_runner_up():
+    """A gap between 1e-5 |v2| and 1e-5 |v1| is a near tie (the threshold is
+    relative to the maximum)."""
+    v1 = 1000.0
+    gap = 1e-5 * v1 - 5e-8
+    assert gap > 1e-5 * (v1 - gap)
+    f = _planted(v1, v1 - gap)
+    assert O.track(f, _delta_ref(f.shape), 10)["status"] & O.NEAR_TIE
+
+
+def test_near_tie_of_a_negative_maximum_uses_its_magnitude():
+    """Correlations can be negative everywhere (CC-SN's weight B < 0): the
+    threshold is 1e-5 |v1|, not 1e-5 v1."""
+    v1 = -1000.0
+    f = _planted(v1, v1 - 0.005, floor=-5000.0)
+    r = O.track(f, _delta_ref(f.shape), 10)
+    assert r["status"] & O.NEAR_TIE and tuple(r["p"]) == (3, 5)
+    f = _planted(v1, v1 - 0.02, floor=-5000.0)
+    assert not O.track(f, _delta_ref(f.shape), 10)["status"] & O.NEAR_TIE
+
+
+def test_exact_tie_goes_to_the_lowest_row_major_index():
+    f = _planted(1000.0, 1000.0, pos1=(9, 2), pos2=(3, 5))
+    r = O.track(f, _delta_ref(f.shape), 10)
+    assert tuple(r["p"]) == (3, 5) and r["status"] & O.NEAR_TIE
+    f = _planted(1000.0, 1000.0, pos1=(4, 7), pos2=(4, 6))
+    assert tuple(O.track(f, _delta_ref(f.shape), 10)["p"]) == (4, 6)
+
+
+# ---------------------------------------------------------------- Newton safeguards
+def _trig_spectrum(n, fy, fx):
+    """X = fft2 of samples of C(s) = fy(a s_y) + fx(a s_x), a = 2 pi / n: a
+    trigonometric polynomial of degree 1, so the band-limited correlation
+    of X is C itself (the interpolant of its samples)."""
+    a = 2.0 * np.pi / n
+    y = np.arange(n)[:, None]
+    x = np.arange(n)[None, :]
+    return np.fft.fft2(fy(a * y) + fx(a * x) + 0.0 * x * y)
+
+
+def test_trig_spectrum_reproduces_its_function():
+    n = 16
+    X = _trig_spectrum(n, np.cos, lambda t: -np.cos(t))
+    a = 2.0 * np.pi / n
+    for s in [(0.3, -0.2), (1.7, 0.45)]:
+        assert abs(O.bandlimited(X, s) - (np.cos(a * s[0]) - np.cos(a * s[1]))) <= 1e-12
+
+
+@pytest.mark.parametrize("fy,fx", [(np.cos, lambda t: -np.cos(t)),           # saddle, H_yy < 0
+                                   (lambda t: -np.cos(t), np.cos),           # saddle, H_yy > 0
+                                   (lambda t: -np.cos(t), lambda t: -np.cos(t))])  # minimum
+def test_newton_falls_back_where_the_hessian_is_not_negative_definite(fy, fx):
+    """At a saddle or a minimum of C the seed is returned with
+    NEWTON_FALLBACK (both the sign of H_yy and the determinant matter)."""
+    X = _trig_spectrum(16, fy, fx)
+    seed = np.array([0.0, 0.0])
+    d, c, H, st = O.newton(X, seed, (0, 0), 20)
+    assert st == O.NEWTON_FALLBACK
+    assert d[0] == seed[0] and d[1] == seed[1]
+
+
+def test_newton_falls_back_on_a_step_longer_than_a_grid_step():
+    """From a seed 0.3 px off the maximum of cos + cos the first Newton step
+    is about 0.3 px > 1/u: the seed comes back, unchanged, with the flag; a
+    seed within a grid step converges to the maximum."""
+    X = _trig_spectrum(16, np.cos, np.cos)
+    seed = np.array([0.3, 0.0])
+    d, _, _, st = O.newton(X, seed, (0, 0), 20)
+    assert st == O.NEWTON_FALLBACK and d[0] == 0.3 and d[1] == 0.0
+    d, _, _, st = O.newton(X, np.array([0.02, -0.01]), (0, 0), 20)
+    assert st == 0 and np.max(np.abs(d)) <= 1e-12
+
+
+def test_newton_flags_a_result_outside_the_half_window():
+    """C = cos(a (s_y - 0.9)) + cos(a s_x) peaks 0.9 px from p = (0, 0): Newton
+    from (0.74, 0) converges there (u = 2 allows 0.16-px steps), then the
+    0.75-px window test returns the seed with WINDOW_EXIT; with p = (1, 0)
+    the same maximum is inside the window and is returned."""
+    X = _trig_spectrum(16, lambda t: np.cos(t - 0.9 * 2 * np.pi / 16), np.cos)
+    seed = np.array([0.74, 0.0])
+    d, _, _, st = O.newton(X, seed, (0, 0), 2)
+    assert st == O.WINDOW_EXIT and d[0] == 0.74 and d[1] == 0.0
+    d, _, _, st = O.newton(X, seed, (1, 0), 2)
+    assert st == 0 and abs(d[0] - 0.9) <= 1e-12 and abs(d[1]) <= 1e-12
+
+
 # ---------------------------------------------------------------- offline reference (Eq. 8)
 def test_p13_integer_rolls_average_back_to_the_image():
     """Frames that are exact circular shifts of one image, averaged after
@@ -465,21 +588,36 @@ def test_p15_rate_limit_bounds_every_step_and_is_inactive_for_small_steps():
     r = np.cumsum(rng.normal(0, 0.3, size=(500, 2)), axis=0)
     a0, lim = 0.2, 0.5 / 100
     R, _ = O.drift_filter(r, a0, lim)
-    steps = np.hypot(*np.diff(np.vstack([[0, 0], R]), axis=0).T)
+    steps = np.hypot(*np.diff(R, axis=0).T)
     assert np.all(steps <= lim * (1 + 1e-12))
+    assert np.max(steps) >= lim * (1 - 1e-12)  # the limit is reached on this walk
     small = 1e-4 * np.sin(np.arange(200))[:, None] * np.array([[1.0, 0.5]])
     R1, _ = O.drift_filter(small, a0, lim)
     R0, _ = O.drift_filter(small, a0)
     assert np.max(np.abs(R1 - R0)) <= 1e-18
 
 
+@pytest.mark.parametrize("rate_limit", [0.0, 0.005])
+def test_p15_first_offset_is_eq10_r0(rate_limit):
+    """Eq. (10) starts the low-pass at R_0 = a0 r_0 (the rate limit of
+    Eq. 11-12 acts on the steps R_n - R_{n-1} from n = 1 on), whatever the
+    size of the first displacement."""
+    a0 = 0.25
+    r = np.array([[2.0, -1.0], [2.0, -1.0], [0.0, 0.0]])
+    R, out = O.drift_filter(r, a0, rate_limit)
+    assert R[0, 0] == 0.5 and R[0, 1] == -0.25
+    assert out[0, 0] == 1.5 and out[0, 1] == -0.75
+
+
 def test_p15_rate_limited_step_response_is_a_ramp():
-    """A jump of 1 px with limit 0.005 px per frame: the offset walks towards
-    it in steps of exactly the limit while the filtered step exceeds it."""
+    """A jump of 1 px with limit 0.005 px per frame: R_0 = a0 (Eq. 10), then
+    the offset walks towards 1 in steps of exactly the limit while the
+    filtered step a0 (1 - R) exceeds it."""
     a0, lim = 0.5, 0.005
     r = np.tile([[1.0, 0.0]], (50, 1))
     R, _ = O.drift_filter(r, a0, lim)
-    assert np.allclose(R[:, 0], lim * np.arange(1, 51), atol=1e-15)
+    assert R[0, 0] == 0.5
+    assert np.allclose(R[:, 0], 0.5 + lim * np.arange(50), atol=1e-15)
     assert np.all(R[:, 1] == 0.0)
 
 
