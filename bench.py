@@ -78,10 +78,24 @@ def _oracle_worker(args):
     with threadpool_limits(1):
         t0 = time.perf_counter()
         for f in frames:
+            t1 = time.perf_counter()
             r = O.track(f, ref, u)
-            out.append((r["d"], r["p"], r["status"]))
+            out.append((r["d"], r["p"], r["status"], r["d_grid"], r["grid_gap"], r["grid_ac"],
+                        time.perf_counter() - t1))
         dt = time.perf_counter() - t0
     return out, dt
+
+
+def cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (else the platform's)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def gpu_clocks():
@@ -124,11 +138,17 @@ def cpu_baseline(frames, ref, u, sample, cores):
     with ProcessPoolExecutor(len(jobs), mp_context=mp.get_context("fork")) as ex:
         res = list(ex.map(_oracle_worker, jobs))
     wall = time.perf_counter() - t0
-    d = np.concatenate([np.array([r[0] for r in part]) for part, _ in res])
-    p = np.concatenate([np.array([r[1] for r in part]) for part, _ in res])
-    st = np.concatenate([np.array([r[2] for r in part]) for part, _ in res])
+    col = lambda j: np.concatenate([np.array([r[j] for r in part]) for part, _ in res])  # noqa: E731
     cpu_s = sum(dt for _, dt in res)
-    return dict(d=d, p=p, status=st, wall=wall, cpu_s=cpu_s, cores=len(jobs))
+    return dict(d=col(0), p=col(1), status=col(2), d_grid=col(3), grid_gap=col(4), grid_ac=col(5),
+                frame_s=col(6), wall=wall, cpu_s=cpu_s, cores=len(jobs))
+
+
+def cpu_one_core(frames, ref, u, sample):
+    """The oracle in this process on one core: per-frame times of `sample` frames."""
+    ref64 = np.asarray(ref, np.float32).astype(np.float64)
+    out, dt = _oracle_worker((frames[:sample], ref64, u))
+    return np.array([r[6] for r in out]), dt
 
 
 # ---------------------------------------------------------------- GPU legs
@@ -341,12 +361,15 @@ def main():
     log(f"[bench] generated {n} frames {N}x{N} in {time.perf_counter() - t0:.1f}s")
 
     cpu = None
+    one = None
     if not args.no_cpu:
         cores = max(1, min(16, os.cpu_count() or 1))
         sample = min(args.cpu_sample, n)
         cpu = cpu_baseline(frames, ref, w.u, sample, cores)
         log(f"[bench] oracle: {sample} frames in {cpu['wall']:.1f}s wall on {cpu['cores']} cores "
             f"({cpu['cpu_s']:.1f}s CPU)")
+        one = cpu_one_core(frames, ref, w.u, min(64, n))
+        log(f"[bench] oracle on one core: {len(one[0])} frames in {one[1]:.1f}s")
 
     import torch
 
@@ -515,12 +538,31 @@ def main():
         ok = (cpu["status"] & (4 | 8 | 16)) == 0
         err = np.max(np.abs(res["d"][:k] - cpu["d"]), axis=1)
         peaks_equal = np.all(res["p"][:k] == cpu["p"], axis=1)
+
+        def grid_stats(r, prec):
+            # the grid estimate (the paper's sub-pixel result) against the
+            # oracle's: same grid point on every frame, and on the frames whose
+            # oracle top-two grid values differ by more than the precision's
+            # rounding (2^-20 of the grid maximum's AC part in FP32, 2^-17 with
+            # bf16 hi + lo operands; the rest are decided by rounding)
+            same = np.max(np.abs(r["d_grid"][:k].astype(np.float64) - cpu["d_grid"]), axis=1) < 0.5 / w.u
+            tol = 2.0 ** -20 if prec == "fp32" else 2.0 ** -17
+            firm = cpu["grid_gap"] > tol * cpu["grid_ac"]
+            gerr = np.max(np.abs(r["d_grid"][:k].astype(np.float64) - cpu["d_grid"]), axis=1)
+            return dict(grid_index_agreement=float(same.mean()),
+                        grid_index_agreement_beyond_rounding=float(same[firm].mean()) if firm.any() else None,
+                        frames_beyond_rounding=int(firm.sum()),
+                        max_grid_err_px=float(gerr.max()), p99_grid_err_px=float(np.percentile(gerr, 99)))
+
         accuracy = dict(frames_checked=int(k), max_err_px=float(err[ok].max()),
+                        p99_err_px=float(np.percentile(err[ok], 99)),
                         mean_err_px=float(err[ok].mean()), integer_peak_agreement=float(peaks_equal.mean()),
-                        oracle_fallbacks=int((~ok).sum()))
+                        oracle_fallbacks=int((~ok).sum()), oracle_near_ties=int(((cpu["status"] & 4) != 0).sum()),
+                        **grid_stats(res, args.precision))
         if r2 is not None:
             e2 = np.max(np.abs(r2["d"][:k] - cpu["d"]), axis=1)
-            accuracy[f"max_err_px_{other}"] = float(e2[ok].max())
+            accuracy[other] = dict(max_err_px=float(e2[ok].max()), p99_err_px=float(np.percentile(e2[ok], 99)),
+                                   **grid_stats(r2, other))
         cpu_json = {
             "value": round(k / cpu["wall"], 2),
             "unit": "frames/s",
@@ -528,8 +570,13 @@ def main():
             "kind": "oracle",
             "sample": f"first {k} of the {n} frames (256x256, u=100), FP64 numpy oracle, "
                       f"one single-threaded process per core; {cpu['cpu_s']:.1f} s of CPU work",
-            "p50_ms_per_frame_per_core": round(1e3 * cpu["cpu_s"] / k, 3),
-            "cpu": platform.processor() or platform.machine(),
+            "mean_ms_per_frame_per_core": round(1e3 * cpu["cpu_s"] / k, 3),
+            "cpu": cpu_model(),
+            "one_core": None if one is None else {
+                "frames_per_s": round(len(one[0]) / one[1], 2),
+                "p50_ms_per_frame": round(float(np.median(one[0])) * 1e3, 3),
+                "p99_ms_per_frame": round(float(np.percentile(one[0], 99)) * 1e3, 3),
+                "sample": f"first {len(one[0])} frames, one single-threaded process"},
         }
 
     line = {

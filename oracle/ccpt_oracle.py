@@ -290,10 +290,17 @@ def track(frame, ref, u, mode=MODE_CCU, eps=200.0, newton_it=NEWTON_MAX_IT):
     p, ccp, _ = integer_peak(cc)
     status = NEAR_TIE if is_near_tie(cc) else 0
     U = upsampled_grid(X, p, u)
-    d_grid, _ = grid_peak(U, p, u)
+    d_grid, m = grid_peak(U, p, u)
     d, c, H, st = newton(X, d_grid, p, u, max_it=newton_it)
     out.update(d=d, d_grid=d_grid, p=p, peak=c, hess=np.array([H[0, 0], H[0, 1], H[1, 1]]),
-               cc_peak=ccp, status=status | st)
+               cc_peak=ccp, status=status | st, grid_index=m)
+    # diagnostics for comparisons made in lower precision (no part of the
+    # result): the gaps between the two largest correlation and grid values,
+    # and the grid maximum without the DC term's constant X(0)/(ny nx)
+    top_cc = np.sort(cc.ravel())[-2:]
+    top_u = np.sort(U.ravel())[-2:]
+    out.update(cc_gap=float(top_cc[1] - top_cc[0]), grid_gap=float(top_u[1] - top_u[0]),
+               grid_ac=float(abs(top_u[1] - X[0, 0].real / X.size)))
     return out
 
 

@@ -26,12 +26,15 @@ def result_fields(res: torch.Tensor):
 class CCPTrack(torch.autograd.Function):
     @staticmethod
     def forward(ctx, frames: torch.Tensor, ref: torch.Tensor, tracker: Tracker):
-        ref32 = ref.detach().to(torch.float32).contiguous()
+        # a private copy: the backward needs the reference of this forward,
+        # whatever the tracker holds (or the caller does to `ref`) by then
+        ref32 = ref.detach().to(torch.float32).clone()
         tracker.set_reference(ref32)
         fr = frames.detach().contiguous()
         res = tracker.track(fr)
         d, peak, status = result_fields(res)
         ctx.tracker = tracker
+        ctx.ref32 = ref32
         ctx.save_for_backward(fr, res)
         ctx.ref_shape = ref.shape
         ctx.frames_dtype = frames.dtype
@@ -47,6 +50,9 @@ class CCPTrack(torch.autograd.Function):
             return None, None, None
         if g_d is None:
             g_d = torch.zeros((fr.shape[0], 2), dtype=torch.float64, device=fr.device)
+        tr = ctx.tracker
+        if not (len(tr._refs) == 1 and tr._refs[0] is ctx.ref32):
+            tr.set_reference(ctx.ref32)  # another forward has set its own since
         gf, gr = ctx.tracker.track_grad(fr, res, g_d.contiguous(), g_peak, want_frames=want_f,
                                         want_ref=want_r)
         gfr = gf.reshape(fr.shape).to(ctx.frames_dtype) if want_f else None

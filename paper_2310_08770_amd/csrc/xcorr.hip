@@ -417,13 +417,10 @@ __global__ void __launch_bounds__(kThreads) k_rows_inv(const C* __restrict__ T, 
   if constexpr (ARGMAX && !FP64) {
     // the two largest keys of the block (keys are unique: they hold the index)
     unsigned long long best = 0, second = 0;
-    auto push = [&](unsigned long long k) {
-      if (k > best) {
-        second = best;
-        best = k;
-      } else if (k > second) {
-        second = k;
-      }
+    auto push = [&](unsigned long long k) {  // branch-free top-two insertion
+      const unsigned long long lo = k < best ? k : best;
+      best = k < best ? best : k;
+      second = second < lo ? lo : second;
     };
     for (int i = tid; i < RPB * L; i += kThreads) {
       const int r = i / L, n = i - r * L;

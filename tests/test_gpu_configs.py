@@ -9,6 +9,7 @@ import torch
 
 from oracle import ccpt_oracle as O
 from synth import frames as S
+from tests._parity import grid_exempt, oracle_many, same_grid_point, tie_band
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda", 0)
@@ -28,32 +29,47 @@ def tracker(**kw):
     return Tracker(**kw)
 
 
-def sampled_parity(res, w, idx, tol, **kw):
-    errs = []
-    for i in idx:
-        ref = np.asarray(w.refs[int(w.ref_ids[i])], np.float32).astype(np.float64)
-        o = O.track(w.frames[i], ref, w.u, **kw)
+def sampled_parity(res, w, idx, tol, precision="fp32", **kw):
+    """Frames idx of a full-size call against the oracle (run in parallel on
+    the host): integer peak bit-exact off near ties, d within tol off
+    fallbacks, grid index as in tests/_parity.py; returns the d errors."""
+    idx = [int(i) for i in idx]
+    orc = oracle_many([w.frames[i] for i in idx], w.refs, [int(w.ref_ids[i]) for i in idx], w.u, **kw)
+    errs, agree, checked = [], 0, 0
+    for j, i in enumerate(idx):
+        o = orc[j]
+        if not tie_band(o):
+            assert (int(res["status"][i]) & O.NEAR_TIE) == (o["status"] & O.NEAR_TIE), i
         if not (o["status"] & O.NEAR_TIE):
             assert tuple(res["p"][i]) == tuple(o["p"]), (i, res["p"][i], o["p"])
+            if not grid_exempt(o, precision):
+                checked += 1
+                assert same_grid_point(res["d_grid"][i], o["d_grid"], w.u), (i, res["d_grid"][i],
+                                                                             o["d_grid"])
+            agree += same_grid_point(res["d_grid"][i], o["d_grid"], w.u)
         if o["status"] & (O.NEWTON_FALLBACK | O.WINDOW_EXIT):
             continue
         errs.append(np.max(np.abs(res["d"][i] - o["d"])))
     errs = np.array(errs)
+    say(f"  {len(idx)} frames vs oracle: max err {errs.max():.2e} px, p99 "
+        f"{np.percentile(errs, 99):.2e}, mean {errs.mean():.2e}; grid index agrees on "
+        f"{agree}/{len(idx)} ({checked} beyond rounding, all equal)")
     assert errs.max() <= tol, errs.max()
     return errs
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
 def test_airy256_full_stream(prec):
-    say(f"case: airy256_u100 10,000 frames in one call, {prec}; 40 sampled frames vs oracle")
+    say(f"case: airy256_u100 10,000 frames in one call, {prec}; 400 sampled frames vs oracle")
     from paper_2310_08770_amd import decode
     w = S.config2(10000)
     tr = tracker(upsample=100, precision=prec)
     tr.set_reference(t(w.refs[0].astype(np.float32)))
     res = decode(tr.track(t(np.stack(w.frames))))
-    assert np.all(res["status"] == 0), np.unique(res["status"])
-    idx = np.linspace(0, 9999, 40).astype(int)
-    errs = sampled_parity(res, w, idx, 1e-3)
+    # no fallbacks; near ties of the integer peak are compared on the sample
+    assert np.all((res["status"] & ~np.uint32(O.NEAR_TIE)) == 0), np.unique(res["status"])
+    idx = np.linspace(0, 9999, 400).astype(int)
+    errs = sampled_parity(res, w, idx, 1e-3, precision=prec)
     say(f"  max err {errs.max():.2e}")
     # accuracy against the known shifts (shot noise sets the scale)
     err_true = np.abs(res["d"] - w.shifts)
@@ -63,7 +79,7 @@ def test_airy256_full_stream(prec):
 
 
 def test_uneven_rois_full():
-    say("case: uneven_rois_u100, 4096 ROIs of 7 sizes in one call; 35 sampled vs oracle")
+    say("case: uneven_rois_u100, 4096 ROIs of 7 sizes in one call; 560 sampled vs oracle")
     from paper_2310_08770_amd import decode
     w = S.config3(4096)
     tr = tracker(upsample=100)
@@ -72,23 +88,23 @@ def test_uneven_rois_full():
     sizes = w.meta["sizes"]
     idx = []
     for n in sorted(set(sizes)):
-        idx += list(np.nonzero(sizes == n)[0][:5])
+        idx += list(np.nonzero(sizes == n)[0][:80])
     errs = sampled_parity(res, w, idx, 1e-3)
     say(f"  max err {errs.max():.2e} over {len(errs)} ROIs; statuses {np.unique(res['status'])}")
     tr.close()
 
 
 def test_gauss512_u200_split_precision_and_crb():
-    say("case: gauss512_u200, 2048 frames bf16x2; 6 sampled vs oracle; scatter vs CRB")
+    say("case: gauss512_u200, 2048 frames bf16x2; all 2048 vs oracle; scatter vs CRB")
     from paper_2310_08770_amd import decode
     w = S.config4(2048)
     ref = w.refs[0].astype(np.float32)
     tr = tracker(upsample=200, precision="bf16x2")
     tr.set_reference(t(ref))
     res = decode(tr.track(t(np.stack(w.frames))))
-    errs = sampled_parity(res, w, np.linspace(0, 2047, 6).astype(int), 1e-2)
+    errs = sampled_parity(res, w, np.arange(2048), 1e-2, precision="bf16x2")
     say(f"  max err vs oracle {errs.max():.2e}")
-    ok = res["status"] == 0
+    ok = (res["status"] & ~np.uint32(O.NEAR_TIE)) == 0
     crb = np.linalg.inv(tr.fisher(t(ref)).cpu().numpy())
     sd = np.sqrt(np.diag(crb))
     scatter = (res["d"][ok] - w.shifts[ok]).std(axis=0)

@@ -308,3 +308,40 @@ def test_chunks_on_two_streams_match_one_stream():
         assert decode(res).tobytes() == want["bf16x2"], rep
         _ = (fr[:4].float() * 2.0).sum().item()  # unrelated eager work between replays
     tr.close()
+
+
+def test_backward_uses_the_reference_of_its_own_forward():
+    """Two forwards with different templates on one tracker, then one
+    backward of the sum: each term's gradients are taken against its own
+    template (compared with the FP64 oracle adjoint)."""
+    say("case: two forwards, one backward, config5 128x128, 3 frames")
+    from paper_2310_08770_amd.autograd import track
+    w = S.config5(3)
+    tr = tracker(upsample=100)
+    fr = t(np.stack(w.frames)).requires_grad_(True)
+    ref_a = w.refs[0].astype(np.float32)
+    ref_b = np.roll(ref_a, (1, -2), axis=(0, 1)) * np.float32(0.8) + np.float32(3.0)
+    ea = t(ref_a).requires_grad_(True)
+    eb = t(ref_b).requires_grad_(True)
+    da, _, sa = track(fr, ea, tr)
+    db, _, sb = track(fr, eb, tr)
+    rng = np.random.Generator(np.random.PCG64(11))
+    wa, wb = rng.standard_normal((3, 2)), rng.standard_normal((3, 2))
+    ((da * t(wa)).sum() + (db * t(wb)).sum()).backward()
+    torch.cuda.synchronize()
+    gI = np.zeros((3, 128, 128))
+    for ref, wt, g_ref in ((ref_a, wa, ea.grad), (ref_b, wb, eb.grad)):
+        r64 = ref.astype(np.float64)
+        gE = np.zeros((128, 128))
+        for i in range(3):
+            o = O.track(w.frames[i], r64, 100)
+            a, b = O.adjoint(w.frames[i], r64, o, wt[i], 0.0)
+            gI[i] += a
+            gE += b
+        rel = np.max(np.abs(g_ref.cpu().numpy() - gE)) / np.max(np.abs(gE))
+        say(f"  template gradient rel err {rel:.2e}")
+        assert rel <= 1e-3
+    rel = np.max(np.abs(fr.grad.cpu().numpy() - gI)) / np.max(np.abs(gI))
+    say(f"  frame gradient rel err {rel:.2e}")
+    assert rel <= 1e-3
+    tr.close()

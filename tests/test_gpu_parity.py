@@ -13,6 +13,7 @@ import torch
 
 from oracle import ccpt_oracle as O
 from synth import frames as S
+from tests._parity import grid_exempt, same_grid_point
 
 pytestmark = pytest.mark.gpu
 
@@ -45,24 +46,35 @@ def oracle_track(frames, refs, ref_ids, u, **kw):
     return [O.track(f, refs32[int(i)], u, **kw) for f, i in zip(frames, ref_ids)]
 
 
-def compare(res, orc, tol=1e-3, grid_tol=None, label=""):
+def compare(res, orc, u, tol=1e-3, precision="fp32", label=""):
+    """Integer peak bit-exact off near ties; d within tol; where the oracle
+    fell back, the GPU's grid estimate is the oracle's grid point (unless the
+    oracle's top two grid values are within the precision's rounding); the
+    grid index of every other frame is checked the same way and its
+    agreement rate reported."""
     n = len(orc)
-    bad_p, errs = [], []
+    bad_p, bad_g, errs = [], [], []
+    agree = checked = 0
     for i in range(n):
         o = orc[i]
         if o["status"] & O.NEAR_TIE:
             continue
         if tuple(res["p"][i]) != tuple(o["p"]):
             bad_p.append((i, tuple(res["p"][i]), tuple(o["p"])))
+        if not grid_exempt(o, precision):
+            checked += 1
+            if same_grid_point(res["d_grid"][i], o["d_grid"], u):
+                agree += 1
+            else:
+                bad_g.append((i, tuple(res["d_grid"][i]), tuple(o["d_grid"])))
         if o["status"] & (O.NEWTON_FALLBACK | O.WINDOW_EXIT):
-            if grid_tol is not None:
-                errs.append(np.max(np.abs(res["d_grid"][i] - o["d_grid"])))
             continue
         errs.append(np.max(np.abs(res["d"][i] - o["d"])))
     errs = np.array(errs)
     say(f"{label}: n={n} peak mismatches={len(bad_p)} max|dd|={errs.max():.3e} "
-        f"mean={errs.mean():.3e}")
+        f"mean={errs.mean():.3e} grid index {agree}/{checked} (exempt {n - checked})")
     assert not bad_p, bad_p[:5]
+    assert not bad_g, bad_g[:5]
     assert errs.max() <= tol, (errs.max(), int(np.argmax(errs)))
     return errs
 
@@ -72,7 +84,7 @@ def test_config1_gauss64_fp32():
     w = S.config1()
     res = gpu_track(w.frames, w.refs, w.ref_ids, w.u)
     orc = oracle_track(w.frames, w.refs, w.ref_ids, w.u)
-    compare(res, orc, label="config1")
+    compare(res, orc, w.u, label="config1")
     assert np.all(res["status"] == 0)
 
 
@@ -81,7 +93,7 @@ def test_config2_airy256_fp32_sample():
     w = S.config2(48)
     res = gpu_track(w.frames, w.refs, w.ref_ids, w.u)
     orc = oracle_track(w.frames, w.refs, w.ref_ids, w.u)
-    compare(res, orc, label="config2")
+    compare(res, orc, w.u, label="config2")
 
 
 @pytest.mark.parametrize("n", [16, 18, 24, 32, 36, 48, 54, 64, 96, 128, 192, 256, 512])
@@ -97,7 +109,7 @@ def test_sizes_fp32(n):
     ref = spot + 20.0
     res = gpu_track(frames, [ref], [0] * 6, 20)
     orc = oracle_track(frames, [ref], [0] * 6, 20)
-    compare(res, orc, label=f"N={n}")
+    compare(res, orc, 20, label=f"N={n}")
 
 
 def test_exact_integer_shifts():
@@ -130,7 +142,7 @@ def test_mixed_sizes_one_call():
     w = S.config3(40)
     res = gpu_track(w.frames, w.refs, w.ref_ids, w.u)
     orc = oracle_track(w.frames, w.refs, w.ref_ids, w.u)
-    compare(res, orc, label="config3[:40]")
+    compare(res, orc, w.u, label="config3[:40]")
 
 
 def test_deterministic_rerun():
