@@ -109,7 +109,7 @@ def test_ccu_fp32_many_frames_match_the_oracle(shape):
     tr.set_reference(t(w.refs[0], np.float32))
     res = decode(tr.track(t(np.stack(w.frames))))
     idx = list(range(0, 48, 6))
-    sub = {k: res[k][idx] for k in ("p", "d")}
+    sub = {k: res[k][idx] for k in ("p", "d", "status")}
     errs = oracle_check(sub, [w.frames[i] for i in idx], w.refs[0], w.u, O.MODE_CCU, 200.0, 1e-3)
     say(f"  max |dd| {errs.max():.2e} px")
     tr.close()
@@ -184,7 +184,7 @@ def test_mixed_shapes_in_one_call():
     res = decode(tr.track([t(f) for f in frames], ids))
     for k in range(len(shapes)):
         sel = [i for i in range(len(ids)) if ids[i] == k]
-        sub = {q: res[q][sel] for q in ("p", "d")}
+        sub = {q: res[q][sel] for q in ("p", "d", "status")}
         oracle_check(sub, [frames[i] for i in sel], refs[k], 128, O.MODE_CCSN, 200.0, 1e-3)
     tr.close()
 
