@@ -205,6 +205,28 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
 int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* out,
                      void* stream);
 
+/* ccpt_track_batch for callers that cannot allocate device memory (tight
+   serving loops, harnesses that forbid hipMalloc): the same tracking,
+   results and errors, with every per-call buffer (descriptor table, frame
+   states, spectra workspace) in the library's static device scratch of
+   64 MiB per GPU instead of the context's grown workspace.  Calls no
+   hipMalloc/hipFree.  `rois` is a host array, consumed before the call
+   returns (its copy to the scratch is enqueued from pageable memory, so the
+   call is not meant for stream capture).  Frames run in chunks that fit the
+   scratch (about 80 frames of 256x256 in split precision); no graphs,
+   second stream or profiling events; small launches take the unsplit
+   kernels, so results equal ccpt_track_batch's to rounding (<= 1e-6 px;
+   integer peak and grid index identical).  The context must already hold
+   its references (set by ccpt_set_reference, which allocates).  All calls
+   on one GPU share its scratch, which keeps the last call's contents: calls
+   that overlap on one GPU (other streams, threads or contexts) race and
+   must be ordered by the caller.  n <= CCPT_STATIC_MAX_ROIS, else
+   CCPT_E_INVALID; a frame whose workspace alone exceeds the scratch (none
+   of the supported shapes) gives CCPT_E_INVALID. */
+#define CCPT_STATIC_MAX_ROIS 65536
+int ccpt_track_batch_static(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* out,
+                            void* stream);
+
 /* Backward pass of ccpt_track_batch for L = sum_i g_d[i] . d_i + g_peak[i] C_i(d_i)
    (implicit function theorem at the Newton maximiser; integer and grid
    maxima are piecewise constant and carry no gradient).  `fwd` is the

@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libccpt.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.cpp", "xcorr.hip", "updft.hip", "updft64.hip", "newton.hip", "grad.hip",
-           "reference.hip"]
+           "reference.hip", "scratch.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -92,6 +92,8 @@ def lib():
         L.ccpt_set_reference.restype = c_int
         L.ccpt_track_batch.argtypes = [c_void_p, POINTER(Roi), c_int, c_void_p, c_void_p]
         L.ccpt_track_batch.restype = c_int
+        L.ccpt_track_batch_static.argtypes = [c_void_p, POINTER(Roi), c_int, c_void_p, c_void_p]
+        L.ccpt_track_batch_static.restype = c_int
         L.ccpt_track_grad.argtypes = [c_void_p, POINTER(Roi), c_int, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p]
         L.ccpt_track_grad.restype = c_int
@@ -120,7 +122,7 @@ def lib():
 EXPORTS = ["ccpt_default_options", "ccpt_create", "ccpt_destroy", "ccpt_set_reference",
            "ccpt_track_batch", "ccpt_track_grad", "ccpt_fisher", "ccpt_autotune", "ccpt_schedule",
            "ccpt_stage_times", "ccpt_status_string", "ccpt_last_error", "ccpt_mean_aligned",
-           "ccpt_track_update", "ccpt_drift_filter"]
+           "ccpt_track_update", "ccpt_drift_filter", "ccpt_track_batch_static"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -242,6 +244,19 @@ class Tracker:
             out = torch.empty((n, RESULT_BYTES), dtype=torch.uint8, device=self.device)
         self._check(lib().ccpt_track_batch(self._h, arr, n, c_void_p(out.data_ptr()),
                                            c_void_p(_stream_handle(stream))))
+        return out
+
+    def track_static(self, frames=None, ref_ids=None, out=None, stream=None, rois=None):
+        """track() through ccpt_track_batch_static: no device allocation by
+        the library (its static scratch holds every per-call buffer); `out`
+        must then be supplied by the caller as well."""
+        if rois is None:
+            rois = self.rois(frames, ref_ids)
+        arr, n = rois
+        if out is None:
+            raise ValueError("track_static needs a preallocated out buffer [n, 72] uint8")
+        self._check(lib().ccpt_track_batch_static(self._h, arr, n, c_void_p(out.data_ptr()),
+                                                  c_void_p(_stream_handle(stream))))
         return out
 
     def track_grad(self, frames, fwd, g_d, g_peak=None, want_frames=True, want_ref=True,

@@ -283,12 +283,41 @@ int chunk_for(const ccpt_ctx* ctx, int n) {
   return default_chunk(n, ctx->o.precision);
 }
 
+// Device memory the launches of one call work in: the context's buffers
+// (ccpt_track_batch) or the library's static scratch (ccpt_track_batch_static).
+struct CallMem {
+  char* ws = nullptr;          // chunk workspace, slot_ws bytes per slot
+  size_t slot_ws = 0;
+  FrameState* st = nullptr;    // frame states, slot_st entries per slot
+  size_t slot_st = 0;
+  void* ypart = nullptr;       // FP32 split-K partials, slot_ypart bytes per slot (or none)
+  size_t slot_ypart = 0;
+  void* nparts = nullptr;      // Newton partial models per slot (or none)
+  size_t chunk_bytes = 0;      // > 0: chunks limited to this much workspace
+  bool slots = true;           // two chunk slots allowed (CCPT_FLAG_STREAMS)
+  bool mark = true;            // profiling events allowed
+  bool* st_dirty = nullptr;    // set while a chunk's states may be left non-initial
+};
+
+CallMem ctx_mem(ccpt_ctx* ctx) {
+  CallMem m;
+  m.ws = ctx->ws;
+  m.slot_ws = ctx->slot_ws;
+  m.st = ctx->st_buf;
+  m.slot_st = ctx->slot_st;
+  m.ypart = ctx->ypart;
+  m.slot_ypart = ctx->slot_ypart;
+  m.nparts = ctx->nparts;
+  m.st_dirty = &ctx->st_dirty;
+  return m;
+}
+
 // Carves the workspace for a chunk of `chunk` frames of size n (every part
 // 16-byte aligned: spectra rows hold an even number of float2).
-void carve(ccpt_ctx* ctx, int n, int chunk, int slot, GroupParams& g) {
+void carve(ccpt_ctx* ctx, const CallMem& mem, int n, int chunk, int slot, GroupParams& g) {
   const size_t spec = spec_elems(n);
-  char* ws = ctx->ws + slot * ctx->slot_ws;
-  g.st = ctx->st_buf + slot * ctx->slot_st;
+  char* ws = mem.ws + slot * mem.slot_ws;
+  g.st = mem.st + slot * mem.slot_st;
   if (fp64(ctx)) {
     g.T = g.X = nullptr;
     g.Xb = nullptr;
@@ -409,16 +438,21 @@ bool use_slots(const ccpt_ctx* ctx) {
 }
 
 // Launches the whole tracking sequence for one size group, chunk by chunk.
-int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int count,
-              ccpt_result* out, hipStream_t s) {
-  const int chunk = std::min(count, chunk_for(ctx, n));
+int run_group(ccpt_ctx* ctx, const CallMem& mem, int n, const FrameDesc* d_desc, int first,
+              int count, ccpt_result* out, hipStream_t s) {
+  int chunk = std::min(count, chunk_for(ctx, n));
+  if (mem.chunk_bytes) {
+    chunk = std::min<int>(chunk, (int)(mem.chunk_bytes / frame_ws_bytes(n, ctx->o.precision)));
+    chunk = std::min<int>(chunk, (int)mem.slot_st);
+  }
+  if (chunk < 1) return fail(ctx, CCPT_E_INVALID, "no workspace for one frame");
   SizeTables& t = ctx->tables[table_key(n)];
   const int ny = code_ny(n), nx = code_nx(n);
   UpdftTables ut{t.ky, t.wb, t.Mp, ctx->o.precision, t.kfold};
-  const Marker mark = marker_of(ctx, s);
+  const Marker mark = mem.mark ? marker_of(ctx, s) : Marker{};
   // several chunks: alternate between the two slots (streams s and aux),
   // forked from and joined back into s
-  const bool two = count > chunk && use_slots(ctx);
+  const bool two = count > chunk && mem.slots && use_slots(ctx);
   if (two) {
     HIP_CHECK(ctx, hipEventRecord(ctx->fork_evt, s));
     HIP_CHECK(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_evt, 0));
@@ -436,12 +470,15 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
     g.first = first + c0;
     g.count = std::min(chunk, count - c0);
     g.out = out;
-    carve(ctx, n, chunk, slot, g);
+    carve(ctx, mem, n, chunk, slot, g);
     const size_t yb = split_partials_bytes(ctx, n, g.count);
-    g.ypart = (yb && yb <= ctx->slot_ypart) ? (float*)((char*)ctx->ypart + slot * ctx->slot_ypart)
-                                            : nullptr;
-    g.nparts = (double*)ctx->nparts + (size_t)slot * kNewtonSplitMax * kNewtonParts * kNewtonCoef;
-    ctx->st_dirty = true;  // until this chunk's Newton launch has gone in
+    g.ypart = (yb && mem.ypart && yb <= mem.slot_ypart)
+                  ? (float*)((char*)mem.ypart + slot * mem.slot_ypart)
+                  : nullptr;
+    g.nparts = mem.nparts ? (double*)mem.nparts +
+                                (size_t)slot * kNewtonSplitMax * kNewtonParts * kNewtonCoef
+                          : nullptr;
+    if (mem.st_dirty) *mem.st_dirty = true;  // until this chunk's Newton launch has gone in
     if ((fp64(ctx) ? launch_xcorr64(n, g, cs, mark) : launch_xcorr(ny, nx, g, cs, mark)))
       return failed("correlation");
     mark(CCPT_STAGE_UPDFT, 1);
@@ -453,7 +490,7 @@ int run_group(ccpt_ctx* ctx, int n, const FrameDesc* d_desc, int first, int coun
     if (launch_newton(ny, nx, g, step_limit(ctx), cs))
       return failed("Newton");
     mark(CCPT_STAGE_NEWTON, 0);
-    ctx->st_dirty = false;
+    if (mem.st_dirty) *mem.st_dirty = false;
   }
   if (two) {
     HIP_CHECK(ctx, hipEventRecord(ctx->join_evt, ctx->aux));
@@ -658,7 +695,7 @@ int ccpt_create(ccpt_ctx** out, int device, const ccpt_options* opts) {
   ctx->o = o;
   ctx->M = M;
   ctx->c = M / 2;
-  if (hipSetDevice(device) != hipSuccess ||
+  if (hipSetDevice(device) != hipSuccess || scratch_setup(device) != 0 ||
       hipEventCreateWithFlags(&ctx->desc_evt, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->fork_evt, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->join_evt, hipEventDisableTiming) != hipSuccess ||
@@ -876,9 +913,10 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
 
   auto launch_all = [&]() -> int {
     int first = 0;
+    const CallMem mem = ctx_mem(ctx);
     for (size_t gi = 0; gi < sig.size(); gi += 2) {
       const int nn = sig[gi], cnt = sig[gi + 1];
-      int r2 = run_group(ctx, nn, ctx->d_desc, first, cnt, out, s);
+      int r2 = run_group(ctx, mem, nn, ctx->d_desc, first, cnt, out, s);
       if (r2) return r2;
       first += cnt;
     }
@@ -904,6 +942,55 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
     it = ctx->graphs.emplace(key, exec).first;
   }
   HIP_CHECK(ctx, hipGraphLaunch(it->second, s));
+  return CCPT_OK;
+}
+
+int ccpt_track_batch_static(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* out,
+                            void* stream) {
+  if (!ctx) return CCPT_E_INVALID;
+  if (n < 0 || (n > 0 && (!rois || !out))) return fail(ctx, CCPT_E_INVALID, "bad roi array");
+  if (n > CCPT_STATIC_MAX_ROIS)
+    return fail(ctx, CCPT_E_INVALID, "%d rois exceed the static scratch's %d", n,
+                CCPT_STATIC_MAX_ROIS);
+  if (n == 0) return CCPT_OK;
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  char* base = (char*)scratch_ptr(ctx->device);
+  if (!base) return fail(ctx, CCPT_E_HIP, "static scratch not set up on device %d", ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  Plan plan;
+  rc = plan_rois(ctx, rois, n, plan);
+  if (rc) return rc;
+  // scratch layout: descriptors | frame states of one chunk | chunk workspace
+  const size_t desc_bytes = ((size_t)n * sizeof(FrameDesc) + 255) / 256 * 256;
+  constexpr size_t kStates = 4096;  // the largest chunk of any schedule
+  const size_t st_bytes = (kStates * sizeof(FrameState) + 255) / 256 * 256;
+  CallMem mem;
+  mem.st = (FrameState*)(base + desc_bytes);
+  mem.slot_st = kStates;
+  mem.ws = base + desc_bytes + st_bytes;
+  mem.chunk_bytes = kScratchBytes - desc_bytes - st_bytes;
+  mem.slots = false;
+  mem.mark = false;
+  for (size_t gi = 0; gi < plan.sig.size(); gi += 2)
+    if (frame_ws_bytes(plan.sig[gi], ctx->o.precision) > mem.chunk_bytes)
+      return fail(ctx, CCPT_E_INVALID, "one %dx%d frame needs %zu bytes of workspace, more than "
+                  "the static scratch holds", code_ny(plan.sig[gi]), code_nx(plan.sig[gi]),
+                  frame_ws_bytes(plan.sig[gi], ctx->o.precision));
+  FrameDesc* d_desc = (FrameDesc*)base;
+  // from pageable memory: the host array is consumed before the call returns
+  HIP_CHECK(ctx, hipMemcpyAsync(d_desc, plan.desc.data(), (size_t)n * sizeof(FrameDesc),
+                                hipMemcpyHostToDevice, s));
+  // whatever an earlier call left in the states: back to the initial state
+  if (launch_init_state(mem.st, (int)kStates, s))
+    return fail(ctx, CCPT_E_HIP, "state initialisation launch failed");
+  int first = 0;
+  for (size_t gi = 0; gi < plan.sig.size(); gi += 2) {
+    const int nn = plan.sig[gi], cnt = plan.sig[gi + 1];
+    rc = run_group(ctx, mem, nn, d_desc, first, cnt, out, s);
+    if (rc) return rc;
+    first += cnt;
+  }
   return CCPT_OK;
 }
 

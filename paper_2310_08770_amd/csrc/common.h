@@ -288,6 +288,13 @@ int launch_rt_update(int N, const ccpt_result* res, const float2* F, float2* S, 
 // img *= scale / *cnt (zeros when *cnt == 0).
 int launch_scale_by_count(float* img, int nn, float scale, const unsigned* cnt, hipStream_t s);
 
+// Static device scratch of ccpt_track_batch_static (scratch.hip): its size,
+// the once-per-device set-up (call with `device` current; 0 on success) and
+// the device address kept by the set-up (null before it).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+int scratch_setup(int device);
+void* scratch_ptr(int device);
+
 // Fills bytes of device memory with zero using a kernel (graph-safe).
 int launch_zero(void* p, size_t bytes, hipStream_t s);
 

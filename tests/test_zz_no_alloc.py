@@ -1,0 +1,74 @@
+"""ccpt_track_batch_static (no device allocation: every per-call buffer in
+the library's static scratch) against ccpt_track_batch on the same inputs,
+two calls in a row on one context, the second smaller than the first."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from synth import frames as S
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _t(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _compare(a, b, u, label):
+    from paper_2310_08770_amd import decode
+    ra, rb = decode(a), decode(b)
+    assert np.array_equal(ra["p"], rb["p"]), label
+    assert np.array_equal(ra["status"], rb["status"]), label
+    assert np.max(np.abs(ra["d_grid"].astype(np.float64) - rb["d_grid"])) < 0.5 / u, label
+    err = np.max(np.abs(ra["d"] - rb["d"]))
+    say(f"  {label}: {len(ra)} results, max |dd| {err:.2e} px, bit-identical "
+        f"{bool(torch.equal(a, b))}")
+    assert err <= 1e-6, (label, err)
+
+
+@pytest.mark.parametrize("precision", ["bf16x2", "fp32"])
+def test_static_entry_matches_track_batch_on_two_calls(precision):
+    from paper_2310_08770_amd import Tracker, lib
+    say(f"case: ccpt_track_batch_static vs ccpt_track_batch, {precision}: "
+        "300 x 256^2 + 40 x 64^2, then 50 x 64^2")
+    L = lib()
+    w2 = S.config2(300)
+    w1 = S.config1(90)
+    tr = Tracker(upsample=100, precision=precision)
+    tr.set_reference([_t(w2.refs[0].astype(np.float32)), _t(w1.refs[0].astype(np.float32))])
+    big = _t(np.stack(w2.frames))
+    small = _t(np.stack(w1.frames))
+    # call 1: mixed sizes
+    frames = [big[i] for i in range(300)] + [small[i] for i in range(40)]
+    ids = [0] * 300 + [1] * 40
+    arr, n = tr.rois(frames, ids)
+    want = torch.empty((n, 72), dtype=torch.uint8, device=DEV)
+    got = torch.full((n, 72), 0xAB, dtype=torch.uint8, device=DEV)
+    assert L.ccpt_track_batch(tr._h, arr, n, ctypes.c_void_p(want.data_ptr()), None) == 0
+    assert L.ccpt_track_batch_static(tr._h, arr, n, ctypes.c_void_p(got.data_ptr()), None) == 0
+    torch.cuda.synchronize()
+    _compare(got, want, 100, "call 1")
+    # call 2: fewer, smaller frames (the scratch keeps call 1's contents)
+    arr2, n2 = tr.rois([small[i] for i in range(40, 90)], [1] * 50)
+    want2 = torch.empty((n2, 72), dtype=torch.uint8, device=DEV)
+    got2 = torch.full((n2, 72), 0xCD, dtype=torch.uint8, device=DEV)
+    assert L.ccpt_track_batch(tr._h, arr2, n2, ctypes.c_void_p(want2.data_ptr()), None) == 0
+    assert L.ccpt_track_batch_static(tr._h, arr2, n2, ctypes.c_void_p(got2.data_ptr()), None) == 0
+    torch.cuda.synchronize()
+    _compare(got2, want2, 100, "call 2")
+    # more rois than the scratch's descriptor table holds: a clear error
+    assert L.ccpt_track_batch_static(tr._h, arr2, 65537, ctypes.c_void_p(got2.data_ptr()),
+                                     None) == -1
+    buf = ctypes.create_string_buffer(256)
+    L.ccpt_last_error(tr._h, buf, 256)
+    assert b"static scratch" in buf.value
+    tr.close()
