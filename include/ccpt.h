@@ -130,7 +130,8 @@ enum ccpt_stage {
   CCPT_STAGE_UPDFT = 4,    /* upsampled matrix DFT + grid maximum */
   CCPT_STAGE_NEWTON = 5,   /* FP64 Newton refinement + result */
   CCPT_STAGE_GRAD = 6,     /* all kernels of ccpt_track_grad */
-  CCPT_NUM_STAGES = 7
+  CCPT_STAGE_XCORR = 7,    /* stages 1-3 in one kernel (256 x 256 frames) */
+  CCPT_NUM_STAGES = 8
 };
 
 typedef struct ccpt_options {

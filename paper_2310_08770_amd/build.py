@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libccpt.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.cpp", "xcorr.hip", "updft.hip", "updft64.hip", "newton.hip", "grad.hip",
-           "reference.hip", "scratch.hip"]
+           "reference.hip", "scratch.hip", "xcorr256.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

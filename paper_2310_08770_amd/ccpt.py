@@ -38,7 +38,7 @@ U16, F32, F64 = 0, 1, 2
 FLAG_GRAPH = 1
 FLAG_PROFILE = 2
 FLAG_STREAMS = 4
-STAGES = ["init", "rows_fwd", "cols", "rows_inv", "updft", "newton", "grad"]
+STAGES = ["init", "rows_fwd", "cols", "rows_inv", "updft", "newton", "grad", "xcorr"]
 
 RESULT_DTYPE = np.dtype([
     ("d", "<f8", (2,)),

@@ -438,8 +438,20 @@ bool use_slots(const ccpt_ctx* ctx) {
 }
 
 // Launches the whole tracking sequence for one size group, chunk by chunk.
+// Frames first..first+count-1 of a plan are uint16 or float32 with an even
+// pitch and pixel pairs aligned to their size.
+bool pairs_ok(const std::vector<FrameDesc>& desc, int first, int count) {
+  for (int i = first; i < first + count; ++i) {
+    const FrameDesc& d = desc[i];
+    if ((d.dtype != CCPT_U16 && d.dtype != CCPT_F32) || (d.pitch & 1) ||
+        ((uintptr_t)d.data & (uintptr_t)(2 * dtype_bytes(d.dtype) - 1)))
+      return false;
+  }
+  return true;
+}
+
 int run_group(ccpt_ctx* ctx, const CallMem& mem, int n, const FrameDesc* d_desc, int first,
-              int count, ccpt_result* out, hipStream_t s) {
+              int count, ccpt_result* out, hipStream_t s, bool pairs) {
   int chunk = std::min(count, chunk_for(ctx, n));
   if (mem.chunk_bytes) {
     chunk = std::min<int>(chunk, (int)(mem.chunk_bytes / frame_ws_bytes(n, ctx->o.precision)));
@@ -466,6 +478,7 @@ int run_group(ccpt_ctx* ctx, const CallMem& mem, int n, const FrameDesc* d_desc,
     const int slot = two ? (ci & 1) : 0;
     hipStream_t cs = slot ? ctx->aux : s;
     GroupParams g = base_params(ctx, n);
+    g.pairs_ok = pairs ? 1 : 0;
     g.desc = d_desc;
     g.first = first + c0;
     g.count = std::min(chunk, count - c0);
@@ -916,7 +929,8 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
     const CallMem mem = ctx_mem(ctx);
     for (size_t gi = 0; gi < sig.size(); gi += 2) {
       const int nn = sig[gi], cnt = sig[gi + 1];
-      int r2 = run_group(ctx, mem, nn, ctx->d_desc, first, cnt, out, s);
+      int r2 = run_group(ctx, mem, nn, ctx->d_desc, first, cnt, out, s,
+                         pairs_ok(plan.desc, first, cnt));
       if (r2) return r2;
       first += cnt;
     }
@@ -987,7 +1001,7 @@ int ccpt_track_batch_static(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_res
   int first = 0;
   for (size_t gi = 0; gi < plan.sig.size(); gi += 2) {
     const int nn = plan.sig[gi], cnt = plan.sig[gi + 1];
-    rc = run_group(ctx, mem, nn, d_desc, first, cnt, out, s);
+    rc = run_group(ctx, mem, nn, d_desc, first, cnt, out, s, pairs_ok(plan.desc, first, cnt));
     if (rc) return rc;
     first += cnt;
   }

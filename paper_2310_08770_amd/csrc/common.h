@@ -79,6 +79,8 @@ struct GroupParams {
   double2* X64;
   PeakCand* cand;
   const double2* tw64;
+  int pairs_ok;           // every frame is uint16 or float32 with an even pitch and
+                          // pixel pairs aligned to their size (one load per pair)
   int trans;              // 1: the frames are wider than tall and are processed as
                           // their transposes (NY x NX above is the transposed
                           // shape); integer-peak and grid indices keep the frame's
@@ -208,6 +210,11 @@ int launch_xcorr(int ny, int nx, const GroupParams& g, hipStream_t s, const Mark
 int launch_spectrum(int ny, int nx, const void* data, int dtype, int pitch, long img_stride,
                     int trans, int n, int weight, float eps, int conj_out, float2* T, float2* spec,
                     const float2* tw, hipStream_t s);
+
+// The correlation stage of 256 x 256 frames (FP32 and split precision) in
+// one kernel with the half spectrum held in registers: the same outputs as
+// the three passes of launch_xcorr (X, Xb, the frame states), no T.
+int launch_xcorr256(const GroupParams& g, hipStream_t s);
 
 // FP64 mode: the same two calls with every FFT in FP64 (g.T64, g.X64,
 // g.cand; the integer peak is left as per-row-block candidates).
