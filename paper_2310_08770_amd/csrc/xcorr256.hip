@@ -28,6 +28,8 @@
 // scale does not move the maximum).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "fft.h"
 
@@ -100,6 +102,18 @@ __device__ __forceinline__ void dft16(float2* v) {
 
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
+// Pointers read from a descriptor are generic; these say they are global, so
+// their loads are global (vector memory only) rather than flat loads, which
+// the LDS waits would also have to wait for.
+typedef const unsigned long long __attribute__((address_space(1)))* gcf2;  // float2 pairs
+typedef const float __attribute__((address_space(1)))* gcf;
+typedef const unsigned short __attribute__((address_space(1)))* gcu16;
+
+__device__ __forceinline__ float2 ld2(gcf2 p) {
+  const unsigned long long u = *p;
+  return make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
+}
+
 // F[k] = E + W O from Z[k] (a) and Z[128-k] (b), W = W256^k:
 // E = (a + conj b)/2, O = (a - conj b)/2i
 __device__ __forceinline__ float2 r2c_bin(float2 a, float2 b, float2 w) {
@@ -133,6 +147,7 @@ template <bool SPLIT>
 __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
   __shared__ __align__(16) float2 lds[kLds];
   __shared__ float2 tw[N];
+  __shared__ float2 stage[2 * N];  // products of the real columns 0 and N/2
   __shared__ unsigned long long red[2][kT / 64];
   __shared__ unsigned redu[3][kT / 64];
   const int t = threadIdx.x;
@@ -162,20 +177,23 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
     // an even pitch and pairs aligned to their size: one load per pair)
     const size_t p = (size_t)desc.pitch;
     if (desc.dtype == CCPT_U16) {
-      const unsigned short* b = (const unsigned short*)desc.data + (size_t)rq * p + 2 * n2;
+      const gcu16 b = (gcu16)desc.data + (size_t)rq * p + 2 * n2;
+      unsigned raw[64];  // all loads in flight before the first use
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1) {
-          const unsigned w = *(const unsigned*)(b + 64 * j * p + 16 * n1);
-          take(make_float2((float)(w & 0xFFFFu), (float)(w >> 16)), j * 16 + n1);
-        }
+        for (int n1 = 0; n1 < 16; ++n1)
+          raw[j * 16 + n1] = *(const unsigned __attribute__((address_space(1)))*)(b + 64 * j * p + 16 * n1);
+#pragma unroll
+      for (int e = 0; e < 64; ++e) take(make_float2((float)(raw[e] & 0xFFFFu), (float)(raw[e] >> 16)), e);
     } else {
-      const float* b = (const float*)desc.data + (size_t)rq * p + 2 * n2;
+      const gcf b = (gcf)desc.data + (size_t)rq * p + 2 * n2;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1) take(*(const float2*)(b + 64 * j * p + 16 * n1), j * 16 + n1);
+        for (int n1 = 0; n1 < 16; ++n1) r[j * 16 + n1] = ld2((gcf2)(b + 64 * j * p + 16 * n1));
+#pragma unroll
+      for (int e = 0; e < 64; ++e) take(r[e], e);
     }
   }
   __syncthreads();  // twiddle table
@@ -338,9 +356,16 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
     __syncthreads();
   }
   // ---------------------------------------------------------------- C2, product, X
+  // C2 thread: hp = t / 64 (the pair of c values, uniform per wave), cp = t % 64
+  // (columns cp and cp + 64).  The reference spectrum is read in batches whose
+  // loads are issued before the previous batch's products (no stores come
+  // between them, so a batch waits only for its own loads); the products go
+  // out after all of a half's loads.  Column 0 (packed) falls to lane 0 of
+  // every wave: its two real columns' products go to LDS and out by all
+  // threads.
   {
     const int hp = t >> 6, cp = t & 63;
-    const float2* R = (const float2*)desc.rspec;
+    const gcf2 R = (gcf2)desc.rspec;
     float2* Xf = g.X + (size_t)f * N * H;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -355,78 +380,125 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
       }
       const int col = cp + 64 * i;
       float2 xb0 = make_float2(0.f, 0.f);
-      if (i == 0 && cp == 0) {
-        // packed column: P = F0 + i F128 with F0, F128 the spectra of real
-        // columns, F0[ky] = (P[ky] + conj P[-ky]) / 2, F128 = (P - conj P[-ky]) / 2i;
-        // a pair (ky, -ky) gives conjugate values of both
-        auto pair = [&](int e1, int e2) {
-          const float2 a = r[pslot(e1, 0)], bb = r[pslot(e2, 0)];
-          const float2 F0 = make_float2(0.5f * (a.x + bb.x), 0.5f * (a.y - bb.y));
-          const float2 F1 = make_float2(0.5f * (a.y + bb.y), -0.5f * (a.x - bb.x));
-          const int ky1 = kap(hp, e1 >> 4) + 16 * (e1 & 15);
-          const int ky2 = kap(hp, e2 >> 4) + 16 * (e2 & 15);
-          const float2 X0 = cmul(F0, R[(size_t)ky1 * H]);
-          const float2 X1 = cmul(F1, R[(size_t)ky1 * H + N / 2]);
-          Xf[(size_t)ky1 * H] = X0;
-          Xf[(size_t)ky1 * H + N / 2] = X1;
-          r[pslot(e1, 0)] = make_float2(X0.x - X1.y, X0.y + X1.x);  // X0 + i X128
-          if (ky1 == 0) xb0 = make_float2(-X1.y, X0.y + X1.x);      // the DC term dropped
-          if (e2 != e1) {
-            const float2 Y0 = cmul(conjf2(F0), R[(size_t)ky2 * H]);
-            const float2 Y1 = cmul(conjf2(F1), R[(size_t)ky2 * H + N / 2]);
-            Xf[(size_t)ky2 * H] = Y0;
-            Xf[(size_t)ky2 * H + N / 2] = Y1;
-            r[pslot(e2, 0)] = make_float2(Y0.x - Y1.y, Y0.y + Y1.x);
+      const bool packed = i == 0 && cp == 0;
+      if (packed) {
+        // P = F0 + i F128 with F0, F128 the spectra of the real columns 0 and
+        // N/2: F0[ky] = (P[ky] + conj P[-ky]) / 2, F128 = (P[ky] - conj P[-ky]) / 2i;
+        // a pair (ky, -ky) gives conjugate values of both.  Pairs by element:
+        // hp > 0: (d, 31 - d); hp = 0: (0, 0), (8, 8), (d, 16 - d), (16 + d, 31 - d)
+        auto run = [&](auto hz) {
+          constexpr bool H0 = decltype(hz)::value;  // hp == 0 (compile-time pair list)
+          constexpr int np = H0 ? 17 : 16;
+          auto e1_of = [](int q) {
+            return !H0 ? q : (q == 0 ? 0 : q == 1 ? 8 : q <= 8 ? q - 1 : 16 + (q - 9));
+          };
+          auto e2_of = [](int q) {
+            return !H0 ? 31 - q : (q == 0 ? 0 : q == 1 ? 8 : q <= 8 ? 16 - (q - 1) : 31 - (q - 9));
+          };
+          auto ky_of = [&](int e) { return kap(hp, e >> 4) + 16 * (e & 15); };
+          // batches of 4 pairs: R*[ky1][0], R*[ky1][N/2], R*[ky2][0], R*[ky2][N/2]
+          float2 rb[2][4][4];
+          auto load = [&](int b, float2 (*dst)[4]) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int q = 4 * b + k;
+              if (q < np) {
+                const int k1 = ky_of(e1_of(q)), k2 = ky_of(e2_of(q));
+                dst[k][0] = ld2(R + (size_t)k1 * H);
+                dst[k][1] = ld2(R + (size_t)k1 * H + N / 2);
+                dst[k][2] = ld2(R + (size_t)k2 * H);
+                dst[k][3] = ld2(R + (size_t)k2 * H + N / 2);
+              }
+            }
+          };
+          load(0, rb[0]);
+#pragma unroll
+          for (int b = 0; b < 5; ++b) {
+            if (b < 4) load(b + 1, rb[(b + 1) & 1]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int q = 4 * b + k;
+              if (q < np) {
+                const int e1 = e1_of(q), e2 = e2_of(q);
+                const float2 a = r[pslot(e1, 0)], bb = r[pslot(e2, 0)];
+                const float2 F0 = make_float2(0.5f * (a.x + bb.x), 0.5f * (a.y - bb.y));
+                const float2 F1 = make_float2(0.5f * (a.y + bb.y), -0.5f * (a.x - bb.x));
+                const int k1 = ky_of(e1), k2 = ky_of(e2);
+                const float2 X0 = cmul(F0, rb[b & 1][k][0]), X1 = cmul(F1, rb[b & 1][k][1]);
+                stage[k1] = X0;
+                stage[N + k1] = X1;
+                r[pslot(e1, 0)] = make_float2(X0.x - X1.y, X0.y + X1.x);  // X0 + i X128
+                if (H0 && q == 0) xb0 = make_float2(-X1.y, X0.y + X1.x);  // ky = 0: DC dropped
+                if (e2 != e1) {
+                  const float2 Y0 = cmul(conjf2(F0), rb[b & 1][k][2]);
+                  const float2 Y1 = cmul(conjf2(F1), rb[b & 1][k][3]);
+                  stage[k2] = Y0;
+                  stage[N + k2] = Y1;
+                  r[pslot(e2, 0)] = make_float2(Y0.x - Y1.y, Y0.y + Y1.x);
+                }
+              }
+            }
           }
         };
-        if (hp != 0) {
-#pragma unroll
-          for (int d = 0; d < 16; ++d) pair(d, 16 + 15 - d);
-        } else {
-          pair(0, 0);
-          pair(8, 8);
-#pragma unroll
-          for (int d = 1; d < 8; ++d) pair(d, 16 - d);
-#pragma unroll
-          for (int d = 0; d < 8; ++d) pair(16 + d, 16 + 15 - d);
-        }
+        if (hp == 0)
+          run(std::integral_constant<bool, true>());
+        else
+          run(std::integral_constant<bool, false>());
       } else {
+        float2 rb[2][8];
+        auto load = [&](int b, float2* dst) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int d = 0; d < 16; ++d) {
-            const int ky = kap(hp, s) + 16 * d;
-            const float2 x = cmul(r[pslot(s * 16 + d, i)], R[(size_t)ky * H + col]);
-            Xf[(size_t)ky * H + col] = x;
-            r[pslot(s * 16 + d, i)] = x;
+          for (int k = 0; k < 8; ++k) {
+            const int e = 8 * b + k, ky = kap(hp, e >> 4) + 16 * (e & 15);
+            dst[k] = ld2(R + (size_t)ky * H + col);
           }
+        };
+        load(0, rb[0]);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if (b < 3) load(b + 1, rb[(b + 1) & 1]);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int e = 8 * b + k;
+            r[pslot(e, i)] = cmul(r[pslot(e, i)], rb[b & 1][k]);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 32; ++e) {
+          const int ky = kap(hp, e >> 4) + 16 * (e & 15);
+          Xf[(size_t)ky * H + col] = r[pslot(e, i)];
+        }
+      }
+      if (i == 0) {
+        // the two real columns' products, staged by the packed lanes
+        __syncthreads();
+        for (int e = t; e < 2 * N; e += kT) Xf[(size_t)(e & (N - 1)) * H + (e >> 8) * (N / 2)] = stage[e];
       }
       if constexpr (SPLIT) {
         // the split copy for the matrix cores goes out row kx by row kx
-        // (ky contiguous) through LDS; row 0 is X[., 0] + i X[., N/2] with
-        // the DC term dropped
+        // (ky contiguous, four words per store) through LDS; row 0 is
+        // X[., 0] + i X[., N/2] with the DC term dropped
         uint2* xs = (uint2*)lds;
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int d = 0; d < 16; ++d) {
-            const int ky = kap(hp, s) + 16 * d;
-            float2 x = r[pslot(s * 16 + d, i)];
-            if (i == 0 && s == 0 && d == 0 && cp == 0 && hp == 0) x = xb0;
-            unsigned wh, wl;
-            split_pair(x, wh, wl);
-            xs[cp * QS + ky] = make_uint2(wh, wl);
-          }
+        for (int e = 0; e < 32; ++e) {
+          const int ky = kap(hp, e >> 4) + 16 * (e & 15);
+          float2 x = r[pslot(e, i)];
+          if (i == 0 && e == 0 && cp == 0 && hp == 0) x = xb0;
+          unsigned wh, wl;
+          split_pair(x, wh, wl);
+          xs[cp * QS + ky] = make_uint2(wh, wl);
+        }
         __syncthreads();
         constexpr int P = xb_pitch(N);
         unsigned* hi = g.Xb + (size_t)f * 2 * (N / 2) * P;
         unsigned* lo = hi + (size_t)(N / 2) * P;
-        for (int e = t; e < 64 * N; e += kT) {
-          const int row = e >> 8, ky = e & 255;
-          const uint2 wv = xs[row * QS + ky];
-          hi[(size_t)(row + 64 * i) * P + ky] = wv.x;
-          lo[(size_t)(row + 64 * i) * P + ky] = wv.y;
+        for (int e = t; e < 64 * N / 4; e += kT) {
+          const int row = e >> 6, ky = (e & 63) * 4;
+          const uint4 a = *(const uint4*)&xs[row * QS + ky];
+          const uint4 b = *(const uint4*)&xs[row * QS + ky + 2];
+          *(uint4*)&hi[(size_t)(row + 64 * i) * P + ky] = make_uint4(a.x, a.z, b.x, b.z);
+          *(uint4*)&lo[(size_t)(row + 64 * i) * P + ky] = make_uint4(a.y, a.w, b.y, b.w);
         }
       }
       // I1: inverse DFT over d, twiddle W256^{-c a'}
