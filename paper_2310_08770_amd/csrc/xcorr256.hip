@@ -41,11 +41,24 @@ constexpr int kT = 512;  // threads per block (8 waves)
 constexpr int N = 256, H = N / 2 + 1;
 
 // LDS strides (complex values), padded against bank conflicts
-constexpr int RS = 128 + 8;   // row exchanges: [y (128)][k1 (16)][n2 (8)]
+// The 16-byte chunks a thread reads with one b128 load are XOR-swizzled by the
+// reader's own index, so the 16 lanes served together hit distinct banks.
+constexpr int RS2 = 128 + 4;  // first row exchange: [y (128)][k1 (16)][n2 (8)]
+constexpr int RS7 = 128 + 8;  // last row exchange: [y (128)][a'' (8)][k1 (16)]
 constexpr int CS = 256 + 4;   // transposes: [kx (64)][y (256)]
 constexpr int QS = 256 + 2;   // column exchanges: [kx (64)][16][16]
-constexpr int kLds = 128 * RS > 64 * CS ? (128 * RS > 64 * QS ? 128 * RS : 64 * QS)
-                                        : (64 * CS > 64 * QS ? 64 * CS : 64 * QS);
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kLds = cmax(cmax(128 * RS2, 128 * RS7), cmax(64 * CS, 64 * QS));
+// element positions within a row or column block
+__device__ __forceinline__ int e2pos(int k1, int n2) {  // chunks (n2 pairs) swizzled by bit 2 of k1
+  return k1 * 8 + 2 * ((n2 >> 1) ^ ((k1 >> 2) & 1)) + (n2 & 1);
+}
+__device__ __forceinline__ int e5pos(int a, int c) {  // chunks (c pairs) swizzled by a / 2
+  return a * 16 + 2 * ((c >> 1) ^ (a >> 1)) + (c & 1);
+}
+__device__ __forceinline__ int e7pos(int a, int k1) {  // chunks (k1 pairs) swizzled by a / 2
+  return a * 16 + 2 * ((k1 >> 1) ^ (a >> 1)) + (k1 & 1);
+}
 
 __device__ __forceinline__ int kap(int g, int s) { return s == 0 ? g : (g == 0 ? 8 : 16 - g); }
 
@@ -143,13 +156,13 @@ __device__ __forceinline__ T wave_max(T v) {
 
 }  // namespace
 
-template <bool SPLIT>
+template <bool SPLIT, bool SN>
 __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
   __shared__ __align__(16) float2 lds[kLds];
   __shared__ float2 tw[N];
   __shared__ float2 stage[2 * N];  // products of the real columns 0 and N/2
-  __shared__ unsigned long long red[2][kT / 64];
-  __shared__ unsigned redu[3][kT / 64];
+  __shared__ float redf[2][kT / 64];
+  __shared__ unsigned redu[4][kT / 64];
   const int t = threadIdx.x;
   const int f = blockIdx.x;
   const FrameDesc desc = g.desc[g.first + f];
@@ -161,10 +174,9 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
   unsigned kmin = 0xFFFFFFFFu, kmax = 0u, bad;
   {
     const int n2 = t & 7, rq = t >> 3;
-    const bool sn = g.mode == CCPT_MODE_CCSN;
     const float eps = g.eps;
     auto take = [&](float2 a, int e) {
-      if (sn) {
+      if (SN) {
         a.x = (a.x + eps) * (a.x + eps);
         a.y = (a.y + eps) * (a.y + eps);
       }
@@ -219,7 +231,7 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
       for (int jj = 0; jj < 2; ++jj) {
         const int j = 2 * h + jj, yl = rq + 64 * jj;
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) lds[yl * RS + k1 * 8 + n2] = r[j * 16 + k1];
+        for (int k1 = 0; k1 < 16; ++k1) lds[yl * RS2 + e2pos(k1, n2)] = r[j * 16 + k1];
       }
     }
     __syncthreads();
@@ -230,10 +242,11 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
         const int j = 2 * h + jj, yl = rq + 64 * jj;
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-          const float4* src = (const float4*)&lds[yl * RS + kap(gg, s) * 8];
+          const int k1 = kap(gg, s), sw = (k1 >> 2) & 1;
+          const float4* src = (const float4*)&lds[yl * RS2 + k1 * 8];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const float4 v = src[q];
+            const float4 v = src[q ^ sw];
             r[j * 16 + s * 8 + 2 * q] = make_float2(v.x, v.y);
             r[j * 16 + s * 8 + 2 * q + 1] = make_float2(v.z, v.w);
           }
@@ -527,7 +540,7 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
       for (int s = 0; s < 2; ++s) {
         const int c = kap(hp, s);
 #pragma unroll
-        for (int a = 0; a < 16; ++a) lds[cp * QS + a * 16 + c] = r[pslot(s * 16 + a, h)];
+        for (int a = 0; a < 16; ++a) lds[cp * QS + e5pos(a, c)] = r[pslot(s * 16 + a, h)];
       }
     }
     __syncthreads();
@@ -539,7 +552,7 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
         const float4* src = (const float4*)&lds[cl * QS + ap * 16];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          const float4 v = src[q];
+          const float4 v = src[q ^ (ap >> 1)];
           r[pslot(ii * 16 + 2 * q, h)] = make_float2(v.x, v.y);
           r[pslot(ii * 16 + 2 * q + 1, h)] = make_float2(v.z, v.w);
         }
@@ -641,7 +654,7 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-          for (int a = 0; a < 8; ++a) lds[yl * RS + a * 16 + kap(gg, s)] = r[j * 16 + s * 8 + a];
+          for (int a = 0; a < 8; ++a) lds[yl * RS7 + e7pos(a, kap(gg, s))] = r[j * 16 + s * 8 + a];
       }
     }
     __syncthreads();
@@ -650,10 +663,10 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) {
         const int j = 2 * h + jj, yl = rq + 64 * jj;
-        const float4* src = (const float4*)&lds[yl * RS + a2 * 16];
+        const float4* src = (const float4*)&lds[yl * RS7 + a2 * 16];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          const float4 v = src[q];
+          const float4 v = src[q ^ (a2 >> 1)];
           r[j * 16 + 2 * q] = make_float2(v.x, v.y);
           r[j * 16 + 2 * q + 1] = make_float2(v.z, v.w);
         }
@@ -661,62 +674,74 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
     }
   }
   // ---------------------------------------------------------------- J2 + maximum
-  unsigned long long best = 0, second = 0;
+  // the two largest values (equal values count twice) by float max/min, then
+  // the lowest row-major index holding the frame's maximum in a second pass
+  float t1 = -__builtin_inff(), t2 = -__builtin_inff();
   {
-    const int a2 = t & 7, rq = t >> 3;
-    auto push = [&](unsigned long long k) {
-      const unsigned long long lo = k < best ? k : best;
-      best = k < best ? best : k;
-      second = second < lo ? lo : second;
-    };
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       dft16<+1>(r + 16 * j);
-      const int y = rq + 64 * j;
 #pragma unroll
       for (int b2 = 0; b2 < 16; ++b2) {
-        const int n = a2 + 8 * b2;
-        const unsigned flat = (unsigned)(y * N + 2 * n);
-        push(peak_key(r[16 * j + b2].x, flat));
-        push(peak_key(r[16 * j + b2].y, flat + 1));
+        const float2 v = r[16 * j + b2];
+        float lo = fminf(t1, v.x);
+        t1 = fmaxf(t1, v.x);
+        t2 = fmaxf(t2, lo);
+        lo = fminf(t1, v.y);
+        t1 = fmaxf(t1, v.y);
+        t2 = fmaxf(t2, lo);
       }
     }
   }
+  auto merge2 = [](float& a1, float& a2, float b1, float b2) {
+    const float lo = fminf(a1, b1);
+    a1 = fmaxf(a1, b1);
+    a2 = fmaxf(fmaxf(a2, b2), lo);
+  };
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long b1 = __shfl_xor(best, o, 64), b2 = __shfl_xor(second, o, 64);
-    const unsigned long long lo = b1 < best ? b1 : best;
-    second = second > b2 ? second : b2;
-    second = second > lo ? second : lo;
-    best = b1 > best ? b1 : best;
-  }
+  for (int o = 32; o > 0; o >>= 1) merge2(t1, t2, __shfl_xor(t1, o, 64), __shfl_xor(t2, o, 64));
   // a non-finite value has a key above +inf's (NaN) or below -inf's, or equal
   bad = (kmax >= 0xFF800000u || kmin <= 0x007FFFFFu) ? 1u : 0u;
   kmin = ~wave_max(~kmin);
   kmax = wave_max(kmax);
   bad = wave_max(bad);
   if ((t & 63) == 0) {
-    red[0][t >> 6] = best;
-    red[1][t >> 6] = second;
+    redf[0][t >> 6] = t1;
+    redf[1][t >> 6] = t2;
     redu[0][t >> 6] = kmin;
     redu[1][t >> 6] = kmax;
     redu[2][t >> 6] = bad;
   }
   __syncthreads();
+  t1 = redf[0][0];
+  t2 = redf[1][0];
+#pragma unroll
+  for (int w = 1; w < kT / 64; ++w) merge2(t1, t2, redf[0][w], redf[1][w]);
+  unsigned idx = 0xFFFFFFFFu;
+  {
+    const int a2 = t & 7, rq = t >> 3;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int b2 = 0; b2 < 16; ++b2) {
+        const unsigned flat = (unsigned)((rq + 64 * j) * N + 2 * (a2 + 8 * b2));
+        if (r[16 * j + b2].x == t1) idx = min(idx, flat);
+        if (r[16 * j + b2].y == t1) idx = min(idx, flat + 1);
+      }
+  }
+  idx = ~wave_max(~idx);
+  if ((t & 63) == 0) redu[3][t >> 6] = idx;
+  __syncthreads();
   if (t == 0) {
     for (int w = 1; w < kT / 64; ++w) {
-      const unsigned long long b1 = red[0][w], b2 = red[1][w];
-      const unsigned long long lo = b1 < best ? b1 : best;
-      second = second > b2 ? second : b2;
-      second = second > lo ? second : lo;
-      best = b1 > best ? b1 : best;
+      idx = min(idx, redu[3][w]);
       kmin = min(kmin, redu[0][w]);
       kmax = max(kmax, redu[1][w]);
       bad |= redu[2][w];
     }
     FrameState& st = g.st[f];
-    st.peak_key = best;
-    st.second_key = second;
+    st.peak_key = peak_key(t1, idx);
+    st.second_key = peak_key(t2, 0u);
     st.amin = kmin;
     st.amax = kmax;
     if (bad) st.flags |= CCPT_ST_NONFINITE;
@@ -724,10 +749,15 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
 }
 
 int launch_xcorr256(const GroupParams& g, hipStream_t s) {
-  if (g.Xb)
-    hipLaunchKernelGGL((k_xcorr256<true>), dim3(g.count), dim3(kT), 0, s, g);
+  const bool sn = g.mode == CCPT_MODE_CCSN;
+  if (g.Xb && sn)
+    hipLaunchKernelGGL((k_xcorr256<true, true>), dim3(g.count), dim3(kT), 0, s, g);
+  else if (g.Xb)
+    hipLaunchKernelGGL((k_xcorr256<true, false>), dim3(g.count), dim3(kT), 0, s, g);
+  else if (sn)
+    hipLaunchKernelGGL((k_xcorr256<false, true>), dim3(g.count), dim3(kT), 0, s, g);
   else
-    hipLaunchKernelGGL((k_xcorr256<false>), dim3(g.count), dim3(kT), 0, s, g);
+    hipLaunchKernelGGL((k_xcorr256<false, false>), dim3(g.count), dim3(kT), 0, s, g);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
