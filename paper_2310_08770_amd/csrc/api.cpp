@@ -266,7 +266,8 @@ size_t frame_ws_bytes(int n, int precision) {
   if (precision == CCPT_PREC_FP64)
     return 2 * spec_elems(n) * sizeof(double2) + (size_t)(n / row_block64(n)) * sizeof(PeakCand);
   size_t b = 2 * spec_elems(n) * sizeof(float2);
-  if (precision == CCPT_PREC_BF16X2) b += split_words(n) * sizeof(unsigned);
+  if (precision == CCPT_PREC_BF16X2)
+    b += split_words(n) * sizeof(unsigned) + (size_t)code_ny(n) * sizeof(float2);  // Xb, Zc
   return b;
 }
 
@@ -330,9 +331,12 @@ void carve(ccpt_ctx* ctx, const CallMem& mem, int n, int chunk, int slot, GroupP
   g.X = g.T + spec * chunk;
   char* p = (char*)(g.X + spec * chunk);
   g.Xb = nullptr;
+  g.Zc = nullptr;
   if (split(ctx)) {
     g.Xb = (unsigned*)p;
     p += split_words(n) * sizeof(unsigned) * chunk;
+    g.Zc = (float2*)p;
+    p += (size_t)code_ny(n) * sizeof(float2) * chunk;
   }
   (void)p;
 }
@@ -484,6 +488,9 @@ int run_group(ccpt_ctx* ctx, const CallMem& mem, int n, const FrameDesc* d_desc,
     g.count = std::min(chunk, count - c0);
     g.out = out;
     carve(ctx, mem, n, chunk, slot, g);
+    // the one-kernel correlation leaves the split for the matrix DFT to make
+    if (g.Xb && xcorr_fused(ny, nx, pairs)) g.Xb = nullptr;
+    if (g.Xb) g.Zc = nullptr;
     const size_t yb = split_partials_bytes(ctx, n, g.count);
     g.ypart = (yb && mem.ypart && yb <= mem.slot_ypart)
                   ? (float*)((char*)mem.ypart + slot * mem.slot_ypart)

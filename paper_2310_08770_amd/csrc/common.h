@@ -58,6 +58,9 @@ struct GroupParams {
   unsigned* Xb;           // split-precision copy of X for the matrix cores, or null:
                           // [count][2 (hi, lo)][N/2][xb_pitch(N)] words, one word =
                           // bf16 re | bf16 im << 16, ky contiguous, DC zeroed
+  float2* Zc;             // split precision on the one-kernel 256 x 256 path (Xb
+                          // null): [count][N], Z[ky] = X[ky, 0] + i X[ky, N/2] with
+                          // the DC term dropped; the matrix DFT splits X itself
   FrameState* st;         // [count]
   ccpt_result* out;       // caller's results
   const float2* tw;       // exp(-2 pi i m / N), m < N
@@ -215,6 +218,10 @@ int launch_spectrum(int ny, int nx, const void* data, int dtype, int pitch, long
 // one kernel with the half spectrum held in registers: the same outputs as
 // the three passes of launch_xcorr (X, Xb, the frame states), no T.
 int launch_xcorr256(const GroupParams& g, hipStream_t s);
+
+// Whether frames of ny x nx take that one-kernel path (pairs_ok as in
+// GroupParams); launch_xcorr and the launch set-up agree through it.
+inline bool xcorr_fused(int ny, int nx, bool pairs_ok) { return ny == 256 && nx == 256 && pairs_ok; }
 
 // FP64 mode: the same two calls with every FFT in FP64 (g.T64, g.X64,
 // g.cand; the integer peak is left as per-row-block candidates).

@@ -549,7 +549,12 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
 // is read 2 times per frame instead of 2*MT); its three products accumulate
 // into one register tile per row half (separate ones per product left the
 // compiler shuffling accumulators beside the pending Stage A tiles).
-template <int NY, int NX, int MT>
+//
+// FROMX: the frame's spectrum comes as FP32 X (row-major) plus the packed
+// column Zc instead of the split copy Xb, and each chunk's B fragments are
+// split into bf16 hi/lo here, after the MFMAs of the chunk before (the same
+// words the split copy would hold).
+template <int NY, int NX, int MT, bool FROMX>
 __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
     k_updft_bf16x2_wide(GroupParams g, const unsigned* __restrict__ kfold,
                         const unsigned short* __restrict__ WbT, int Mp) {
@@ -678,7 +683,51 @@ __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
   };
 
   u32x4 bh[KC / 8], bl[KC / 8];
-  if constexpr (PIPE) {
+  if constexpr (FROMX) {
+    static_assert(PIPE && xb_pitch(NY) == NY, "FP32 operands on the pipelined path only");
+    constexpr int H = NX / 2 + 1;
+    // column kxrow of X, or the packed column for kxrow = 0
+    const float2* Xc = kxrow == 0 ? g.Zc + (size_t)f * NY : g.X + (size_t)f * NY * H + kxrow;
+    const int xs = kxrow == 0 ? 1 : H;
+    float2 xr[KC / 8][4];  // the next chunk's values, split after this chunk's MFMAs
+    auto load_x = [&](int k0) {
+#pragma unroll
+      for (int s8 = 0; s8 < KC / 8; ++s8)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          xr[s8][e] = (BFULL || bvalid) ? Xc[(size_t)(k0 + s8 * 8 + 4 * h + e) * xs]
+                                        : make_float2(0.f, 0.f);
+    };
+    auto split_x = [&]() {
+#pragma unroll
+      for (int s8 = 0; s8 < KC / 8; ++s8)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          unsigned wh, wl;
+          split_pair(xr[s8][e], wh, wl);
+          bh[s8][e] = wh;
+          bl[s8][e] = wl;
+        }
+    };
+    load_x(0);
+    load_k(0);
+    split_x();
+    store_k(raw);
+    __syncthreads();
+    for (int c = 0; c < NCH; ++c) {
+      const bool more = c + 1 < NCH;
+      if (more) {
+        load_x((c + 1) * KC);
+        load_k((c + 1) * KC);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      mma_chunk(raw + (c & 1) * KW, bh, bl);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) store_k(raw + ((c + 1) & 1) * KW);
+      __syncthreads();
+      if (more) split_x();
+    }
+  } else if constexpr (PIPE) {
     // software pipeline: chunk c + 1's operands are loaded while chunk c's
     // MFMAs run; K' chunks alternate between two LDS buffers
     u32x4 nh[KC / 8], nl[KC / 8];
@@ -911,12 +960,21 @@ static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
                          s, g, (const float2*)t.ky, (const float*)t.wb, t.Mp, (float*)nullptr, 1);
     }
   } else if (t.precision == CCPT_PREC_BF16X2) {
-    if (!g.Xb) return -1;
+    if (!g.Xb && !(NY == 256 && NX == 256 && g.Zc)) return -1;
     if constexpr (NX >= kWideMinN) {
       constexpr int MT = kWideMT;
       constexpr int NW = (NX / 2 + 31) / 32;
       if (!t.kfold) return -1;
-      hipLaunchKernelGGL((k_updft_bf16x2_wide<NY, NX, MT>), dim3((mtiles + MT - 1) / MT, g.count),
+      if constexpr (NY == 256 && NX == 256) {
+        if (!g.Xb) {  // the one-kernel correlation left X and its packed column
+          if (!g.Zc) return -1;
+          hipLaunchKernelGGL((k_updft_bf16x2_wide<NY, NX, MT, true>),
+                             dim3((mtiles + MT - 1) / MT, g.count), dim3(64 * NW), 0, s, g,
+                             (const unsigned*)t.kfold, (const unsigned short*)t.wb, t.Mp);
+          return hipGetLastError() == hipSuccess ? 0 : -1;
+        }
+      }
+      hipLaunchKernelGGL((k_updft_bf16x2_wide<NY, NX, MT, false>), dim3((mtiles + MT - 1) / MT, g.count),
                          dim3(64 * NW), 0, s, g, (const unsigned*)t.kfold,
                          (const unsigned short*)t.wb, t.Mp);
     } else {

@@ -392,7 +392,6 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
         for (int d = 0; d < 16; ++d) r[pslot(s * 16 + d, i)] = v[d];
       }
       const int col = cp + 64 * i;
-      float2 xb0 = make_float2(0.f, 0.f);
       const bool packed = i == 0 && cp == 0;
       if (packed) {
         // P = F0 + i F128 with F0, F128 the spectra of the real columns 0 and
@@ -441,7 +440,6 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
                 stage[k1] = X0;
                 stage[N + k1] = X1;
                 r[pslot(e1, 0)] = make_float2(X0.x - X1.y, X0.y + X1.x);  // X0 + i X128
-                if (H0 && q == 0) xb0 = make_float2(-X1.y, X0.y + X1.x);  // ky = 0: DC dropped
                 if (e2 != e1) {
                   const float2 Y0 = cmul(conjf2(F0), rb[b & 1][k][2]);
                   const float2 Y1 = cmul(conjf2(F1), rb[b & 1][k][3]);
@@ -483,35 +481,16 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
         }
       }
       if (i == 0) {
-        // the two real columns' products, staged by the packed lanes
+        // the two real columns' products, staged by the packed lanes; in
+        // split precision also Z = X[., 0] + i X[., N/2] without the DC term,
+        // the packed column the matrix DFT takes as its kx = 0 operand
         __syncthreads();
         for (int e = t; e < 2 * N; e += kT) Xf[(size_t)(e & (N - 1)) * H + (e >> 8) * (N / 2)] = stage[e];
-      }
-      if constexpr (SPLIT) {
-        // the split copy for the matrix cores goes out row kx by row kx
-        // (ky contiguous, four words per store) through LDS; row 0 is
-        // X[., 0] + i X[., N/2] with the DC term dropped
-        uint2* xs = (uint2*)lds;
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 32; ++e) {
-          const int ky = kap(hp, e >> 4) + 16 * (e & 15);
-          float2 x = r[pslot(e, i)];
-          if (i == 0 && e == 0 && cp == 0 && hp == 0) x = xb0;
-          unsigned wh, wl;
-          split_pair(x, wh, wl);
-          xs[cp * QS + ky] = make_uint2(wh, wl);
-        }
-        __syncthreads();
-        constexpr int P = xb_pitch(N);
-        unsigned* hi = g.Xb + (size_t)f * 2 * (N / 2) * P;
-        unsigned* lo = hi + (size_t)(N / 2) * P;
-        for (int e = t; e < 64 * N / 4; e += kT) {
-          const int row = e >> 6, ky = (e & 63) * 4;
-          const uint4 a = *(const uint4*)&xs[row * QS + ky];
-          const uint4 b = *(const uint4*)&xs[row * QS + ky + 2];
-          *(uint4*)&hi[(size_t)(row + 64 * i) * P + ky] = make_uint4(a.x, a.z, b.x, b.z);
-          *(uint4*)&lo[(size_t)(row + 64 * i) * P + ky] = make_uint4(a.y, a.w, b.y, b.w);
+        if constexpr (SPLIT) {
+          for (int ky = t; ky < N; ky += kT) {
+            const float2 x0 = stage[ky], x1 = stage[N + ky];
+            g.Zc[(size_t)f * N + ky] = make_float2((ky ? x0.x : 0.f) - x1.y, x0.y + x1.x);
+          }
         }
       }
       // I1: inverse DFT over d, twiddle W256^{-c a'}
@@ -750,9 +729,9 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
 
 int launch_xcorr256(const GroupParams& g, hipStream_t s) {
   const bool sn = g.mode == CCPT_MODE_CCSN;
-  if (g.Xb && sn)
+  if (g.Zc && sn)
     hipLaunchKernelGGL((k_xcorr256<true, true>), dim3(g.count), dim3(kT), 0, s, g);
-  else if (g.Xb)
+  else if (g.Zc)
     hipLaunchKernelGGL((k_xcorr256<true, false>), dim3(g.count), dim3(kT), 0, s, g);
   else if (sn)
     hipLaunchKernelGGL((k_xcorr256<false, true>), dim3(g.count), dim3(kT), 0, s, g);
