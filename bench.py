@@ -361,15 +361,15 @@ def main():
     log(f"[bench] generated {n} frames {N}x{N} in {time.perf_counter() - t0:.1f}s")
 
     cpu = None
-    one = None
+    one_core = None
     if not args.no_cpu:
         cores = max(1, min(16, os.cpu_count() or 1))
         sample = min(args.cpu_sample, n)
         cpu = cpu_baseline(frames, ref, w.u, sample, cores)
         log(f"[bench] oracle: {sample} frames in {cpu['wall']:.1f}s wall on {cpu['cores']} cores "
             f"({cpu['cpu_s']:.1f}s CPU)")
-        one = cpu_one_core(frames, ref, w.u, min(64, n))
-        log(f"[bench] oracle on one core: {len(one[0])} frames in {one[1]:.1f}s")
+        one_core = cpu_one_core(frames, ref, w.u, min(64, n))
+        log(f"[bench] oracle on one core: {len(one_core[0])} frames in {one_core[1]:.1f}s")
 
     import torch
 
@@ -572,11 +572,11 @@ def main():
                       f"one single-threaded process per core; {cpu['cpu_s']:.1f} s of CPU work",
             "mean_ms_per_frame_per_core": round(1e3 * cpu["cpu_s"] / k, 3),
             "cpu": cpu_model(),
-            "one_core": None if one is None else {
-                "frames_per_s": round(len(one[0]) / one[1], 2),
-                "p50_ms_per_frame": round(float(np.median(one[0])) * 1e3, 3),
-                "p99_ms_per_frame": round(float(np.percentile(one[0], 99)) * 1e3, 3),
-                "sample": f"first {len(one[0])} frames, one single-threaded process"},
+            "one_core": None if one_core is None else {
+                "frames_per_s": round(len(one_core[0]) / one_core[1], 2),
+                "p50_ms_per_frame": round(float(np.median(one_core[0])) * 1e3, 3),
+                "p99_ms_per_frame": round(float(np.percentile(one_core[0], 99)) * 1e3, 3),
+                "sample": f"first {len(one_core[0])} frames, one single-threaded process"},
         }
 
     line = {
