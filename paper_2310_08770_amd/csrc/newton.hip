@@ -36,7 +36,7 @@
 
 namespace ccpt {
 
-constexpr int kNThreads = 512;
+constexpr int kNThreads = 256;  // three blocks (frames) per CU: one frame's serial phases overlap the others' loops
 constexpr int kOrder = 7;                               // K
 constexpr int kCoef = (kOrder + 1) * (kOrder + 2) / 2;  // pairs with n + m <= K
 static_assert(kCoef == kNewtonCoef, "model size");
@@ -133,45 +133,62 @@ constexpr int pow2_floor(int x) {
 }
 
 // Work split of one model pass over a spectrum of NY rows and NX/2+1
-// columns: each column kx < NX/2 is shared by S adjacent lanes (ky segments
-// of length SEG); after their moments are combined, lane `seg` accumulates
-// the coefficients with m = seg, seg + S, ... (QM of them).
+// columns.  Rows are taken in conjugate pairs q = 1 .. NY/2-1 (rows q and
+// NY-q, whose phases and frequencies are conjugate and opposite), plus the
+// pair q = 0 of the two rows that pair with themselves (0 and the Nyquist
+// row NY/2).  Each column kx < NX/2 is shared by S adjacent lanes (pair
+// segments of length SEG), at least four, the block taking its columns in
+// NCG groups of CPG; after a column's moments are combined, lane `seg`
+// accumulates its share of the coefficients, m = seg, seg + S, ... (QM of
+// them), over the lane's columns.
+// Spectrum values are loaded in batches of up to 4 pairs, the next batch in
+// flight while the current one is summed.
 template <int NY, int NX>
 struct ModelSplit {
   static constexpr int NC = NX / 2;
-  static constexpr int S0 = kNThreads / NC;
-  static constexpr int S = pow2_floor(S0 < 64 ? (S0 < NY ? S0 : NY) : 64);
-  static constexpr int SEG = (NY + S - 1) / S;
+  static constexpr int NQ = NY / 2;  // row pairs
+  static constexpr int S0 = kNThreads / NC < 4 ? 4 : kNThreads / NC;
+  static constexpr int S = pow2_floor(S0 < 64 ? (S0 < NQ ? S0 : NQ) : 64);
+  static constexpr int CPG = kNThreads / S;          // columns per group
+  static constexpr int NCG = (NC + CPG - 1) / CPG;   // column groups, one after the other
+  static constexpr int SEG = (NQ + S - 1) / S;
   static constexpr int QM = (kOrder + S) / S;
+  // pairs per lane in one of the kNewtonParts shares of a split model
+  static constexpr int SEGP = ((NQ + kNewtonParts - 1) / kNewtonParts + S - 1) / S;
 };
 
 // One pass: the model coefficients around (sy, sx) into coef (LDS), from
-// the spectrum rows ky_lo <= ky < ky_hi (all rows: the full model; a range:
-// its share, the coefficients being linear in the spectrum).  CX is the
+// the row pairs q_lo <= q < q_hi (all pairs: the full model; a range: its
+// share, the coefficients being linear in the spectrum).  CX is the
 // spectrum's element type (float2, or double2 in FP64 mode).  Frames are
 // NY rows of NX (a_ky = 2 pi ky~ / NY, b_kx = 2 pi kx / NX, 1/N^2 becomes
 // 1/(NY NX)).
-template <int NY, int NX, typename CX>
+//
+// The lane's first pair and a zero offset pass through an empty asm
+// statement in every column group, so that the compiler forms the per-lane
+// offsets, frequencies and their powers where they are used instead of
+// hoisting them out of the column-group and re-centring loops (hundreds of
+// registers).
+//
+// For a pair q >= 1 with t1 = X[q] phi_q(sy), t2 = X[NY-q] conj(phi_q(sy))
+// and a = a_q, the two rows add (i a)^n (t1 + (-1)^n t2) to M_n; the sums
+// R_n + i I_n = sum a^n (t1 +- t2) are accumulated with FMAs on real powers
+// and M_n = i^n (R_n + i I_n) is formed once per column.
+template <int NY, int NX, typename CX, int SEGL = ModelSplit<NY, NX>::SEG>
 __device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy, double sx, double2* phy,
-                            double* ay, double (*red)[kOrder + 1][kOrder + 1],
-                            double (*nred)[2 * (kOrder + 1)], double* coef, int ky_lo = 0,
-                            int ky_hi = NY) {
+                            double (*red)[kOrder + 1][kOrder + 1],
+                            double (*nred)[2 * (kOrder + 1)], double* coef, int q_lo = 0,
+                            int q_hi = NY / 2) {
   using MS = ModelSplit<NY, NX>;
   constexpr int H = NX / 2 + 1;
-  constexpr int NC = MS::NC, S = MS::S, QM = MS::QM;
+  constexpr int NC = MS::NC, NQ = MS::NQ, S = MS::S, QM = MS::QM;
   const double pi = 3.14159265358979323846;
+  const double a_unit = 2.0 * pi / (double)NY;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int ky = tid; ky < NY; ky += kNThreads) {
-    if (2 * ky == NY) {
-      phy[ky] = make_double2(0.0, 0.0);  // the Nyquist row is added separately
-      ay[ky] = 0.0;
-    } else {
-      const int kt = 2 * ky < NY ? ky : ky - NY;
-      double sn, cs;
-      sincospi(2.0 * (double)kt * sy / (double)NY, &sn, &cs);
-      phy[ky] = make_double2(cs, sn);
-      ay[ky] = 2.0 * pi * (double)kt / (double)NY;
-    }
+  for (int q = tid; q < NQ; q += kNThreads) {
+    double sn, cs;
+    sincospi(2.0 * (double)q * sy / (double)NY, &sn, &cs);
+    phy[q] = make_double2(cs, sn);
   }
   __syncthreads();
   // Nyquist row: Re[exp(i pi sy) (i pi)^n]
@@ -186,43 +203,105 @@ __device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy
       t = make_double2(-pi * t.y, pi * t.x);
     }
   }
-  // ---- moments of column kx over this lane's ky segment
-  const int kx = tid / S, seg = tid % S;
-  double2 M[kOrder + 1];
-#pragma unroll
-  for (int n = 0; n <= kOrder; ++n) M[n] = make_double2(0.0, 0.0);
-  if (kx < NC) {
-    const int segl = (ky_hi - ky_lo + S - 1) / S;  // SEG for the full range
-    const int y0 = ky_lo + seg * segl, y1 = min(ky_hi, y0 + segl);
-    const CX* col = Xf + kx;
-#pragma unroll 4
-    for (int ky = y0; ky < y1; ++ky) {
-      const CX xf = col[(size_t)ky * H];
-      const double2 ph = phy[ky];
-      add_powers(M, make_double2((double)xf.x * ph.x - (double)xf.y * ph.y,
-                                 (double)xf.x * ph.y + (double)xf.y * ph.x),
-                 ay[ky]);
-    }
-    if (y0 <= NY / 2 && NY / 2 < y1) {
-      const CX xf = col[(size_t)(NY / 2) * H];
-#pragma unroll
-      for (int n = 0; n <= kOrder; ++n) {
-        M[n].x += (double)xf.x * ry[n];
-        M[n].y += (double)xf.y * ry[n];
-      }
-    }
-  }
-#pragma unroll
-  for (int n = 0; n <= kOrder; ++n) {
-    M[n].x = group_sum<S>(M[n].x);
-    M[n].y = group_sum<S>(M[n].y);
-  }
-  // ---- this lane's share of the coefficients: m = seg + S q
+  const int seg = tid % S;
   double acc[QM][kOrder + 1];
 #pragma unroll
   for (int q = 0; q < QM; ++q)
 #pragma unroll
     for (int n = 0; n <= kOrder; ++n) acc[q][n] = 0.0;
+#pragma unroll 1
+  for (int cg = 0; cg < MS::NCG; ++cg) {
+  // ---- moments of column kx over this lane's pair segment
+  const int kx = cg * MS::CPG + tid / S;
+  double R[kOrder + 1], I[kOrder + 1];
+#pragma unroll
+  for (int n = 0; n <= kOrder; ++n) R[n] = I[n] = 0.0;
+  if (kx < NC) {
+    // this lane's pairs qa <= q < qb (at most SEGL of them); q = 0 stands for
+    // row 0 (phase 1, a = 0) and the Nyquist row, which is loaded in the
+    // second slot and added separately
+    const int segl = (q_hi - q_lo + S - 1) / S;
+    int qa = q_lo + seg * segl;
+    const int qb = min(q_hi, qa + segl);
+    // (32-bit offsets from the frame's uniform base)
+    unsigned fo = 0;
+    asm volatile("" : "+s"(fo), "+v"(qa));
+    constexpr int BQ = SEGL < 4 ? SEGL : 4;
+    constexpr int NB = (SEGL + BQ - 1) / BQ;
+    CX b0[2 * BQ], b1[2 * BQ];
+    // unconditional loads from clamped addresses (no branches between the
+    // loads, so the next batch stays in flight while this one is summed);
+    // values past the segment are masked where they are used
+    auto load = [&](CX* b, int base) {
+#pragma unroll
+      for (int e = 0; e < BQ; ++e) {
+        const int q = min(base + e, NQ - 1);
+        b[2 * e] = Xf[fo + (unsigned)(q * H + kx)];
+        b[2 * e + 1] = Xf[fo + (unsigned)((q == 0 ? NQ : NY - q) * H + kx)];
+      }
+    };
+    auto sum = [&](const CX* b, int base) {
+#pragma unroll
+      for (int e = 0; e < BQ; ++e) {
+        const int q = base + e;
+        const bool v1 = q < qb, v2 = v1 && q > 0;
+        const double2 ph = phy[min(q, NQ - 1)];
+        const double x1 = v1 ? (double)b[2 * e].x : 0.0, y1 = v1 ? (double)b[2 * e].y : 0.0;
+        const double x2 = v2 ? (double)b[2 * e + 1].x : 0.0, y2 = v2 ? (double)b[2 * e + 1].y : 0.0;
+        const double t1x = x1 * ph.x - y1 * ph.y, t1y = x1 * ph.y + y1 * ph.x;
+        const double t2x = x2 * ph.x + y2 * ph.y, t2y = y2 * ph.x - x2 * ph.y;
+        const double sxv = t1x + t2x, syv = t1y + t2y, dxv = t1x - t2x, dyv = t1y - t2y;
+        const double a = (double)q * a_unit;
+        double pw = 1.0;
+#pragma unroll
+        for (int n = 0; n <= kOrder; ++n) {
+          R[n] = fma((n & 1) ? dxv : sxv, pw, R[n]);
+          I[n] = fma((n & 1) ? dyv : syv, pw, I[n]);
+          pw *= a;
+        }
+      }
+    };
+    load(b0, qa);
+    // a rolled loop: two batches live at a time (unrolled, the scheduler
+    // hoists every load and runs out of registers)
+#pragma unroll 1
+    for (int bi = 0; bi < NB; bi += 2) {
+      if (bi + 1 < NB) load(b1, qa + (bi + 1) * BQ);
+      sum(b0, qa + bi * BQ);
+      if (bi == 0) {
+        // the Nyquist row (second slot of pair 0, masked elsewhere; no branch),
+        // rotated by (-i)^n into the R + i I form
+        const bool nq = qa == 0 && qb > 0;
+        const double xn = nq ? (double)b0[1].x : 0.0, yn = nq ? (double)b0[1].y : 0.0;
+#pragma unroll
+        for (int n = 0; n <= kOrder; ++n) {
+          const double vx = xn * ry[n], vy = yn * ry[n];
+          switch (n & 3) {
+            case 0: R[n] += vx; I[n] += vy; break;
+            case 1: R[n] += vy; I[n] -= vx; break;
+            case 2: R[n] -= vx; I[n] -= vy; break;
+            default: R[n] -= vy; I[n] += vx; break;
+          }
+        }
+      }
+      if (bi + 1 < NB) {
+        if (bi + 2 < NB) load(b0, qa + (bi + 2) * BQ);
+        sum(b1, qa + (bi + 1) * BQ);
+      }
+    }
+  }
+  double2 M[kOrder + 1];
+#pragma unroll
+  for (int n = 0; n <= kOrder; ++n) {
+    const double r = group_sum<S>(R[n]), i = group_sum<S>(I[n]);
+    switch (n & 3) {  // M_n = i^n (R_n + i I_n)
+      case 0: M[n] = make_double2(r, i); break;
+      case 1: M[n] = make_double2(-i, r); break;
+      case 2: M[n] = make_double2(-r, -i); break;
+      default: M[n] = make_double2(i, -r); break;
+    }
+  }
+  // ---- this lane's share of the coefficients: m = seg + S q
   if (kx < NC) {
     const double b = 2.0 * pi * (double)kx / (double)NX;
     const double w = kx == 0 ? 1.0 : 2.0;
@@ -241,6 +320,7 @@ __device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy
 #pragma unroll
       for (int k = 0; k < S && k <= kOrder; ++k) P = make_double2(-b * P.y, b * P.x);
     }
+  }
   }
   // sum over the columns of each 16-lane row (lanes with the same seg); the
   // rows' partials (RP per wave) are added in the final sums
@@ -267,23 +347,28 @@ __device__ __forceinline__ void build_model(const CX* __restrict__ Xf, double sy
         for (int n = 0; n <= kOrder; ++n) red[wave * RP + lane / RW][m][n] = acc[q][n];
     }
   }
-  // ---- Nyquist column kx = NX/2: wave 0, one row per lane at a time
+  // ---- Nyquist column kx = NX/2: wave 0, one row pair per lane at a time
   double2 Mn[kOrder + 1];
 #pragma unroll
   for (int n = 0; n <= kOrder; ++n) Mn[n] = make_double2(0.0, 0.0);
-  for (int ky = ky_lo + (wave == 0 ? lane : ky_hi); ky < ky_hi; ky += 64) {
-    const CX xf = Xf[(size_t)ky * H + NC];
-    if (2 * ky == NY) {
+  for (int q = q_lo + (wave == 0 ? lane : q_hi); q < q_hi; q += 64) {
+    if (q == 0) {
+      const CX x0 = Xf[NC], xn = Xf[(size_t)NQ * H + NC];
+      Mn[0].x += (double)x0.x;
+      Mn[0].y += (double)x0.y;
 #pragma unroll
       for (int n = 0; n <= kOrder; ++n) {
-        Mn[n].x += (double)xf.x * ry[n];
-        Mn[n].y += (double)xf.y * ry[n];
+        Mn[n].x += (double)xn.x * ry[n];
+        Mn[n].y += (double)xn.y * ry[n];
       }
     } else {
-      const double2 ph = phy[ky];
-      add_powers(Mn, make_double2((double)xf.x * ph.x - (double)xf.y * ph.y,
-                                  (double)xf.x * ph.y + (double)xf.y * ph.x),
-                 ay[ky]);
+      const double2 ph = phy[q];
+      const double a = (double)q * a_unit;
+      const CX x1 = Xf[(size_t)q * H + NC], x2 = Xf[(size_t)(NY - q) * H + NC];
+      add_powers(Mn, make_double2((double)x1.x * ph.x - (double)x1.y * ph.y,
+                                  (double)x1.x * ph.y + (double)x1.y * ph.x), a);
+      add_powers(Mn, make_double2((double)x2.x * ph.x + (double)x2.y * ph.y,
+                                  (double)x2.y * ph.x - (double)x2.x * ph.y), -a);
     }
   }
   if (wave == 0) {  // (the other waves hold zeros)
@@ -354,14 +439,13 @@ __device__ void grid_seed(const GroupParams& g, const FrameState& st, int& py, i
 }
 
 // Small launches: block b of frame f builds the first model's share of the
-// spectrum rows b NY / nb <= ky < (b + 1) NY / nb around the grid estimate
+// row pairs b (NY/2) / nb <= q < (b + 1) (NY/2) / nb around the grid estimate
 // and stores its coefficients to parts[f][b]; the Newton kernel adds the
 // shares in block order.
 template <int NY, int NX, typename CX>
 __global__ void __launch_bounds__(kNThreads) k_newton_part(GroupParams g, double* __restrict__ parts,
                                                            int nb) {
-  __shared__ double2 phy[NY];
-  __shared__ double ay[NY];
+  __shared__ double2 phy[NY / 2];
   __shared__ double red[kNThreads / 16][kOrder + 1][kOrder + 1];
   __shared__ double nred[kNThreads / 64][2 * (kOrder + 1)];
   __shared__ double coef[kCoef];
@@ -373,15 +457,15 @@ __global__ void __launch_bounds__(kNThreads) k_newton_part(GroupParams g, double
   grid_seed<NY, NX>(g, st, py, px, dgy, dgx);
   const CX* Xf = (sizeof(CX) == sizeof(float2) ? (const CX*)g.X : (const CX*)g.X64) +
                  (size_t)f * NY * (NX / 2 + 1);
-  build_model<NY, NX, CX>(Xf, dgy, dgx, phy, ay, red, nred, coef, b * NY / nb, (b + 1) * NY / nb);
+  build_model<NY, NX, CX, ModelSplit<NY, NX>::SEGP>(Xf, dgy, dgx, phy, red, nred, coef, b * (NY / 2) / nb,
+                          (b + 1) * (NY / 2) / nb);
   if (tid < kCoef) parts[((size_t)f * nb + b) * kCoef + tid] = coef[tid];
 }
 
 template <int NY, int NX, typename CX>
-__global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step_limit,
+__global__ void __launch_bounds__(kNThreads, 3) k_newton(GroupParams g, double step_limit,
                                                       const double* __restrict__ parts, int nb) {
-  __shared__ double2 phy[NY];
-  __shared__ double ay[NY];
+  __shared__ double2 phy[NY / 2];
   __shared__ double red[kNThreads / 16][kOrder + 1][kOrder + 1];
   __shared__ double nred[kNThreads / 64][2 * (kOrder + 1)];
   __shared__ double coef[kCoef];
@@ -438,19 +522,11 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
   Deriv fin{0, 0, 0, 0, 0, 0};
   // iterations run in the first kMaxPasses model passes; one more pass may
   // re-centre the model on the final point (a window exit, or an iterate
-  // still moving when the passes ran out) for C and the Hessian there
-  for (int pass = 0; pass <= kMaxPasses; ++pass) {
-    if (pass == 0 && parts) {
-      // the first model from the blocks of k_newton_part, added in block order
-      if (tid < kCoef) {
-        double v = 0.0;
-        for (int b = 0; b < nb; ++b) v += parts[((size_t)f * nb + b) * kCoef + tid];
-        coef[tid] = v;
-      }
-      __syncthreads();
-    } else {
-      build_model<NY, NX, CX>(Xf, cy, cx, phy, ay, red, nred, coef);
-    }
+  // still moving when the passes ran out) for C and the Hessian there.
+  // After each pass thread 0 iterates on the model and says whether another
+  // pass is needed.  The first pass, which every frame runs, is outside the
+  // loop of re-centring passes, which few frames need.
+  auto iterate = [&](int pass) -> bool {
     if (tid == 0) {
       while (!done && it_left > 0) {
         const Deriv e = model_eval(coef, sy - cy, sx - cx);
@@ -498,7 +574,23 @@ __global__ void __launch_bounds__(kNThreads) k_newton(GroupParams g, double step
     cy = ctl[0];
     cx = ctl[1];
     __syncthreads();
-    if (!again) break;
+    return again;
+  };
+  if (parts) {
+    // the first model from the blocks of k_newton_part, added in block order
+    if (tid < kCoef) {
+      double v = 0.0;
+      for (int b = 0; b < nb; ++b) v += parts[((size_t)f * nb + b) * kCoef + tid];
+      coef[tid] = v;
+    }
+    __syncthreads();
+  } else {
+    build_model<NY, NX, CX>(Xf, cy, cx, phy, red, nred, coef);
+  }
+  bool again = iterate(0);
+  for (int pass = 1; again && pass <= kMaxPasses; ++pass) {
+    build_model<NY, NX, CX>(Xf, cy, cx, phy, red, nred, coef);
+    again = iterate(pass);
   }
   if (tid == 0) {
     // in the frame's own axes (a wide frame was processed transposed)
