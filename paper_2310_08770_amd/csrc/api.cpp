@@ -489,7 +489,7 @@ int run_group(ccpt_ctx* ctx, const CallMem& mem, int n, const FrameDesc* d_desc,
     g.out = out;
     carve(ctx, mem, n, chunk, slot, g);
     // the one-kernel correlation leaves the split for the matrix DFT to make
-    if (g.Xb && xcorr_fused(ny, nx, pairs)) g.Xb = nullptr;
+    if (g.Xb && xcorr_fused(ny, nx, pairs, g.count)) g.Xb = nullptr;
     if (g.Xb) g.Zc = nullptr;
     const size_t yb = split_partials_bytes(ctx, n, g.count);
     g.ypart = (yb && mem.ypart && yb <= mem.slot_ypart)

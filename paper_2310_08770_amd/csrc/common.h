@@ -219,9 +219,16 @@ int launch_spectrum(int ny, int nx, const void* data, int dtype, int pitch, long
 // the three passes of launch_xcorr (X, Xb, the frame states), no T.
 int launch_xcorr256(const GroupParams& g, hipStream_t s);
 
-// Whether frames of ny x nx take that one-kernel path (pairs_ok as in
-// GroupParams); launch_xcorr and the launch set-up agree through it.
-inline bool xcorr_fused(int ny, int nx, bool pairs_ok) { return ny == 256 && nx == 256 && pairs_ok; }
+// Whether a launch of `count` frames of ny x nx takes that one-kernel path
+// (pairs_ok as in GroupParams); launch_xcorr and the launch set-up agree
+// through it.  The kernel gives one frame to one CU, which pays only once
+// the launch has about as many frames as the chip has CUs; smaller launches
+// (the per-frame path) take the three passes, which spread a frame over
+// about fifty blocks.
+constexpr int kFusedMinFrames = 128;
+inline bool xcorr_fused(int ny, int nx, bool pairs_ok, int count) {
+  return ny == 256 && nx == 256 && pairs_ok && count >= kFusedMinFrames;
+}
 
 // FP64 mode: the same two calls with every FFT in FP64 (g.T64, g.X64,
 // g.cand; the integer peak is left as per-row-block candidates).

@@ -1,7 +1,9 @@
 """The one-kernel correlation stage of 256x256 frames (half spectrum in
 registers) against the FP64 oracle and against the three-pass path, which
 the library still takes for 256x256 frames whose pixel pairs cannot be read
-as one load (float64 pixels, odd pitch)."""
+as one load (float64 pixels, odd pitch) and for launches of fewer than 128
+frames (the one-kernel path gives one frame to one CU).  Every case here
+passes at least 128 frames so that the one-kernel path runs."""
 import sys
 
 import numpy as np
@@ -54,8 +56,8 @@ def check_oracle(res, frames, ref, u, prec, mode=O.MODE_CCU, eps=200.0, tol=1e-3
 @pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
 @pytest.mark.parametrize("mode", ["ccu", "ccsn"])
 def test_fused_256_matches_oracle_and_three_pass_path(prec, mode):
-    say(f"case: 256x256 fused correlation, {prec}, {mode}: 24 frames u16 vs f64 input and oracle")
-    w = S.config2(24)
+    say(f"case: 256x256 fused correlation, {prec}, {mode}: 128 frames u16 vs f64 input and oracle")
+    w = S.config2(128)
     fr = np.stack(w.frames)
     ref = w.refs[0].astype(np.float32)
     m = O.MODE_CCU if mode == "ccu" else O.MODE_CCSN
@@ -72,14 +74,14 @@ def test_fused_256_matches_oracle_and_three_pass_path(prec, mode):
 
 
 def test_fused_256_float32_input_and_odd_pitch_fallback():
-    say("case: 256x256 float32 frames (fused) and an odd-pitch view (three passes)")
-    w = S.config2(8)
+    say("case: 256x256 float32 frames (fused) and odd-pitch views (three passes), 128 frames")
+    w = S.config2(128)
     fr = np.stack(w.frames).astype(np.float32)
     ref = w.refs[0]
     a = track(fr, ref, 100)
-    big = torch.zeros((8, 256, 257), dtype=torch.float32, device=DEV)
+    big = torch.zeros((128, 256, 257), dtype=torch.float32, device=DEV)
     big[:, :, :256] = torch.from_numpy(fr).to(DEV)
-    views = [big[i, :, :256] for i in range(8)]  # pitch 257
+    views = [big[i, :, :256] for i in range(128)]  # pitch 257
     b = track(views, ref, 100)
     assert np.array_equal(a["p"], b["p"])
     assert np.max(np.abs(a["d"] - b["d"])) <= 1e-5
@@ -87,7 +89,7 @@ def test_fused_256_float32_input_and_odd_pitch_fallback():
 
 
 def test_fused_256_status_and_near_ties():
-    say("case: 256x256 flat, NaN, planted near tie and exact tie with a delta reference")
+    say("case: 256x256 flat, NaN, planted near tie and exact tie with a delta reference (128 frames)")
     n = 256
     E = np.zeros((n, n), np.float32)
     E[0, 0] = 1.0
@@ -101,7 +103,8 @@ def test_fused_256_status_and_near_ties():
     flat = np.full((n, n), 3.0)
     nan = base.copy()
     nan[5, 5] = np.nan
-    frames = np.stack([tie, far, exact, flat, nan]).astype(np.float32)
+    # (padded to 128 frames with copies of `far` so that the one-kernel path runs)
+    frames = np.stack([tie, far, exact, flat, nan] + [far] * 123).astype(np.float32)
     res = track(frames, E, 20)
     st = [int(x) for x in res["status"]]
     assert st[0] & O.NEAR_TIE and tuple(res["p"][0]) == (30, 40)
