@@ -419,7 +419,7 @@ def main():
     flops_launch = updft_flops_per_frame(N, M, args.precision) * frames_per_launch
     achieved = flops_launch / (per_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    kernel_tag = f"k_updft_{'f32' if args.precision == 'fp32' else 'bf16x2_wide'}<{N}>"
+    kernel_tag = f"k_updft_{'f32' if args.precision == 'fp32' else 'bf16x2_t256'}<{N}>"
     traffic_pf = measured_traffic(kernel_tag)
     roofline = {
         "kernel": kernel_tag,

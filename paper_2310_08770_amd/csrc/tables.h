@@ -102,6 +102,32 @@ inline HostTables build_tables(int ny, int nx, int u, int M, int c, int precisio
     float* W = (float*)t.wb.data();
     for (int mx = 0; mx < Mp; ++mx)
       for (int j = 0; j < Kb; ++j) W[(size_t)mx * Kb + j] = (float)w[(size_t)j * Mp + mx];
+  } else if (nx == 256) {
+    // Stage B operand of the 256-column split kernel (k_updft_bf16x2_t256), in
+    // the order of its k steps: wave w (kx tile 32 w .. 32 w + 31), k step s
+    // (s < 2: the real rows j = kx, s >= 2: the imaginary rows j = N/2 + kx,
+    // whose kx = 0 is the Nyquist row), lane l (grid column mx = 32 r + l mod
+    // 32 of column tile r, half h = l / 32) holds W[j][mx] for its eight k
+    // slots e = 0..7, kx = 32 w + (2 (s mod 2) + e / 4) 8 + 4 h + e mod 4:
+    // [2 (hi, lo)][Mp / 32][4][4][64][8] uint16
+    const int nr = Mp / 32;
+    const size_t plane = (size_t)nr * 4 * 4 * 64 * 8;
+    t.wb.resize(2 * plane * 2);
+    uint16_t* W = (uint16_t*)t.wb.data();
+    for (int r = 0; r < nr; ++r)
+      for (int wv = 0; wv < 4; ++wv)
+        for (int s4 = 0; s4 < 4; ++s4)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 8; ++e) {
+              const int mx = 32 * r + (l & 31), hh = l >> 5;
+              const int kx = 32 * wv + (2 * (s4 & 1) + (e >> 2)) * 8 + 4 * hh + (e & 3);
+              const int jj = s4 < 2 ? kx : nx / 2 + kx;
+              uint16_t hi, lo;
+              split_bf16(w[(size_t)jj * Mp + mx], hi, lo);
+              const size_t o = ((((size_t)r * 4 + wv) * 4 + s4) * 64 + l) * 8 + e;
+              W[o] = hi;
+              W[plane + o] = lo;
+            }
   } else {
     // Stage B operand, transposed W^T[mx][j] as bf16, hi plane then lo plane:
     // [2][Mp][Kb] uint16

@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
 }
 
 
-// Wide variant for rows of NX >= 256: one block per frame and group of up to MT
+// Wide variant for rows of NX > 256: one block per frame and group of up to MT
 // 32-row m-tiles, one wave per 32-column kx tile.  Each frame's split
 // spectrum is streamed once from memory straight into the B operands (each
 // fragment feeds 6 MT matrix instructions).  The A operands come from the
@@ -549,12 +549,7 @@ __global__ void __launch_bounds__(kUThreads) k_updft_bf16x2(GroupParams g, const
 // is read 2 times per frame instead of 2*MT); its three products accumulate
 // into one register tile per row half (separate ones per product left the
 // compiler shuffling accumulators beside the pending Stage A tiles).
-//
-// FROMX: the frame's spectrum comes as FP32 X (row-major) plus the packed
-// column Zc instead of the split copy Xb, and each chunk's B fragments are
-// split into bf16 hi/lo here, after the MFMAs of the chunk before (the same
-// words the split copy would hold).
-template <int NY, int NX, int MT, bool FROMX>
+template <int NY, int NX, int MT>
 __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
     k_updft_bf16x2_wide(GroupParams g, const unsigned* __restrict__ kfold,
                         const unsigned short* __restrict__ WbT, int Mp) {
@@ -683,51 +678,7 @@ __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
   };
 
   u32x4 bh[KC / 8], bl[KC / 8];
-  if constexpr (FROMX) {
-    static_assert(PIPE && xb_pitch(NY) == NY, "FP32 operands on the pipelined path only");
-    constexpr int H = NX / 2 + 1;
-    // column kxrow of X, or the packed column for kxrow = 0
-    const float2* Xc = kxrow == 0 ? g.Zc + (size_t)f * NY : g.X + (size_t)f * NY * H + kxrow;
-    const int xs = kxrow == 0 ? 1 : H;
-    float2 xr[KC / 8][4];  // the next chunk's values, split after this chunk's MFMAs
-    auto load_x = [&](int k0) {
-#pragma unroll
-      for (int s8 = 0; s8 < KC / 8; ++s8)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          xr[s8][e] = (BFULL || bvalid) ? Xc[(size_t)(k0 + s8 * 8 + 4 * h + e) * xs]
-                                        : make_float2(0.f, 0.f);
-    };
-    auto split_x = [&]() {
-#pragma unroll
-      for (int s8 = 0; s8 < KC / 8; ++s8)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          unsigned wh, wl;
-          split_pair(xr[s8][e], wh, wl);
-          bh[s8][e] = wh;
-          bl[s8][e] = wl;
-        }
-    };
-    load_x(0);
-    load_k(0);
-    split_x();
-    store_k(raw);
-    __syncthreads();
-    for (int c = 0; c < NCH; ++c) {
-      const bool more = c + 1 < NCH;
-      if (more) {
-        load_x((c + 1) * KC);
-        load_k((c + 1) * KC);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      mma_chunk(raw + (c & 1) * KW, bh, bl);
-      __builtin_amdgcn_sched_barrier(0);
-      if (more) store_k(raw + ((c + 1) & 1) * KW);
-      __syncthreads();
-      if (more) split_x();
-    }
-  } else if constexpr (PIPE) {
+  if constexpr (PIPE) {
     // software pipeline: chunk c + 1's operands are loaded while chunk c's
     // MFMAs run; K' chunks alternate between two LDS buffers
     u32x4 nh[KC / 8], nl[KC / 8];
@@ -901,6 +852,328 @@ __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
   }
 }
 
+// Variant for rows of NX = 256 (four 32-column kx tiles): the same Stage A as
+// k_updft_bf16x2_wide with the operands of every matrix instruction swapped,
+// so each wave holds Y^T of its kx tile: lane l has grid row m = l mod 32 of
+// each row tile and, across its registers, the kx values
+// (v / 4) 8 + 4 (l / 32) + v mod 4 of the tile.  That is the layout of a
+// Stage B A operand whose k index runs over the kx of the tile, so Stage B
+// takes Y from registers (split into bf16 hi/lo in place) against the W
+// table stored in the matching order (tables.h, the 256-column layout), with
+// no staging of Y in LDS.  Each wave contracts its own kx slice (its 32
+// columns of Yr and of Yi, four k steps) for every grid point, so the four
+// waves do equal work; per 32-column tile of the grid the four partial
+// grids meet in LDS and are added in wave order (a fixed order), and the
+// grid maximum is taken from the sums.
+//
+// FROMX: the frame's spectrum comes as FP32 X (row-major) plus the packed
+// column Zc instead of the split copy Xb, and each chunk's A fragments are
+// split into bf16 hi/lo here, after the matrix instructions of the chunk
+// before (the same words the split copy would hold).
+template <int NY, int MT, bool FROMX>
+__global__ void __launch_bounds__(256)
+    k_updft_bf16x2_t256(GroupParams g, const unsigned* __restrict__ kfold,
+                        const unsigned short* __restrict__ WP, int Mp) {
+  constexpr int NX = 256, NC = 128, NKT = 4, NTH = 256;
+  constexpr int P = xb_pitch(NY);
+  constexpr int KC = 32;
+  constexpr int KCS = KC + 4;
+  constexpr int ROWS = MT * 32;
+  constexpr int RX = NY / NX;  // kx phase index step in the NY table
+  constexpr int KW = 2 * ROWS * KCS;
+  constexpr int UST = ROWS + 4;  // floats per grid column of a kx slice's partial grid
+  constexpr int UW = 32 * UST;   // floats per kx slice's partial grid (one 32-column tile)
+  constexpr int RAWW = 2 * KW > NKT * UW ? 2 * KW : NKT * UW;
+  __shared__ __attribute__((aligned(16))) unsigned raw[RAWW];
+  __shared__ float2 twf[NY];
+  __shared__ unsigned long long red[NTH / 64];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kt = wave;  // kx tile
+  const int f = blockIdx.y;
+  const int m0 = blockIdx.x * ROWS;  // the folded table has rows up to a whole block
+  const FrameState st = g.st[f];
+  if (frame_skipped(st)) return;
+  int iy, ix;
+  peak_yx<NY, NX>(key_index(st.peak_key), g.trans, iy, ix);
+  const bool tr = transposed<NY, NX>(g.trans);
+  for (int i = tid; i < NY; i += NTH) twf[i] = cconj(g.tw[i]);
+
+  const size_t kplane = (size_t)kfold_rows(Mp) * P;
+  const unsigned* Kh = kfold + (size_t)iy * 2 * kplane;
+  const unsigned* Kl = Kh + kplane;
+  const unsigned* Xbh = g.Xb + (size_t)f * 2 * NC * P;
+  const unsigned* Xbl = Xbh + (size_t)NC * P;
+  const int h = lane >> 5, j = lane & 31;
+  const int kxrow = kt * 32 + j;
+
+  f32x16 accr[MT], acci[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) accr[t][v] = acci[t][v] = 0.f;
+  constexpr int NCH = P / KC;
+  constexpr int KCOPY = ROWS * (KC / 4);
+  constexpr int KQ = (KCOPY + NTH - 1) / NTH;
+
+  auto load_b = [&](int k0, u32x4* dh, u32x4* dl) {
+#pragma unroll
+    for (int s8 = 0; s8 < KC / 8; ++s8) {
+      const int col = k0 + s8 * 8 + 4 * h;
+      dh[s8] = *(const u32x4*)(Xbh + (size_t)kxrow * P + col);
+      dl[s8] = *(const u32x4*)(Xbl + (size_t)kxrow * P + col);
+    }
+  };
+  u32x4 kh[KQ], kl[KQ];
+  auto load_k = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int i = tid + q * NTH;
+      if (KCOPY % NTH == 0 || i < KCOPY) {
+        const int r = i / (KC / 4), c4 = i - r * (KC / 4);
+        const size_t src = (size_t)(m0 + r) * P + k0 + 4 * c4;
+        kh[q] = *(const u32x4*)(Kh + src);
+        kl[q] = *(const u32x4*)(Kl + src);
+      }
+    }
+  };
+  auto store_k = [&](unsigned* dh) {
+    unsigned* dl = dh + ROWS * KCS;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int i = tid + q * NTH;
+      if (KCOPY % NTH == 0 || i < KCOPY) {
+        const int r = i / (KC / 4), c4 = i - r * (KC / 4);
+        *(u32x4*)(dh + r * KCS + 4 * c4) = kh[q];
+        *(u32x4*)(dl + r * KCS + 4 * c4) = kl[q];
+      }
+    }
+  };
+  // Stage A products of one ky chunk, transposed: the spectrum fragment is the
+  // A operand (rows kx), the K' fragment the B operand (columns m)
+  auto mma_chunk = [&](const unsigned* ks_hi, const u32x4* bh, const u32x4* bl) {
+    const unsigned* ks_lo = ks_hi + ROWS * KCS;
+#pragma unroll
+    for (int s8 = 0; s8 < KC / 8; ++s8) {
+      const int col = s8 * 8 + 4 * h;
+      const bf16x8 bh_r = as_bf(neg_im(bh[s8])), bh_i = as_bf(swap_ri(bh[s8]));
+      const bf16x8 bl_r = as_bf(neg_im(bl[s8])), bl_i = as_bf(swap_ri(bl[s8]));
+      bf16x8 ah[MT], al[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        {
+          ah[t] = as_bf(*(const u32x4*)(ks_hi + (t * 32 + j) * KCS + col));
+          al[t] = as_bf(*(const u32x4*)(ks_lo + (t * 32 + j) * KCS + col));
+        }
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        {
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh_r, ah[t], accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh_i, ah[t], acci[t], 0, 0, 0);
+        }
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        {
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl_r, ah[t], accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl_i, ah[t], acci[t], 0, 0, 0);
+        }
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        {
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh_r, al[t], accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh_i, al[t], acci[t], 0, 0, 0);
+        }
+    }
+  };
+
+  u32x4 bh[KC / 8], bl[KC / 8];
+  if constexpr (FROMX) {
+    static_assert(xb_pitch(NY) == NY, "FP32 operands: rows of whole chunks");
+    constexpr int H = NX / 2 + 1;
+    const float2* Xc = kxrow == 0 ? g.Zc + (size_t)f * NY : g.X + (size_t)f * NY * H + kxrow;
+    const int xs = kxrow == 0 ? 1 : H;
+    float2 xr[KC / 8][4];
+    auto load_x = [&](int k0) {
+#pragma unroll
+      for (int s8 = 0; s8 < KC / 8; ++s8)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xr[s8][e] = Xc[(size_t)(k0 + s8 * 8 + 4 * h + e) * xs];
+    };
+    auto split_x = [&]() {
+#pragma unroll
+      for (int s8 = 0; s8 < KC / 8; ++s8)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          unsigned wh, wl;
+          split_pair(xr[s8][e], wh, wl);
+          bh[s8][e] = wh;
+          bl[s8][e] = wl;
+        }
+    };
+    load_x(0);
+    load_k(0);
+    split_x();
+    store_k(raw);
+    __syncthreads();
+    for (int c = 0; c < NCH; ++c) {
+      const bool more = c + 1 < NCH;
+      if (more) {
+        load_x((c + 1) * KC);
+        load_k((c + 1) * KC);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      mma_chunk(raw + (c & 1) * KW, bh, bl);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) store_k(raw + ((c + 1) & 1) * KW);
+      __syncthreads();
+      if (more) split_x();
+    }
+  } else {
+    u32x4 nh[KC / 8], nl[KC / 8];
+    load_b(0, bh, bl);
+    load_k(0);
+    store_k(raw);
+    __syncthreads();
+    for (int c = 0; c < NCH; ++c) {
+      const bool more = c + 1 < NCH;
+      if (more) {
+        load_b((c + 1) * KC, nh, nl);
+        load_k((c + 1) * KC);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      mma_chunk(raw + (c & 1) * KW, bh, bl);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) store_k(raw + ((c + 1) & 1) * KW);
+      __syncthreads();
+      if (more) {
+#pragma unroll
+        for (int s8 = 0; s8 < KC / 8; ++s8) {
+          bh[s8] = nh[s8];
+          bl[s8] = nl[s8];
+        }
+      }
+    }
+  }
+  // kx phase of the fold, per register (kx of register v); column 0 holds
+  // (Y[., 0], Y[., N/2]): phase 1, and the Nyquist output takes exp(i pi p_x)
+  const float nyq_sign = (ix & 1) ? -1.f : 1.f;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int kx = kt * 32 + (v >> 2) * 8 + 4 * h + (v & 3);
+    if (kx > 0) {
+      const float2 ph = twf[(kx * ix * RX) % NY];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const float yr = accr[t][v], yi = acci[t][v];
+        accr[t][v] = yr * ph.x - yi * ph.y;
+        acci[t][v] = yr * ph.y + yi * ph.x;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < MT; ++t) acci[t][v] *= nyq_sign;
+    }
+  }
+  // Y as bf16 hi/lo A operands: k step s < 2 takes Yr, s >= 2 Yi, registers
+  // 8 (s mod 2) .. 8 (s mod 2) + 7
+  u32x4 yh[MT][4], yl[MT][4];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int v = 8 * (s4 & 1) + 2 * q;
+        const f32x16& a = s4 < 2 ? accr[t] : acci[t];
+        unsigned wh, wl;
+        split2(a[v], a[v + 1], wh, wl);
+        yh[t][s4][q] = wh;
+        yl[t][s4][q] = wl;
+      }
+  // Stage B per 32-column tile r of the grid: this wave's partial over its kx
+  // slice, then the four partials added in wave order
+  const int nr = Mp / 32;
+  const size_t wplane = (size_t)nr * NKT * 4 * 64 * 8;
+  const unsigned short* WPl = WP + wplane;
+  u32x4 wh[4], wl[4], nwh[4], nwl[4];
+  auto load_w = [&](int r, u32x4* dh, u32x4* dl) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const size_t off = ((((size_t)r * NKT + kt) * 4 + s4) * 64 + lane) * 8;
+      dh[s4] = *(const u32x4*)(WP + off);
+      dl[s4] = *(const u32x4*)(WPl + off);
+    }
+  };
+  float* up = (float*)raw;
+  unsigned long long best = 0;
+  load_w(0, wh, wl);
+  for (int r = 0; r < nr; ++r) {
+    if (r + 1 < nr) load_w(r + 1, nwh, nwl);
+    f32x16 au[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) au[t][v] = 0.f;
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const bf16x8 w_h = as_bf(wh[s4]), w_l = as_bf(wl[s4]);
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        au[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(yh[t][s4]), w_h, au[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        au[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(yh[t][s4]), w_l, au[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        au[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(yl[t][s4]), w_h, au[t], 0, 0, 0);
+    }
+    __syncthreads();  // the last round's sums (or Stage A's chunks) are done with LDS
+    // this wave's partial grid, column-major: up[kt][mx][my] (mx = lane mod 32)
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+      {
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4)
+          *(f32x4*)(up + kt * UW + j * UST + t * 32 + v4 * 8 + 4 * h) =
+              f32x4{au[t][4 * v4], au[t][4 * v4 + 1], au[t][4 * v4 + 2], au[t][4 * v4 + 3]};
+      }
+    __syncthreads();
+    for (int i = tid; i < 32 * ROWS / 4; i += NTH) {
+      const int mxl = i / (ROWS / 4), my4 = i - mxl * (ROWS / 4);
+      const float* q = up + mxl * UST + 4 * my4;
+      f32x4 sum = *(const f32x4*)q;
+#pragma unroll
+      for (int w = 1; w < NKT; ++w) {
+        const f32x4 o = *(const f32x4*)(q + w * UW);
+        sum[0] += o[0];
+        sum[1] += o[1];
+        sum[2] += o[2];
+        sum[3] += o[3];
+      }
+      const int mx = r * 32 + mxl;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int my = m0 + 4 * my4 + e;
+        if (my < g.M && mx < g.M) {
+          const unsigned long long key = peak_key(sum[e], grid_index(my, mx, g.M, tr));
+          best = key > best ? key : best;
+        }
+      }
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      wh[s4] = nwh[s4];
+      wl[s4] = nwl[s4];
+    }
+  }
+  best = wmax64(best);
+  if (lane == 0) red[wave] = best;
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < NTH / 64; ++w) best = red[w] > best ? red[w] : best;
+    atomicMax(&g.st[f].grid_key, best);
+  }
+}
+
 // Folded split table for the wide kernel: K'_p[m, ky] = phi_ky(p + (m - c)/u)
 // for every integer peak row p of frames of N rows, as bf16 hi/lo words
 // (re | im << 16), [N][2][Mp][xb_pitch(N)], computed in FP64 with exactly
@@ -965,18 +1238,25 @@ static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
       constexpr int MT = kWideMT;
       constexpr int NW = (NX / 2 + 31) / 32;
       if (!t.kfold) return -1;
-      if constexpr (NY == 256 && NX == 256) {
-        if (!g.Xb) {  // the one-kernel correlation left X and its packed column
-          if (!g.Zc) return -1;
-          hipLaunchKernelGGL((k_updft_bf16x2_wide<NY, NX, MT, true>),
-                             dim3((mtiles + MT - 1) / MT, g.count), dim3(64 * NW), 0, s, g,
-                             (const unsigned*)t.kfold, (const unsigned short*)t.wb, t.Mp);
-          return hipGetLastError() == hipSuccess ? 0 : -1;
+      if constexpr (NX == 256) {
+        static_assert(NW == 4, "four kx tiles");
+        if constexpr (NY == 256) {
+          if (!g.Xb) {  // the one-kernel correlation left X and its packed column
+            if (!g.Zc) return -1;
+            hipLaunchKernelGGL((k_updft_bf16x2_t256<NY, MT, true>),
+                               dim3((mtiles + MT - 1) / MT, g.count), dim3(256), 0, s, g,
+                               (const unsigned*)t.kfold, (const unsigned short*)t.wb, t.Mp);
+            return hipGetLastError() == hipSuccess ? 0 : -1;
+          }
         }
+        hipLaunchKernelGGL((k_updft_bf16x2_t256<NY, MT, false>), dim3((mtiles + MT - 1) / MT, g.count),
+                           dim3(256), 0, s, g, (const unsigned*)t.kfold, (const unsigned short*)t.wb,
+                           t.Mp);
+      } else {
+        hipLaunchKernelGGL((k_updft_bf16x2_wide<NY, NX, MT>),
+                           dim3((mtiles + MT - 1) / MT, g.count), dim3(64 * NW), 0, s, g,
+                           (const unsigned*)t.kfold, (const unsigned short*)t.wb, t.Mp);
       }
-      hipLaunchKernelGGL((k_updft_bf16x2_wide<NY, NX, MT, false>), dim3((mtiles + MT - 1) / MT, g.count),
-                         dim3(64 * NW), 0, s, g, (const unsigned*)t.kfold,
-                         (const unsigned short*)t.wb, t.Mp);
     } else {
       hipLaunchKernelGGL((k_updft_bf16x2<NY, NX>), dim3(mtiles, g.count), dim3(kUThreads), 0, s,
                          g, (const float2*)t.ky, (const unsigned short*)t.wb, t.Mp);

@@ -258,10 +258,14 @@ def test_autotune_and_chunking_do_not_change_results():
         # from 8 ky slices), the same sums run in other orders
         for other in (outs[7], outs[32], outs[64], tuned):
             assert np.array_equal(other["p"], outs[256]["p"])
-            same = np.max(np.abs(other["d_grid"].astype(np.float64) - outs[256]["d_grid"]), axis=1) < 0.005
+            # grid points: at u = 100 the top two grid values of these frames lie
+            # within the split precision's rounding, so the two summation orders
+            # may pick neighbouring points; never farther
+            gd = np.max(np.abs(other["d_grid"].astype(np.float64) - outs[256]["d_grid"]), axis=1)
             err = np.max(np.abs(other["d"] - outs[256]["d"]))
-            say(f"  {prec}: max |dd| vs 256-frame launches = {err:.2e}, same grid point {same.mean():.3f}")
-            assert same.mean() >= 0.95
+            say(f"  {prec}: max |dd| vs 256-frame launches = {err:.2e}, same grid point "
+                f"{np.mean(gd < 0.005):.3f}")
+            assert gd.max() <= 0.01 + 1e-6
             assert err <= 1e-5
         tr.close()
 

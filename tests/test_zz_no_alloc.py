@@ -30,10 +30,11 @@ def _compare(a, b, u, label):
     assert np.array_equal(ra["status"], rb["status"]), label
     # (the static entry point's chunks are smaller, so 256x256 frames may take
     # the three-pass correlation where the other call took the one-kernel
-    # path: FP32 FFTs in another order, the grid maximum moved by rounding on
-    # a near tie at most)
-    same = np.max(np.abs(ra["d_grid"].astype(np.float64) - rb["d_grid"]), axis=1) < 0.5 / u
-    assert same.mean() >= 0.95, label
+    # path: FFTs and the DFT's fold in another order, the grid maximum moved
+    # to a neighbouring point by rounding on a near tie at most)
+    gd = np.max(np.abs(ra["d_grid"].astype(np.float64) - rb["d_grid"]), axis=1)
+    same = gd < 0.5 / u
+    assert gd.max() <= 1.0 / u + 1e-6, label
     err = np.max(np.abs(ra["d"] - rb["d"]))
     say(f"  {label}: {len(ra)} results, max |dd| {err:.2e} px, same grid point {same.mean():.3f}, "
         f"bit-identical {bool(torch.equal(a, b))}")
