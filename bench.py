@@ -195,25 +195,34 @@ def _sync_time(fn, reps, torch):
 
 def leg_uneven_rois(dev, torch, Tracker):
     """4096 ROIs of seven sizes (32..256) with their own references, one
-    batched FP32 call: the default chunking against the autotuned one."""
+    batched FP32 call: size groups one after another with the default plans,
+    the default (concurrent size groups, default plans), and the plans and
+    lane count chosen by the autotuner timing this mixed call."""
     from synth import frames as S
     w = S.config3(4096)
     refs = [torch.from_numpy(r.astype(np.float32)).to(dev) for r in w.refs]
     fr = [torch.from_numpy(np.ascontiguousarray(f)).to(dev) for f in w.frames]
     ids = [int(i) for i in w.ref_ids]
     out = {}
-    for tuned in (False, True):
+    ref_res = None
+    for name in ("serial_groups", "default", "autotuned"):
         tr = Tracker(upsample=w.u)
         tr.set_reference(refs)
         rois = tr.rois(fr, ids)
         res = torch.empty((len(fr), 72), dtype=torch.uint8, device=dev)
-        if tuned:
-            sizes = w.meta["sizes"]
-            for n in sorted(set(int(x) for x in sizes)):
-                tr.autotune(n, int((sizes == n).sum()))
+        if name == "serial_groups":
+            tr.lanes(1)
+        if name == "autotuned":
+            tr.autotune_batch(rois=rois)
         dt = _sync_time(lambda: tr.track(None, out=res, rois=rois), 10, torch)
-        out["autotuned" if tuned else "default"] = dict(rois_per_s=round(len(fr) / dt, 1),
-                                                        ms_per_call=round(dt * 1e3, 3))
+        out[name] = dict(rois_per_s=round(len(fr) / dt, 1), ms_per_call=round(dt * 1e3, 3),
+                         lanes=tr.lanes())
+        if name == "autotuned":
+            out[name]["plans"] = {int(n): tr.plan(int(n)) for n in sorted(set(int(x) for x in w.meta["sizes"]))}
+        if ref_res is None:
+            ref_res = res.clone()
+        else:
+            out[name]["bit_identical_to_serial"] = bool(torch.equal(res, ref_res))
         tr.close()
     return out
 

@@ -307,14 +307,56 @@ int ccpt_drift_filter(const double* r, int n, double a0, double rate_limit, doub
    chunk size trades that residency against the number of launches.
    ccpt_autotune times ccpt_track_batch on `batch` frames of size n x n (each
    frame is the context's reference of that size; timing does not depend on
-   content) for a range of chunk sizes and keeps the fastest for later calls
-   on this context.  Needs a reference of size n (CCPT_E_NOREF otherwise).
-   Allocates and synchronises the stream. */
+   content) over chunk sizes and the block plans of ccpt_plan, and keeps the
+   fastest for later calls on this context.  Needs a reference of size n
+   (CCPT_E_NOREF otherwise).  Allocates and synchronises the stream. */
 int ccpt_autotune(ccpt_ctx* ctx, int n, int batch, void* stream);
 
 /* Reads (set = 0) or sets (set != 0) the chunk size used for frames of size
    n x n; 0 restores the default.  Lets a caller persist tuning results. */
 int ccpt_schedule(ccpt_ctx* ctx, int n, int* chunk, int set);
+
+/* Launch plan of one frame shape (a10), any supported ny x nx (rectangles
+   included): the chunk size and the block plans the kernels choose between.
+   Tuning it changes how work is split over blocks and launches, never the
+   arithmetic of a launch of a given size. */
+typedef struct ccpt_plan {
+  int chunk;        /* frames per launch chunk; 0 = default */
+  int split_blocks; /* FP32 matrix DFT: launches of fewer than this many 32-row grid
+                       tiles split Stage A over 8 ky slices added in a fixed order
+                       (latency); -1 = default (128), 0 = never; at most 512 */
+  int fused_min;    /* 256 x 256 frames: launches of at least this many frames take
+                       the one-kernel correlation stage (one frame per CU), smaller
+                       ones the three passes; -1 = default (128) */
+} ccpt_plan;
+
+/* Reads the plan in force for ny x nx frames (defaults filled in), or sets
+   it (-1 fields and chunk 0 select the defaults).  CCPT_E_UNSUPPORTED for an
+   unsupported shape, CCPT_E_INVALID for out-of-range fields.  Setting drops
+   the context's captured graphs. */
+int ccpt_get_plan(ccpt_ctx* ctx, int ny, int nx, ccpt_plan* plan);
+int ccpt_set_plan(ccpt_ctx* ctx, int ny, int nx, const ccpt_plan* plan);
+
+/* Concurrent size groups (a10; Sec. III.A: frames tracked against fixed
+   references are independent): a ccpt_track_batch call with frames of
+   several shapes runs its size groups on up to `lanes` streams at once, the
+   caller's stream and context-owned ones (default priority) forked from it
+   and joined back into it by events, so the call stays stream-ordered and
+   graph-capturable; groups go to lanes largest estimated cost first, each
+   to the least-loaded lane, and each lane has its own workspace.  Results
+   do not depend on the lane count.  Reads (set = 0) or sets (set != 0) the
+   most lanes a call uses: 1 (groups one after another) .. 4; 0 = default (4).
+   Profiling contexts (CCPT_FLAG_PROFILE) use one lane. */
+int ccpt_lanes(ccpt_ctx* ctx, int* lanes, int set);
+
+/* Tunes the launch plans of every shape in `rois` and the lane count by
+   timing ccpt_track_batch on this very array (a mixed-size batch is tuned
+   as the mixed call it is): lanes 1..4, then each shape's chunk size and
+   block plans with the others fixed, then lanes again.  Arguments as in
+   ccpt_track_batch (validated the same way); allocates and synchronises the
+   stream; results of later calls are unchanged up to the summation orders
+   the plans select. */
+int ccpt_autotune_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, void* stream);
 
 /* With CCPT_FLAG_PROFILE: total GPU time (ms) and number of launches of
    each stage recorded since the last reset, summed over chunks and calls.

@@ -61,6 +61,10 @@ class Image(ctypes.Structure):
     _fields_ = [("data", c_void_p), ("ny", c_int), ("nx", c_int), ("pitch", c_int), ("dtype", c_int)]
 
 
+class Plan(ctypes.Structure):
+    _fields_ = [("chunk", c_int), ("split_blocks", c_int), ("fused_min", c_int)]
+
+
 class Roi(ctypes.Structure):
     _fields_ = [("data", c_void_p), ("ny", c_int), ("nx", c_int), ("pitch", c_int), ("dtype", c_int),
                 ("ref_id", c_int)]
@@ -109,6 +113,14 @@ def lib():
         L.ccpt_autotune.restype = c_int
         L.ccpt_schedule.argtypes = [c_void_p, c_int, POINTER(c_int), c_int]
         L.ccpt_schedule.restype = c_int
+        L.ccpt_get_plan.argtypes = [c_void_p, c_int, c_int, POINTER(Plan)]
+        L.ccpt_get_plan.restype = c_int
+        L.ccpt_set_plan.argtypes = [c_void_p, c_int, c_int, POINTER(Plan)]
+        L.ccpt_set_plan.restype = c_int
+        L.ccpt_lanes.argtypes = [c_void_p, POINTER(c_int), c_int]
+        L.ccpt_lanes.restype = c_int
+        L.ccpt_autotune_batch.argtypes = [c_void_p, POINTER(Roi), c_int, c_void_p]
+        L.ccpt_autotune_batch.restype = c_int
         L.ccpt_stage_times.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int), c_int, c_int]
         L.ccpt_stage_times.restype = c_int
         L.ccpt_status_string.argtypes = [c_int]
@@ -122,7 +134,8 @@ def lib():
 EXPORTS = ["ccpt_default_options", "ccpt_create", "ccpt_destroy", "ccpt_set_reference",
            "ccpt_track_batch", "ccpt_track_grad", "ccpt_fisher", "ccpt_autotune", "ccpt_schedule",
            "ccpt_stage_times", "ccpt_status_string", "ccpt_last_error", "ccpt_mean_aligned",
-           "ccpt_track_update", "ccpt_drift_filter", "ccpt_track_batch_static"]
+           "ccpt_track_update", "ccpt_drift_filter", "ccpt_track_batch_static", "ccpt_get_plan",
+           "ccpt_set_plan", "ccpt_lanes", "ccpt_autotune_batch"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -358,6 +371,33 @@ class Tracker:
     def set_chunk(self, n, chunk):
         c = c_int(int(chunk))
         self._check(lib().ccpt_schedule(self._h, int(n), ctypes.byref(c), 1))
+
+    def plan(self, ny, nx=None):
+        """Launch plan in force for ny x nx frames: dict(chunk, split_blocks, fused_min)."""
+        p = Plan()
+        self._check(lib().ccpt_get_plan(self._h, int(ny), int(ny if nx is None else nx), ctypes.byref(p)))
+        return dict(chunk=p.chunk, split_blocks=p.split_blocks, fused_min=p.fused_min)
+
+    def set_plan(self, ny, nx=None, chunk=0, split_blocks=-1, fused_min=-1):
+        """Sets the launch plan of ny x nx frames (0 / -1 fields: defaults)."""
+        p = Plan(int(chunk), int(split_blocks), int(fused_min))
+        self._check(lib().ccpt_set_plan(self._h, int(ny), int(ny if nx is None else nx), ctypes.byref(p)))
+
+    def lanes(self, set_to=None):
+        """Most concurrent size-group lanes a call uses (reads, or sets when set_to is given)."""
+        if set_to is not None:
+            c = c_int(int(set_to))
+            self._check(lib().ccpt_lanes(self._h, ctypes.byref(c), 1))
+        c = c_int(0)
+        self._check(lib().ccpt_lanes(self._h, ctypes.byref(c), 0))
+        return c.value
+
+    def autotune_batch(self, frames=None, ref_ids=None, rois=None, stream=None):
+        """Tunes lanes and every shape's launch plan by timing this batch itself."""
+        if rois is None:
+            rois = self.rois(frames, ref_ids)
+        arr, n = rois
+        self._check(lib().ccpt_autotune_batch(self._h, arr, n, c_void_p(_stream_handle(stream))))
 
 
 def drift_filter(r, a0, rate_limit=0.0, state=None):

@@ -73,9 +73,15 @@ struct Ref {
   float2* espec = nullptr;    // CC-SN: F[E], N x (N/2+1), for real-time updates
 };
 
+// Launch plan of one frame shape (ccpt_plan): chunk size and block plans.
 struct Schedule {
-  int chunk = 0;  // frames per launch chunk (0 = default)
+  int chunk = 0;          // frames per launch chunk (0 = default)
+  int split_blocks = -1;  // FP32: split Stage A below this many row tiles per launch (-1: default)
+  int fused_min = -1;     // 256x256: one-kernel correlation from this many frames (-1: default)
 };
+
+// Size groups of one call run concurrently on up to kMaxLanes streams.
+constexpr int kMaxLanes = 4;
 
 struct GraphKey {
   std::vector<int> sig;  // group sizes and counts
@@ -140,6 +146,13 @@ struct ccpt_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t fork_evt = nullptr, join_evt = nullptr;
   size_t slot_ws = 0, slot_st = 0, slot_ypart = 0;
+  // concurrent size groups: lane 0 is the caller's stream, lanes 1.. these
+  // context-owned streams (default priority), forked from and joined back
+  // into the caller's stream by events; each lane has its own workspace,
+  // frame states, split-K and Newton partials
+  hipStream_t lane_s[kMaxLanes - 1] = {};
+  hipEvent_t lane_evt[kMaxLanes - 1] = {};
+  int lanes = 0;  // most lanes a call uses (0: kMaxLanes)
   // real-time updates: scratch spectra T and F
   void* rt_buf = nullptr;
   size_t rt_cap = 0;
@@ -284,6 +297,18 @@ int chunk_for(const ccpt_ctx* ctx, int n) {
   return default_chunk(n, ctx->o.precision);
 }
 
+int split_blocks_for(const ccpt_ctx* ctx, int n) {
+  auto it = ctx->sched.find(n);
+  if (it != ctx->sched.end() && it->second.split_blocks >= 0) return it->second.split_blocks;
+  return kSplitMaxBlocks;
+}
+
+int fused_min_for(const ccpt_ctx* ctx, int n) {
+  auto it = ctx->sched.find(n);
+  if (it != ctx->sched.end() && it->second.fused_min >= 0) return it->second.fused_min;
+  return kFusedMinFrames;
+}
+
 // Device memory the launches of one call work in: the context's buffers
 // (ccpt_track_batch) or the library's static scratch (ccpt_track_batch_static).
 struct CallMem {
@@ -386,6 +411,7 @@ GroupParams base_params(ccpt_ctx* ctx, int n) {
   g.c = ctx->c;
   g.newton_iters = ctx->o.newton_iters;
   g.half_window = 0.5 * ctx->o.window;
+  g.fused_min = fused_min_for(ctx, n);
   return g;
 }
 
@@ -430,7 +456,7 @@ size_t split_partials_bytes(const ccpt_ctx* ctx, int n, int count) {
   auto it = ctx->tables.find(table_key(n));
   if (it == ctx->tables.end()) return 0;
   const int mtiles = it->second.Mp / 32;
-  if ((long)count * mtiles >= kSplitMaxBlocks) return 0;
+  if ((long)count * mtiles >= split_blocks_for(ctx, n)) return 0;
   return (size_t)count * mtiles * kSplitSlices * 32 * stage_b_k(code_nx(n)) * sizeof(float);
 }
 
@@ -489,7 +515,7 @@ int run_group(ccpt_ctx* ctx, const CallMem& mem, int n, const FrameDesc* d_desc,
     g.out = out;
     carve(ctx, mem, n, chunk, slot, g);
     // the one-kernel correlation leaves the split for the matrix DFT to make
-    if (g.Xb && xcorr_fused(ny, nx, pairs, g.count)) g.Xb = nullptr;
+    if (g.Xb && xcorr_fused(ny, nx, pairs, g.count, g.fused_min)) g.Xb = nullptr;
     if (g.Xb) g.Zc = nullptr;
     const size_t yb = split_partials_bytes(ctx, n, g.count);
     g.ypart = (yb && mem.ypart && yb <= mem.slot_ypart)
@@ -636,8 +662,9 @@ int ensure_state(ccpt_ctx* ctx, size_t count, hipStream_t s) {
     ctx->st_dirty = true;
   }
   if (!ctx->nparts) {
-    // one share per chunk slot
-    const size_t bytes = (size_t)2 * kNewtonSplitMax * kNewtonParts * kNewtonCoef * sizeof(double);
+    // one share per chunk slot (two) or lane (kMaxLanes)
+    const size_t bytes =
+        (size_t)kMaxLanes * kNewtonSplitMax * kNewtonParts * kNewtonCoef * sizeof(double);
     int rc = ensure_buf(ctx, ctx->nparts, ctx->nparts_cap, bytes);
     if (rc) return rc;
   }
@@ -647,6 +674,16 @@ int ensure_state(ccpt_ctx* ctx, size_t count, hipStream_t s) {
     ctx->st_dirty = false;
   }
   return CCPT_OK;
+}
+
+// The streams and events of lanes 1.. (default priority).
+int create_lanes(ccpt_ctx* ctx) {
+  static_assert(kMaxLanes >= 2, "the two chunk slots use two Newton partial shares");
+  for (int l = 0; l < kMaxLanes - 1; ++l)
+    if (hipStreamCreateWithFlags(&ctx->lane_s[l], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->lane_evt[l], hipEventDisableTiming) != hipSuccess)
+      return -1;
+  return 0;
 }
 
 }  // namespace
@@ -720,6 +757,7 @@ int ccpt_create(ccpt_ctx** out, int device, const ccpt_options* opts) {
       hipEventCreateWithFlags(&ctx->fork_evt, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->join_evt, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
+      create_lanes(ctx) != 0 ||
       hipEventCreateWithFlags(&ctx->small_evt, hipEventDisableTiming) != hipSuccess) {
     ccpt_destroy(ctx);
     return CCPT_E_HIP;
@@ -760,6 +798,10 @@ void ccpt_destroy(ccpt_ctx* ctx) {
   if (ctx->fork_evt) (void)hipEventDestroy(ctx->fork_evt);
   if (ctx->join_evt) (void)hipEventDestroy(ctx->join_evt);
   if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+  for (int l = 0; l < kMaxLanes - 1; ++l) {
+    if (ctx->lane_s[l]) (void)hipStreamDestroy(ctx->lane_s[l]);
+    if (ctx->lane_evt[l]) (void)hipEventDestroy(ctx->lane_evt[l]);
+  }
   if (ctx->small_evt) (void)hipEventDestroy(ctx->small_evt);
   if (ctx->gsmall) (void)hipFree(ctx->gsmall);
   if (ctx->acc_buf) (void)hipFree(ctx->acc_buf);
@@ -895,53 +937,103 @@ int ccpt_track_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* ou
   rc = plan_rois(ctx, rois, n, plan);
   if (rc) return rc;
   const std::vector<int>& sig = plan.sig;
-  // per-slot needs; two slots when some group has several chunks
-  size_t ws_need = 0;
+  const int ngroups = (int)sig.size() / 2;
+  // size groups on lanes: the most expensive first, each to the lane with the
+  // least work so far (work = the group's FFT and matrix-DFT flops); one lane
+  // when profiling (stage timing follows one stream)
+  const int want = ctx->lanes > 0 ? ctx->lanes : kMaxLanes;
+  const int nl = (ctx->o.flags & CCPT_FLAG_PROFILE) ? 1 : std::max(1, std::min(ngroups, want));
+  std::vector<int> lane_of(ngroups, 0);
+  if (nl > 1) {
+    std::vector<double> cost(ngroups), load(nl, 0.0);
+    std::vector<int> order(ngroups);
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const int nn = sig[2 * gi];
+      const double ny = code_ny(nn), nx = code_nx(nn), h = nx / 2 + 1, m = ctx->M;
+      cost[gi] = sig[2 * gi + 1] * (10.0 * ny * nx * std::log2(ny * nx) + 8.0 * m * ny * h + 4.0 * m * m * h);
+      order[gi] = gi;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int gi : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      lane_of[gi] = l;
+      load[l] += cost[gi];
+    }
+  }
+  // per-lane needs (one lane: per chunk slot, two slots when some group has
+  // several chunks and two-stream chunks are on)
+  std::vector<size_t> lws(nl, 0), lst(nl, 0), lyp(nl, 0);
   int nslots = 1;
-  for (size_t gi = 0; gi < sig.size(); gi += 2) {
-    const int nn = sig[gi], cnt = sig[gi + 1];
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const int nn = sig[2 * gi], cnt = sig[2 * gi + 1], l = lane_of[gi];
     const int chunk = std::min(cnt, chunk_for(ctx, nn));
-    ws_need = std::max(ws_need, frame_ws_bytes(nn, ctx->o.precision) * (size_t)chunk + 256);
-    if (cnt > chunk && use_slots(ctx)) nslots = 2;
+    lws[l] = std::max(lws[l], frame_ws_bytes(nn, ctx->o.precision) * (size_t)chunk + 256);
+    lst[l] = std::max(lst[l], (size_t)chunk);
+    lyp[l] = std::max(lyp[l], split_partials_bytes(ctx, nn, chunk));
+    lyp[l] = std::max(lyp[l], split_partials_bytes(ctx, nn, cnt % chunk));
+    if (nl == 1 && cnt > chunk && use_slots(ctx)) nslots = 2;
   }
-  ws_need = (ws_need + 255) / 256 * 256;
-  rc = ensure_ws(ctx, ws_need * nslots);
-  if (rc) return rc;
-  ctx->slot_ws = ws_need;
-  size_t st_need = 0;
-  for (size_t gi = 0; gi < sig.size(); gi += 2)
-    st_need = std::max(st_need, (size_t)std::min(sig[gi + 1], chunk_for(ctx, sig[gi])));
-  rc = ensure_state(ctx, st_need * nslots, s);
-  if (rc) return rc;
-  ctx->slot_st = st_need;
-  size_t ypart_need = 0;
-  for (size_t gi = 0; gi < sig.size(); gi += 2) {
-    const int nn = sig[gi], cnt = sig[gi + 1];
-    const int ch = std::min(cnt, chunk_for(ctx, nn));
-    ypart_need = std::max(ypart_need, split_partials_bytes(ctx, nn, ch));
-    ypart_need = std::max(ypart_need, split_partials_bytes(ctx, nn, cnt % ch));
+  std::vector<size_t> ows(nl + 1, 0), ost(nl + 1, 0), oyp(nl + 1, 0);
+  for (int l = 0; l < nl; ++l) {
+    lws[l] = (lws[l] + 255) / 256 * 256;
+    lyp[l] = (lyp[l] + 255) / 256 * 256;
+    ows[l + 1] = ows[l] + lws[l] * nslots;
+    ost[l + 1] = ost[l] + lst[l] * nslots;
+    oyp[l + 1] = oyp[l] + lyp[l] * nslots;
   }
-  ypart_need = (ypart_need + 255) / 256 * 256;
-  if (ypart_need * nslots > ctx->ypart_cap) {
+  rc = ensure_ws(ctx, ows[nl]);
+  if (rc) return rc;
+  ctx->slot_ws = lws[0];
+  rc = ensure_state(ctx, ost[nl], s);
+  if (rc) return rc;
+  ctx->slot_st = lst[0];
+  if (oyp[nl] > ctx->ypart_cap) {
     drop_graphs(ctx);
-    rc = ensure_buf(ctx, ctx->ypart, ctx->ypart_cap, ypart_need * nslots);
+    rc = ensure_buf(ctx, ctx->ypart, ctx->ypart_cap, oyp[nl]);
     if (rc) return rc;
   }
-  ctx->slot_ypart = ypart_need;
+  ctx->slot_ypart = lyp[0];
   rc = upload_desc(ctx, plan.desc, s);
   if (rc) return rc;
 
   auto launch_all = [&]() -> int {
-    int first = 0;
-    const CallMem mem = ctx_mem(ctx);
-    for (size_t gi = 0; gi < sig.size(); gi += 2) {
-      const int nn = sig[gi], cnt = sig[gi + 1];
-      int r2 = run_group(ctx, mem, nn, ctx->d_desc, first, cnt, out, s,
-                         pairs_ok(plan.desc, first, cnt));
-      if (r2) return r2;
-      first += cnt;
+    std::vector<int> first(ngroups, 0);
+    for (int gi = 1; gi < ngroups; ++gi) first[gi] = first[gi - 1] + sig[2 * gi - 1];
+    // lanes 1.. start after everything already queued on the caller's stream
+    if (nl > 1) {
+      HIP_CHECK(ctx, hipEventRecord(ctx->fork_evt, s));
+      for (int l = 1; l < nl; ++l) HIP_CHECK(ctx, hipStreamWaitEvent(ctx->lane_s[l - 1], ctx->fork_evt, 0));
     }
-    return CCPT_OK;
+    int r2 = CCPT_OK;
+    for (int l = 0; l < nl && r2 == CCPT_OK; ++l) {
+      CallMem mem = ctx_mem(ctx);
+      mem.ws = ctx->ws + ows[l];
+      mem.slot_ws = lws[l];
+      mem.st = ctx->st_buf + ost[l];
+      mem.slot_st = lst[l];
+      mem.ypart = ctx->ypart ? (char*)ctx->ypart + oyp[l] : nullptr;
+      mem.slot_ypart = lyp[l];
+      mem.nparts = ctx->nparts ? (double*)ctx->nparts +
+                                     (size_t)l * kNewtonSplitMax * kNewtonParts * kNewtonCoef
+                               : nullptr;
+      if (nl > 1) mem.slots = false;
+      hipStream_t ls = l ? ctx->lane_s[l - 1] : s;
+      for (int gi = 0; gi < ngroups && r2 == CCPT_OK; ++gi) {
+        if (lane_of[gi] != l) continue;
+        const int nn = sig[2 * gi], cnt = sig[2 * gi + 1];
+        r2 = run_group(ctx, mem, nn, ctx->d_desc, first[gi], cnt, out, ls,
+                       pairs_ok(plan.desc, first[gi], cnt));
+      }
+    }
+    // every lane that was forked joins back, also after a failed launch
+    for (int l = 1; l < nl; ++l) {
+      if (hipEventRecord(ctx->lane_evt[l - 1], ctx->lane_s[l - 1]) != hipSuccess ||
+          hipStreamWaitEvent(s, ctx->lane_evt[l - 1], 0) != hipSuccess) {
+        (void)hipStreamSynchronize(ctx->lane_s[l - 1]);
+        if (r2 == CCPT_OK) r2 = fail(ctx, CCPT_E_HIP, "joining lane %d failed", l);
+      }
+    }
+    return r2;
   };
 
   const bool use_graph = (ctx->o.flags & CCPT_FLAG_GRAPH) && !(ctx->o.flags & CCPT_FLAG_PROFILE) &&
@@ -1339,6 +1431,70 @@ int ccpt_stage_times(ccpt_ctx* ctx, double* ms, int* launches, int n_stages, int
   return CCPT_OK;
 }
 
+// Event-timed average of `reps` calls of ccpt_track_batch (one untimed call
+// first: allocations and graph captures); a negative value if a call failed.
+static float time_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, ccpt_result* out,
+                        void* stream, hipEvent_t e0, hipEvent_t e1, int reps) {
+  hipStream_t s = (hipStream_t)stream;
+  if (ccpt_track_batch(ctx, rois, n, out, stream) != CCPT_OK) return -1.f;
+  if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
+  for (int r = 0; r < reps; ++r)
+    if (ccpt_track_batch(ctx, rois, n, out, stream) != CCPT_OK) return -1.f;
+  float ms = 0.f;
+  if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+      hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+    return -1.f;
+  return ms / reps;
+}
+
+// Coordinate search over the launch plan of one shape code: chunk sizes, then
+// the block plans that apply to the shape (FP32 split-K threshold; for
+// 256x256 the one-kernel correlation threshold), then chunk sizes again if
+// a block plan changed; every candidate timed on the whole call.
+static void tune_shape(ccpt_ctx* ctx, int code, int count, const ccpt_roi* rois, int n,
+                       ccpt_result* out, void* stream, hipEvent_t e0, hipEvent_t e1,
+                       float& best_ms) {
+  Schedule& sc = ctx->sched[code];
+  auto trial = [&](Schedule cand) {
+    const Schedule keep = sc;
+    sc = cand;
+    drop_graphs(ctx);
+    const float ms = time_batch(ctx, rois, n, out, stream, e0, e1, 3);
+    if (ms >= 0.f && ms < best_ms) {
+      best_ms = ms;
+      return true;
+    }
+    sc = keep;
+    return false;
+  };
+  const int cands[] = {16, 32, 64, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 4096};
+  auto sweep_chunks = [&]() {
+    for (int c : cands) {
+      if (c > count && c != cands[0]) break;
+      if (frame_ws_bytes(code, ctx->o.precision) * (size_t)std::min(c, count) > ((size_t)8 << 30))
+        break;
+      Schedule cand = sc;
+      cand.chunk = c;
+      (void)trial(cand);
+    }
+  };
+  sweep_chunks();
+  bool changed = false;
+  if (ctx->o.precision == CCPT_PREC_FP32)
+    for (int sb : {0, kSplitMaxBlocks, 512}) {
+      Schedule cand = sc;
+      cand.split_blocks = sb;
+      changed |= trial(cand);
+    }
+  if (code_ny(code) == 256 && code_nx(code) == 256 && !fp64(ctx))
+    for (int fm : {1, kFusedMinFrames, 1 << 30}) {
+      Schedule cand = sc;
+      cand.fused_min = fm;
+      changed |= trial(cand);
+    }
+  if (changed) sweep_chunks();
+}
+
 int ccpt_autotune(ccpt_ctx* ctx, int n, int batch, void* stream) {
   if (!ctx) return CCPT_E_INVALID;
   if (batch < 1 || !supported_size(n)) return fail(ctx, CCPT_E_INVALID, "bad tuning shape");
@@ -1351,7 +1507,6 @@ int ccpt_autotune(ccpt_ctx* ctx, int n, int batch, void* stream) {
   if (rid < 0) return fail(ctx, CCPT_E_NOREF, "no reference of size %d to tune with", n);
   int rc = set_device(ctx);
   if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
   // every tuning frame is the reference image itself (timing does not depend on content)
   std::vector<ccpt_roi> rois(batch);
   for (auto& r : rois) r = ccpt_roi{ctx->refs[rid].img, n, n, n, CCPT_F32, rid};
@@ -1362,30 +1517,58 @@ int ccpt_autotune(ccpt_ctx* ctx, int n, int batch, void* stream) {
   HIP_CHECK(ctx, hipEventCreate(&e1));
   const int saved_flags = ctx->o.flags;
   ctx->o.flags = 0;  // no graphs or profiling while tuning
-  const int cands[] = {16, 32, 64, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 4096};
-  int best_chunk = default_chunk(n, ctx->o.precision);
-  float best_ms = 1e30f;
-  for (int c : cands) {
-    if (c > batch && c != cands[0]) break;
-    const size_t need = frame_ws_bytes(n, ctx->o.precision) * (size_t)std::min(c, batch) + 256;
-    if (need > ((size_t)8 << 30)) break;
-    ctx->sched[n].chunk = c;
-    float total = 0.f;
-    int good = 1;
-    for (int rep = 0; rep < 4 && good; ++rep) {
-      if (rep == 1) (void)hipEventRecord(e0, s);
-      if (ccpt_track_batch(ctx, rois.data(), batch, out, stream) != CCPT_OK) good = 0;
-    }
-    (void)hipEventRecord(e1, s);
-    if (!good || hipEventSynchronize(e1) != hipSuccess) continue;
-    (void)hipEventElapsedTime(&total, e0, e1);
-    if (total < best_ms) {
-      best_ms = total;
-      best_chunk = c;
-    }
-  }
-  ctx->sched[n].chunk = best_chunk;
+  ctx->sched[n] = Schedule{};
+  float best = 1e30f;
+  tune_shape(ctx, n, batch, rois.data(), batch, out, stream, e0, e1, best);
   ctx->o.flags = saved_flags;
+  drop_graphs(ctx);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  ctx->last_desc.clear();
+  return CCPT_OK;
+}
+
+int ccpt_autotune_batch(ccpt_ctx* ctx, const ccpt_roi* rois, int n, void* stream) {
+  if (!ctx) return CCPT_E_INVALID;
+  if (n < 1 || !rois) return fail(ctx, CCPT_E_INVALID, "bad roi array");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  Plan plan;
+  rc = plan_rois(ctx, rois, n, plan);  // validates every roi
+  if (rc) return rc;
+  ccpt_result* out = nullptr;
+  HIP_CHECK(ctx, hipMalloc(&out, (size_t)n * sizeof(ccpt_result)));
+  hipEvent_t e0, e1;
+  HIP_CHECK(ctx, hipEventCreate(&e0));
+  HIP_CHECK(ctx, hipEventCreate(&e1));
+  const int saved_flags = ctx->o.flags;
+  ctx->o.flags = 0;  // no graphs or profiling while tuning
+  const int ngroups = (int)plan.sig.size() / 2;
+  auto tune_lanes = [&](float& best) {
+    int best_l = ctx->lanes;
+    for (int l = 1; l <= std::min(ngroups, kMaxLanes); ++l) {
+      ctx->lanes = l;
+      drop_graphs(ctx);
+      const float ms = time_batch(ctx, rois, n, out, stream, e0, e1, 3);
+      if (ms >= 0.f && ms < best) {
+        best = ms;
+        best_l = l;
+      }
+    }
+    ctx->lanes = best_l;
+  };
+  float best = 1e30f;
+  for (int gi = 0; gi < ngroups; ++gi) ctx->sched[plan.sig[2 * gi]] = Schedule{};
+  ctx->lanes = 0;
+  tune_lanes(best);
+  // the shapes in the call's order (largest frames first), each plan timed on
+  // the whole call with the others' plans fixed
+  for (int gi = 0; gi < ngroups; ++gi)
+    tune_shape(ctx, plan.sig[2 * gi], plan.sig[2 * gi + 1], rois, n, out, stream, e0, e1, best);
+  tune_lanes(best);
+  ctx->o.flags = saved_flags;
+  drop_graphs(ctx);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(out);
@@ -1399,8 +1582,46 @@ int ccpt_schedule(ccpt_ctx* ctx, int n, int* chunk, int set) {
   if (set) {
     if (*chunk < 0 || *chunk > (1 << 20)) return fail(ctx, CCPT_E_INVALID, "chunk %d", *chunk);
     ctx->sched[n].chunk = *chunk;
+    drop_graphs(ctx);
   } else {
     *chunk = chunk_for(ctx, n);
+  }
+  return CCPT_OK;
+}
+
+int ccpt_get_plan(ccpt_ctx* ctx, int ny, int nx, ccpt_plan* p) {
+  if (!ctx || !p) return CCPT_E_INVALID;
+  const int code = shape_code(ny, nx);
+  if (!code) return fail(ctx, CCPT_E_UNSUPPORTED, "shape %dx%d", ny, nx);
+  p->chunk = chunk_for(ctx, code);
+  p->split_blocks = split_blocks_for(ctx, code);
+  p->fused_min = fused_min_for(ctx, code);
+  return CCPT_OK;
+}
+
+int ccpt_set_plan(ccpt_ctx* ctx, int ny, int nx, const ccpt_plan* p) {
+  if (!ctx || !p) return CCPT_E_INVALID;
+  const int code = shape_code(ny, nx);
+  if (!code) return fail(ctx, CCPT_E_UNSUPPORTED, "shape %dx%d", ny, nx);
+  if (p->chunk < 0 || p->chunk > (1 << 20) || p->split_blocks < -1 || p->split_blocks > 512 ||
+      p->fused_min < -1)
+    return fail(ctx, CCPT_E_INVALID, "plan {%d, %d, %d}", p->chunk, p->split_blocks, p->fused_min);
+  Schedule& sc = ctx->sched[code];
+  sc.chunk = p->chunk;
+  sc.split_blocks = p->split_blocks;
+  sc.fused_min = p->fused_min;
+  drop_graphs(ctx);
+  return CCPT_OK;
+}
+
+int ccpt_lanes(ccpt_ctx* ctx, int* lanes, int set) {
+  if (!ctx || !lanes) return CCPT_E_INVALID;
+  if (set) {
+    if (*lanes < 0 || *lanes > kMaxLanes) return fail(ctx, CCPT_E_INVALID, "lanes %d", *lanes);
+    ctx->lanes = *lanes;
+    drop_graphs(ctx);
+  } else {
+    *lanes = ctx->lanes > 0 ? ctx->lanes : kMaxLanes;
   }
   return CCPT_OK;
 }

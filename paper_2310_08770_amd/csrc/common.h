@@ -89,6 +89,8 @@ struct GroupParams {
                           // shape); integer-peak and grid indices keep the frame's
                           // own row-major order and the Newton stage writes the
                           // result in the frame's own axes
+  int fused_min;          // 256x256: launches of at least this many frames take the
+                          // one-kernel correlation (launch plan)
 };
 
 // Frame shapes of the kernels: square N x N for N in CCPT_FOR_SIZES, and the
@@ -107,8 +109,10 @@ constexpr int kNewtonSplitMax = 64;
 constexpr int kNewtonParts = 8;
 constexpr int kNewtonCoef = 36;  // Taylor coefficients of the degree-7 model
 
-// Small FP32 launches (fewer than kSplitMaxBlocks row tiles in all) split the
-// Stage A contraction over kSplitSlices ky slices for latency.
+// Small FP32 launches (fewer than kSplitMaxBlocks row tiles in all, the
+// default of the launch plan) split the Stage A contraction over kSplitSlices
+// ky slices for latency; the split happens where the launch set-up hands the
+// kernels a partials buffer (GroupParams::ypart).
 constexpr int kSplitMaxBlocks = 128;
 constexpr int kSplitSlices = 8;
 
@@ -220,14 +224,15 @@ int launch_spectrum(int ny, int nx, const void* data, int dtype, int pitch, long
 int launch_xcorr256(const GroupParams& g, hipStream_t s);
 
 // Whether a launch of `count` frames of ny x nx takes that one-kernel path
-// (pairs_ok as in GroupParams); launch_xcorr and the launch set-up agree
-// through it.  The kernel gives one frame to one CU, which pays only once
-// the launch has about as many frames as the chip has CUs; smaller launches
-// (the per-frame path) take the three passes, which spread a frame over
-// about fifty blocks.
+// (pairs_ok as in GroupParams; fused_min from the launch plan);
+// launch_xcorr and the launch set-up agree through it.  The kernel gives one
+// frame to one CU, which pays only once the launch has about as many frames
+// as the chip has CUs; smaller launches (the per-frame path) take the three
+// passes, which spread a frame over about fifty blocks.  kFusedMinFrames is
+// the default threshold.
 constexpr int kFusedMinFrames = 128;
-inline bool xcorr_fused(int ny, int nx, bool pairs_ok, int count) {
-  return ny == 256 && nx == 256 && pairs_ok && count >= kFusedMinFrames;
+inline bool xcorr_fused(int ny, int nx, bool pairs_ok, int count, int fused_min) {
+  return ny == 256 && nx == 256 && pairs_ok && count >= fused_min;
 }
 
 // FP64 mode: the same two calls with every FFT in FP64 (g.T64, g.X64,

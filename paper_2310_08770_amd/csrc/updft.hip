@@ -1223,7 +1223,7 @@ static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
   if (t.precision == CCPT_PREC_FP32) {
     constexpr int NCH = NY / a_chunk(NY, NX);
     const int nsl = NCH < kSplitSlices ? NCH : kSplitSlices;
-    if (g.ypart && g.count * mtiles < kSplitMaxBlocks && nsl > 1) {
+    if (g.ypart && nsl > 1) {  // (the plan decided the split: a partials buffer)
       hipLaunchKernelGGL((k_updft_f32<NY, NX, true>), dim3(mtiles, g.count, nsl), dim3(kUThreads),
                          0, s, g, (const float2*)t.ky, (const float*)t.wb, t.Mp, g.ypart, nsl);
       hipLaunchKernelGGL((k_updft_f32_sum<NY, NX>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,

@@ -605,7 +605,7 @@ static int inverse_n(const float2* spec, int n, float scale, float2* T, float* i
 }
 
 int launch_xcorr(int ny, int nx, const GroupParams& g, hipStream_t s, const Marker& mark) {
-  if (xcorr_fused(ny, nx, g.pairs_ok != 0, g.count)) {
+  if (xcorr_fused(ny, nx, g.pairs_ok != 0, g.count, g.fused_min)) {
     mark(CCPT_STAGE_XCORR, 1);
     const int rc = launch_xcorr256(g, s);
     mark(CCPT_STAGE_XCORR, 0);
