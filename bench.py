@@ -351,6 +351,9 @@ def main():
                     help="skip the two-stream leg and the other workloads (mixed ROIs, 512x512 u=200, "
                          "128x128 gradients, Table I, Fig. 1)")
     ap.add_argument("--no-tune", action="store_true", help="skip the chunk autotuner")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="frames per launch chunk instead of the autotuner's choice (a profiled "
+                         "run pins the chunk the timed runs use)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -400,8 +403,11 @@ def main():
     # ---- batched, headline precision: the timed steps (no per-kernel events)
     tr = Tracker(upsample=w.u, precision=args.precision)
     tr.set_reference(ref_t)
-    chunk = tr.chunk(N) if args.no_tune else tr.autotune(N, n)
-    log(f"[bench] chunk {chunk} frames per launch ({'default' if args.no_tune else 'autotuned'})")
+    if args.chunk > 0:
+        tr.set_chunk(N, args.chunk)
+    chunk = tr.chunk(N) if (args.no_tune or args.chunk > 0) else tr.autotune(N, n)
+    how = "pinned" if args.chunk > 0 else ("default" if args.no_tune else "autotuned")
+    log(f"[bench] chunk {chunk} frames per launch ({how})")
     rois = tr.rois(frames_t)
     out = torch.empty((n, 72), dtype=torch.uint8, device=dev)
     total, lat = time_batched(tr, frames_t, rois, out, args.steps, args.warmup, torch)
@@ -450,7 +456,7 @@ def main():
     try:
         tr2 = Tracker(upsample=w.u, precision=other)
         tr2.set_reference(ref_t)
-        if not args.no_tune:
+        if not args.no_tune and args.chunk == 0:
             tr2.autotune(N, n)
         out2 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
         tot2, lat2 = time_batched(tr2, frames_t, tr2.rois(frames_t), out2, max(3, args.steps // 3), 2, torch)
