@@ -281,9 +281,11 @@ int ccpt_mean_aligned(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_res
    CCPT_ST_NONFINITE or CCPT_ST_FLAT leaves the reference unchanged.  E is
    the mean image in both modes; CC-SN recomputes B = -1/(E + eps) from the
    updated E (frames with values >= 0 keep E + eps > 0 for eps > 0).
-   roi: one frame (host struct, device data); out: one result (device).
-   Stream-ordered with no host synchronisation, so calls can follow each
-   other at the frame rate.  CCPT_E_UNSUPPORTED in FP64 precision. */
+   roi: one frame (host struct, device data) of any supported shape,
+   Table I's rectangles included (the paper's own real-time run is 256 x 128
+   at u = 256, Sec. IV.A); out: one result (device).  Stream-ordered with no
+   host synchronisation, so calls can follow each other at the frame rate.
+   CCPT_E_UNSUPPORTED in FP64 precision. */
 int ccpt_track_update(ccpt_ctx* ctx, const ccpt_roi* roi, double a0, ccpt_result* out,
                       void* stream);
 

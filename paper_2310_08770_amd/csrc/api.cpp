@@ -893,15 +893,17 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
       (void)hipFree(tmp);
       return fail(ctx, CCPT_E_HIP, "reference spectrum launch failed");
     }
-    if (ctx->o.mode == CCPT_MODE_CCSN && !is_rect(code)) {
-      // F[E] itself, the state of real-time updates (B = -1/(E+eps) is not linear in E)
+    if (ctx->o.mode == CCPT_MODE_CCSN) {
+      // F[E] itself (held tall), the state of real-time updates (B = -1/(E+eps)
+      // is not linear in E)
       Ref& rr = ctx->refs.back();
-      if (hipMalloc(&rr.espec, spec_elems(n) * sizeof(float2)) != hipSuccess) {
+      if (hipMalloc(&rr.espec, spec_elems(code) * sizeof(float2)) != hipSuccess) {
         (void)hipFree(tmp);
         return fail(ctx, CCPT_E_NOMEM, "reference spectra");
       }
       HIP_CHECK(ctx, hipStreamSynchronize(s));
-      if (launch_spectrum(n, n, r.img, CCPT_F32, n, 0, 0, 1, 0, 0.f, 0, T, rr.espec, st.tw, s)) {
+      if (launch_spectrum(code_ny(code), code_nx(code), r.img, CCPT_F32, refs[i].nx, 0,
+                          code_trans(code), 1, 0, 0.f, 0, T, rr.espec, st.tw, s)) {
         (void)hipFree(tmp);
         return fail(ctx, CCPT_E_HIP, "reference spectrum launch failed");
       }
@@ -1210,11 +1212,11 @@ int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_resul
       float2* QB = QA + spec * chunk;
       float* img = (float*)(QB + spec * chunk);
       const int f0 = first + c0;
-      if (launch_frame_spectra(nn, ctx->d_desc, f0, count, mode, eps, T, FA, tw, s) ||
+      if (launch_frame_spectra(nn, nn, 0, ctx->d_desc, f0, count, mode, eps, T, FA, tw, s) ||
           launch_grad_psi(nn, ctx->d_desc, f0, count, fwd, g_d, g_peak, FA, QA,
                           g_ref ? QB : nullptr, s))
         return fail(ctx, CCPT_E_HIP, "gradient launch failed");
-      if (g_frames && (launch_inverse(nn, QA, count, 2.0f, T, img, tw, s) ||
+      if (g_frames && (launch_inverse(nn, nn, QA, count, 2.0f, T, img, tw, s) ||
                        launch_grad_frames(nn, ctx->d_desc, f0, count, img, d_goff, g_frames, mode,
                                           eps, s)))
         return fail(ctx, CCPT_E_HIP, "frame gradient launch failed");
@@ -1228,7 +1230,7 @@ int ccpt_track_grad(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_resul
       const int nn = ctx->refs[r].n;
       float2* T = (float2*)ctx->ws;
       float* img = (float*)(T + spec_elems(nn));
-      if (launch_inverse(nn, (float2*)ctx->acc_buf + aoff[r], 1, 2.0f, T, img, ctx->tables[nn].tw,
+      if (launch_inverse(nn, nn, (float2*)ctx->acc_buf + aoff[r], 1, 2.0f, T, img, ctx->tables[nn].tw,
                          s) ||
           launch_grad_ref_chain(img, ctx->refs[r].img, nn * nn, mode, eps, g_ref + roff[r], s))
         return fail(ctx, CCPT_E_HIP, "reference gradient launch failed");
@@ -1277,8 +1279,8 @@ int ccpt_fisher(ccpt_ctx* ctx, const ccpt_image* mu, double* fisher, void* strea
   const float2* tw = ctx->tables[n].tw;
   int bad = launch_spectrum(n, n, mu->data, mu->dtype, mu->pitch, 0, 0, 1, 0, 0.f, 0, T, F, tw,
                             s) ||
-            launch_fisher_deriv(n, F, Dy, Dx, s) || launch_inverse(n, Dy, 1, 2.0f, T, iy, tw, s) ||
-            launch_inverse(n, Dx, 1, 2.0f, T, ix, tw, s) ||
+            launch_fisher_deriv(n, F, Dy, Dx, s) || launch_inverse(n, n, Dy, 1, 2.0f, T, iy, tw, s) ||
+            launch_inverse(n, n, Dx, 1, 2.0f, T, ix, tw, s) ||
             launch_fisher_reduce(iy, ix, mu->data, mu->dtype, mu->pitch, n, part, nblocks, fisher, s);
   hipError_t e = hipStreamSynchronize(s);
   (void)hipFree(tmp);
@@ -1322,12 +1324,12 @@ int ccpt_mean_aligned(ccpt_ctx* ctx, const ccpt_roi* rois, int n, const ccpt_res
   if (launch_zero(acc, head, s)) return fail(ctx, CCPT_E_HIP, "zero launch failed");
   for (int c0 = 0; c0 < n; c0 += chunk) {
     const int count = std::min(chunk, n - c0);
-    if (launch_frame_spectra(N, ctx->d_desc, c0, count, CCPT_MODE_CCU, 0.f, T, F, tw, s) ||
+    if (launch_frame_spectra(N, N, 0, ctx->d_desc, c0, count, CCPT_MODE_CCU, 0.f, T, F, tw, s) ||
         launch_align_accumulate(N, ctx->d_desc, c0, count, fwd, F, acc, cnt, s))
       return fail(ctx, CCPT_E_HIP, "alignment launch failed");
   }
   // the row pass of the inverse returns half the unnormalised transform
-  if (launch_inverse(N, acc, 1, 2.0f / ((float)N * (float)N), T, out, tw, s) ||
+  if (launch_inverse(N, N, acc, 1, 2.0f / ((float)N * (float)N), T, out, tw, s) ||
       launch_scale_by_count(out, N * N, 1.0f, cnt, s))
     return fail(ctx, CCPT_E_HIP, "inverse launch failed");
   return CCPT_OK;
@@ -1339,31 +1341,35 @@ int ccpt_track_update(ccpt_ctx* ctx, const ccpt_roi* roi, double a0, ccpt_result
   if (!roi || !out || !(a0 >= 0.0 && a0 <= 1.0))
     return fail(ctx, CCPT_E_INVALID, "bad arguments");
   if (fp64(ctx)) return fail(ctx, CCPT_E_UNSUPPORTED, "real-time updates need FP32 or BF16X2 precision");
-  int rc = require_square(ctx, roi->ny, roi->nx, "ccpt_track_update");
-  if (rc) return rc;
-  rc = ccpt_track_batch(ctx, roi, 1, out, stream);  // validates roi and reference id
+  int rc = ccpt_track_batch(ctx, roi, 1, out, stream);  // validates roi and reference id
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   Ref& R = ctx->refs[roi->ref_id];
-  const int N = R.n;
-  const size_t spec = spec_elems(N);
-  rc = ensure_buf(ctx, ctx->rt_buf, ctx->rt_cap, 2 * spec * sizeof(float2));
+  const int code = R.n;
+  const int ny = code_ny(code), nx = code_nx(code), tr = code_trans(code);
+  const size_t spec = spec_elems(code);
+  // scratch: two spectra, and for a rectangle in CC-SN the updated E in the
+  // tall layout (the context's copy of a rectangle's E is read by nothing:
+  // the adjoint takes square frames only)
+  const size_t img_bytes = is_rect(code) ? (size_t)ny * nx * sizeof(float) : 0;
+  rc = ensure_buf(ctx, ctx->rt_buf, ctx->rt_cap, 2 * spec * sizeof(float2) + img_bytes);
   if (rc) return rc;
   float2* T = (float2*)ctx->rt_buf;
   float2* F = T + spec;
-  const float2* tw = ctx->tables[N].tw;
+  float* img = is_rect(code) ? (float*)(F + spec) : R.img;
+  const float2* tw = ctx->tables[table_key(code)].tw;
   const float fa0 = (float)a0, fb1 = (float)(1.0 - a0);
   // the frame's own spectrum F[I] (track_batch left its descriptor at index 0)
-  if (launch_frame_spectra(N, ctx->d_desc, 0, 1, CCPT_MODE_CCU, 0.f, T, F, tw, s))
+  if (launch_frame_spectra(ny, nx, tr, ctx->d_desc, 0, 1, CCPT_MODE_CCU, 0.f, T, F, tw, s))
     return fail(ctx, CCPT_E_HIP, "frame spectrum launch failed");
   if (ctx->o.mode == CCPT_MODE_CCU) {
-    if (launch_rt_update(N, out, F, R.spec, fa0, fb1, 1, s))
+    if (launch_rt_update(ny, nx, tr, out, F, R.spec, fa0, fb1, 1, s))
       return fail(ctx, CCPT_E_HIP, "reference update launch failed");
   } else {
-    // update F[E], then E, then conj F[-1/(E+eps)]
-    if (launch_rt_update(N, out, F, R.espec, fa0, fb1, 0, s) ||
-        launch_inverse(N, R.espec, 1, 2.0f / ((float)N * (float)N), T, R.img, tw, s) ||
-        launch_spectrum(N, N, R.img, CCPT_F32, N, 0, 0, 1, 1, (float)ctx->o.eps, 1, T, R.spec, tw,
+    // update F[E], then E (tall layout), then conj F[-1/(E+eps)]
+    if (launch_rt_update(ny, nx, tr, out, F, R.espec, fa0, fb1, 0, s) ||
+        launch_inverse(ny, nx, R.espec, 1, 2.0f / ((float)ny * (float)nx), T, img, tw, s) ||
+        launch_spectrum(ny, nx, img, CCPT_F32, nx, 0, 0, 1, 1, (float)ctx->o.eps, 1, T, R.spec, tw,
                         s))
       return fail(ctx, CCPT_E_HIP, "reference update launch failed");
   }

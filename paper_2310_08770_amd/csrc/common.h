@@ -276,15 +276,18 @@ int launch_updft64(int N, const GroupParams& g, const double2* K, const double2*
 // set, else from g.X).
 int launch_newton(int ny, int nx, const GroupParams& g, double step_limit, hipStream_t s);
 
-// Inverse 2-D c2r of n half spectra [n][N][N/2+1] into n N x N float images
-// scaled by `scale` (T is scratch of the same size as the spectra).
-int launch_inverse(int N, const float2* spec, int n, float scale, float2* T, float* img,
+// Inverse 2-D c2r of n half spectra [n][ny][nx/2+1] into n float images of
+// ny rows of nx (the tall layout of a rectangle) scaled by `scale` (T is
+// scratch of the same size as the spectra).
+int launch_inverse(int ny, int nx, const float2* spec, int n, float scale, float2* T, float* img,
                    const float2* tw, hipStream_t s);
 
 // Forward 2-D r2c spectra (with the frame prologue of `mode`) of the frames of
-// a descriptor chunk into spec [count][N][N/2+1].
-int launch_frame_spectra(int N, const FrameDesc* desc, int first, int count, int mode, float eps,
-                         float2* T, float2* spec, const float2* tw, hipStream_t s);
+// a descriptor chunk into spec [count][ny][nx/2+1], held tall (trans: wide
+// frames read transposed).
+int launch_frame_spectra(int ny, int nx, int trans, const FrameDesc* desc, int first, int count,
+                         int mode, float eps, float2* T, float2* spec, const float2* tw,
+                         hipStream_t s);
 
 // Adjoint pieces (grad.hip).
 int launch_grad_psi(int N, const FrameDesc* desc, int first, int count, const ccpt_result* fwd,
@@ -308,9 +311,11 @@ int launch_align_accumulate(int N, const FrameDesc* desc, int first, int count,
                             const ccpt_result* fwd, float2* F, float2* acc, unsigned* cnt,
                             hipStream_t s);
 // Real-time reference update of Eq. 9 by one frame (spectrum F, result res):
-// S <- a0 v + b1 S with v the frame shifted back (conjugated when conj_s).
-int launch_rt_update(int N, const ccpt_result* res, const float2* F, float2* S, float a0, float b1,
-                     int conj_s, hipStream_t s);
+// S <- a0 v + b1 S with v the frame shifted back (conjugated when conj_s);
+// spectra held tall, ny x (nx/2+1) (trans: a wide frame, whose shift axes
+// swap in that layout).
+int launch_rt_update(int ny, int nx, int trans, const ccpt_result* res, const float2* F, float2* S,
+                     float a0, float b1, int conj_s, hipStream_t s);
 // img *= scale / *cnt (zeros when *cnt == 0).
 int launch_scale_by_count(float* img, int nn, float scale, const unsigned* cnt, hipStream_t s);
 

@@ -88,27 +88,30 @@ __global__ void k_scale_by_count(float* __restrict__ img, int nn, float scale,
 }
 
 // Real-time reference update (Sec. III.B, Eq. 9) by one frame with spectrum
-// F (row-major N x (N/2+1)) and result res: v = F phi_ky(d_y) phi_kx(d_x)
-// (the frame shifted back) enters the resident spectrum S as
+// F (row-major NY x (NX/2+1), the tall layout) and result res: v = F
+// phi_ky(d_y) phi_kx(d_x) (the frame shifted back; for a wide frame, held
+// transposed, the spectrum's rows run along the frame's x) enters the
+// resident spectrum S as
 //   S <- a0 conj(v) + b1 S   (conj_s: S = conj F[E], the CC-U reference)
 //   S <- a0 v + b1 S         (S = F[E], kept for CC-SN)
 // and a frame that did not track leaves S unchanged.
-template <int N>
+template <int NY, int NX>
 __global__ void __launch_bounds__(kRefThreads) k_rt_update(const ccpt_result* __restrict__ res,
                                                            const float2* __restrict__ F,
                                                            float2* __restrict__ S, float a0,
-                                                           float b1, int conj_s) {
-  constexpr int H = N / 2 + 1;
+                                                           float b1, int conj_s, int trans) {
+  constexpr int H = NX / 2 + 1;
   __shared__ float2 px[H];
   __shared__ float2 py[kAlignRows];
   const int y0 = blockIdx.x * kAlignRows, tid = threadIdx.x;
   const ccpt_result r = *res;
   if (!tracked(r)) return;
-  for (int k = tid; k < H; k += kRefThreads) px[k] = shift_phase(k, N, r.d[1]);
+  const double dy = trans ? r.d[1] : r.d[0], dx = trans ? r.d[0] : r.d[1];
+  for (int k = tid; k < H; k += kRefThreads) px[k] = shift_phase(k, NX, dx);
   for (int k = tid; k < kAlignRows; k += kRefThreads)
-    py[k] = y0 + k < N ? shift_phase(y0 + k, N, r.d[0]) : make_float2(0.f, 0.f);
+    py[k] = y0 + k < NY ? shift_phase(y0 + k, NY, dy) : make_float2(0.f, 0.f);
   __syncthreads();
-  const int rows = min(kAlignRows, N - y0);
+  const int rows = min(kAlignRows, NY - y0);
   for (int i = tid; i < rows * H; i += kRefThreads) {
     const int ry = i / H, kx = i - ry * H;
     const size_t e = (size_t)(y0 + ry) * H + kx;
@@ -119,11 +122,11 @@ __global__ void __launch_bounds__(kRefThreads) k_rt_update(const ccpt_result* __
   }
 }
 
-template <int N>
+template <int NY, int NX>
 static int rt_update_n(const ccpt_result* res, const float2* F, float2* S, float a0, float b1,
-                       int conj_s, hipStream_t s) {
-  hipLaunchKernelGGL((k_rt_update<N>), dim3((N + kAlignRows - 1) / kAlignRows), dim3(kRefThreads),
-                     0, s, res, F, S, a0, b1, conj_s);
+                       int conj_s, int trans, hipStream_t s) {
+  hipLaunchKernelGGL((k_rt_update<NY, NX>), dim3((NY + kAlignRows - 1) / kAlignRows),
+                     dim3(kRefThreads), 0, s, res, F, S, a0, b1, conj_s, trans);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -153,15 +156,22 @@ int launch_align_accumulate(int N, const FrameDesc* desc, int first, int count,
   return -2;
 }
 
-int launch_rt_update(int N, const ccpt_result* res, const float2* F, float2* S, float a0, float b1,
-                     int conj_s, hipStream_t s) {
-  switch (N) {
+int launch_rt_update(int ny, int nx, int trans, const ccpt_result* res, const float2* F, float2* S,
+                     float a0, float b1, int conj_s, hipStream_t s) {
+  if (ny == nx) {
+    switch (ny) {
 #define CASE(n) \
   case n:       \
-    return rt_update_n<n>(res, F, S, a0, b1, conj_s, s);
-    CCPT_FOR_SIZES(CASE)
+    return rt_update_n<n, n>(res, F, S, a0, b1, conj_s, 0, s);
+      CCPT_FOR_SIZES(CASE)
 #undef CASE
+    }
+    return -2;
   }
+#define CASE(a, b) \
+  if (ny == a && nx == b) return rt_update_n<a, b>(res, F, S, a0, b1, conj_s, trans, s);
+  CCPT_FOR_RECT(CASE)
+#undef CASE
   return -2;
 }
 

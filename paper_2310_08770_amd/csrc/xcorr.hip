@@ -574,32 +574,35 @@ static int spectrum_n(const void* data, int dtype, int pitch, long img_stride, i
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int N>
+// Spectra of frames given by descriptors, held tall (trans: the frames are
+// wide and read transposed): T and spec as in the tracking passes.
+template <int NY, int NX>
 static int frame_spectra_n(const FrameDesc* desc, int first, int count, int mode, float eps,
-                           float2* T, float2* spec, const float2* tw, hipStream_t s) {
-  constexpr int RPB = row_block(N, N);
-  constexpr int CB = cols_per_block(N, N);
-  constexpr int H = N / 2 + 1;
-  ImgSrc src{desc, first, nullptr, 0, 0, 0, 0};
-  hipLaunchKernelGGL((k_rows_fwd<N, N, RPB, float2>), dim3(N / RPB, count), dim3(kThreads), 0, s,
-                     src, mode == CCPT_MODE_CCSN ? 2 : 0, (double)eps, T, (FrameState*)nullptr,
+                           int trans, float2* T, float2* spec, const float2* tw, hipStream_t s) {
+  constexpr int RPB = row_block(NY, NX);
+  constexpr int CB = cols_per_block(NY, NX);
+  constexpr int H = NX / 2 + 1;
+  ImgSrc src{desc, first, nullptr, 0, 0, 0, trans};
+  hipLaunchKernelGGL((k_rows_fwd<NY, NX, RPB, float2>), dim3(NY / RPB, count), dim3(kThreads), 0,
+                     s, src, mode == CCPT_MODE_CCSN ? 2 : 0, (double)eps, T, (FrameState*)nullptr,
                      tw);
-  hipLaunchKernelGGL((k_cols<N, N, CB, COL_FWD, float2>), dim3((N / 2 + CB - 1) / CB, count),
+  hipLaunchKernelGGL((k_cols<NY, NX, CB, COL_FWD, float2>), dim3((NX / 2 + CB - 1) / CB, count),
                      dim3(kThreads), 0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr,
-                     (unsigned*)nullptr, spec, (long)N * H, tw);
+                     (unsigned*)nullptr, spec, (long)NY * H, tw);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int N>
+// Real images (NY rows of NX, the tall layout) from half spectra.
+template <int NY, int NX>
 static int inverse_n(const float2* spec, int n, float scale, float2* T, float* img,
                      const float2* tw, hipStream_t s) {
-  constexpr int RPB = row_block(N, N);
-  constexpr int CB = cols_per_block(N, N);
-  constexpr int H = N / 2 + 1;
-  hipLaunchKernelGGL((k_cols<N, N, CB, COL_INV, float2>), dim3((N / 2 + CB - 1) / CB, n),
+  constexpr int RPB = row_block(NY, NX);
+  constexpr int CB = cols_per_block(NY, NX);
+  constexpr int H = NX / 2 + 1;
+  hipLaunchKernelGGL((k_cols<NY, NX, CB, COL_INV, float2>), dim3((NX / 2 + CB - 1) / CB, n),
                      dim3(kThreads), 0, s, (const FrameDesc*)nullptr, 0, T, (float2*)nullptr,
-                     (unsigned*)nullptr, (float2*)spec, (long)N * H, tw);
-  hipLaunchKernelGGL((k_rows_inv<N, N, RPB, false, float2>), dim3(N / RPB, n), dim3(kThreads), 0,
+                     (unsigned*)nullptr, (float2*)spec, (long)NY * H, tw);
+  hipLaunchKernelGGL((k_rows_inv<NY, NX, RPB, false, float2>), dim3(NY / RPB, n), dim3(kThreads), 0,
                      s, T, (FrameState*)nullptr, img, scale, tw, (PeakCand*)nullptr, 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -682,27 +685,42 @@ int launch_spectrum64(int N, const void* data, int dtype, int pitch, long img_st
   return -2;
 }
 
-int launch_frame_spectra(int N, const FrameDesc* desc, int first, int count, int mode, float eps,
-                         float2* T, float2* spec, const float2* tw, hipStream_t s) {
-  switch (N) {
+int launch_frame_spectra(int ny, int nx, int trans, const FrameDesc* desc, int first, int count,
+                         int mode, float eps, float2* T, float2* spec, const float2* tw,
+                         hipStream_t s) {
+  if (ny == nx) {
+    switch (ny) {
 #define CASE(nn) \
   case nn:       \
-    return frame_spectra_n<nn>(desc, first, count, mode, eps, T, spec, tw, s);
-    CCPT_FOR_SIZES(CASE)
+    return frame_spectra_n<nn, nn>(desc, first, count, mode, eps, 0, T, spec, tw, s);
+      CCPT_FOR_SIZES(CASE)
 #undef CASE
+    }
+    return -2;
   }
+#define CASE(a, b) \
+  if (ny == a && nx == b) return frame_spectra_n<a, b>(desc, first, count, mode, eps, trans, T, spec, tw, s);
+  CCPT_FOR_RECT(CASE)
+#undef CASE
   return -2;
 }
 
-int launch_inverse(int N, const float2* spec, int n, float scale, float2* T, float* img,
+int launch_inverse(int ny, int nx, const float2* spec, int n, float scale, float2* T, float* img,
                    const float2* tw, hipStream_t s) {
-  switch (N) {
+  if (ny == nx) {
+    switch (ny) {
 #define CASE(nn) \
   case nn:       \
-    return inverse_n<nn>(spec, n, scale, T, img, tw, s);
-    CCPT_FOR_SIZES(CASE)
+    return inverse_n<nn, nn>(spec, n, scale, T, img, tw, s);
+      CCPT_FOR_SIZES(CASE)
 #undef CASE
+    }
+    return -2;
   }
+#define CASE(a, b) \
+  if (ny == a && nx == b) return inverse_n<a, b>(spec, n, scale, T, img, tw, s);
+  CCPT_FOR_RECT(CASE)
+#undef CASE
   return -2;
 }
 

@@ -132,6 +132,29 @@ def test_realtime_matches_the_oracle(mode):
     tr.close()
 
 
+@pytest.mark.parametrize("shape", [(256, 128), (128, 256)])
+@pytest.mark.parametrize("mode", ["ccu", "ccsn"])
+def test_realtime_rectangles_at_the_papers_setting(shape, mode):
+    ny, nx = shape
+    say(f"case: Table I {ny}x{nx} Airy frames, u = 256 (the Sec. IV.A real-time setting), 24 frames "
+        f"in order with the Eq. 9 update, a0 = 0.1, {mode}")
+    from paper_2310_08770_amd import Tracker, decode
+    from paper_2310_08770_amd.reference import realtime_track
+    w = S.table1_frames(ny, nx, 24)
+    frames = [np.asarray(f) for f in w.frames]
+    om = O.MODE_CCU if mode == "ccu" else O.MODE_CCSN
+    res_o = O.realtime_track(frames, 256, 0.1, om, 200.0)
+    tr = Tracker(upsample=256, mode=mode, eps=200.0)
+    r = decode(realtime_track(tr, t(np.stack(frames)), 0.1))
+    d_o = np.array([x["d"] for x in res_o])
+    p_o = np.array([x["p"] for x in res_o])
+    err = np.max(np.abs(r["d"] - d_o), axis=1)
+    say(f"  max |dd| {err.max():.2e} px (frame {int(np.argmax(err))}), last {err[-1]:.2e}")
+    assert np.array_equal(r["p"], p_o)
+    assert err.max() <= 1e-3
+    tr.close()
+
+
 def test_realtime_zero_gain_is_plain_tracking():
     say("case: Eq. 9 with a0 = 0 (reference never changes) equals tracking against frame 0")
     from paper_2310_08770_amd import Tracker, decode
