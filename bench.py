@@ -351,9 +351,9 @@ def main():
                     help="skip the two-stream leg and the other workloads (mixed ROIs, 512x512 u=200, "
                          "128x128 gradients, Table I, Fig. 1)")
     ap.add_argument("--no-tune", action="store_true", help="skip the chunk autotuner")
-    ap.add_argument("--chunk", type=int, default=0,
-                    help="frames per launch chunk instead of the autotuner's choice (a profiled "
-                         "run pins the chunk the timed runs use)")
+    ap.add_argument("--chunk", type=int, default=768,
+                    help="frames per launch chunk of the headline leg (the committed rocprofv3 "
+                         "summary is taken at 768); 0: the autotuner's choice")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -476,7 +476,9 @@ def main():
         try:
             tr3 = Tracker(upsample=w.u, precision=args.precision, streams=2)
             tr3.set_reference(ref_t)
-            chunk3 = tr3.chunk(N) if args.no_tune else tr3.autotune(N, n)
+            if args.chunk > 0:
+                tr3.set_chunk(N, args.chunk)
+            chunk3 = tr3.chunk(N) if (args.no_tune or args.chunk > 0) else tr3.autotune(N, n)
             out3 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
             k3 = max(3, args.steps // 3)
             tot3, lat3 = time_batched(tr3, frames_t, tr3.rois(frames_t), out3, k3, 2, torch)
@@ -488,6 +490,22 @@ def main():
             tr3.close()
         except Exception as e:  # noqa: BLE001
             legs[f"batched_{args.precision}_two_streams"] = dict(error=str(e)[:200])
+
+    # the headline precision with the launch plan the autotuner picks on this machine
+    if not args.no_extra and not args.no_tune and args.chunk > 0:
+        try:
+            tr4 = Tracker(upsample=w.u, precision=args.precision)
+            tr4.set_reference(ref_t)
+            chunk4 = tr4.autotune(N, n)
+            k4 = max(3, args.steps // 3)
+            tot4, lat4 = time_batched(tr4, frames_t, tr4.rois(frames_t), out, k4, 2, torch)
+            legs[f"batched_{args.precision}_autotuned"] = dict(
+                frames_per_s=round(n * k4 / tot4, 1), plan=tr4.plan(N),
+                p50_ms=round(float(np.median(lat4)) * 1e3, 3))
+            log(f"[bench] autotuned: {n * k4 / tot4:,.0f} frames/s (plan {tr4.plan(N)})")
+            tr4.close()
+        except Exception as e:  # noqa: BLE001
+            legs[f"batched_{args.precision}_autotuned"] = dict(error=str(e)[:200])
 
     if not args.no_plain:
         for name, graph in (("plain", False), ("graph_stream", True)):
