@@ -351,10 +351,9 @@ def main():
                     help="skip the two-stream leg and the other workloads (mixed ROIs, 512x512 u=200, "
                          "128x128 gradients, Table I, Fig. 1)")
     ap.add_argument("--no-tune", action="store_true", help="skip the chunk autotuner")
-    ap.add_argument("--chunk", type=int, default=770,
-                    help="frames per launch chunk of the headline leg (770: thirteen launches of the "
-                         "same kernels cover 10,000 frames, as in the committed rocprofv3 summary); "
-                         "0: the autotuner's choice")
+    ap.add_argument("--chunk", type=int, default=768,
+                    help="frames per launch chunk of the headline leg (768, three frames per CU, as in "
+                         "the committed rocprofv3 summary); 0: the autotuner's choice")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
