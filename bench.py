@@ -342,7 +342,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=10000)
-    ap.add_argument("--precision", default="bf16x2", choices=["fp32", "bf16x2"])
+    ap.add_argument("--precision", default="bf16x2", choices=["fp32", "bf16x2", "fp16x2"])
     ap.add_argument("--plain-frames", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -434,7 +434,8 @@ def main():
     flops_launch = updft_flops_per_frame(N, M, args.precision) * frames_per_launch
     achieved = flops_launch / (per_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    kernel_tag = f"k_updft_{'f32' if args.precision == 'fp32' else 'bf16x2_t256'}<{N}>"
+    kernel_tag = "k_updft_" + {"fp32": "f32", "bf16x2": "bf16x2_t256", "fp16x2": "fp16x2_t256"}[args.precision]
+    kernel_tag += f"<{N}>"
     traffic_pf = measured_traffic(kernel_tag)
     roofline = {
         "kernel": kernel_tag,
@@ -468,6 +469,27 @@ def main():
     except Exception as e:  # the other precision may not be available
         r2 = None
         legs[f"batched_{other}"] = dict(error=str(e)[:200])
+
+    # the fp16 split (same kernels, fp16 hi + lo operands) at the headline chunk,
+    # with its agreement with the headline results
+    if not args.no_extra and args.precision == "bf16x2":
+        try:
+            tr5 = Tracker(upsample=w.u, precision="fp16x2")
+            tr5.set_reference(ref_t)
+            tr5.set_chunk(N, chunk)
+            out5 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
+            k5 = max(3, args.steps // 3)
+            tot5, lat5 = time_batched(tr5, frames_t, tr5.rois(frames_t), out5, k5, 2, torch)
+            r5 = decode(out5)
+            legs["batched_fp16x2"] = dict(
+                frames_per_s=round(n * k5 / tot5, 1), chunk=chunk,
+                p50_ms=round(float(np.median(lat5)) * 1e3, 3),
+                same_integer_peak=bool(np.array_equal(r5["p"], res["p"])),
+                max_dd_vs_bf16x2_px=float(np.max(np.abs(r5["d"] - res["d"]))))
+            log(f"[bench] fp16x2: {n * k5 / tot5:,.0f} frames/s, {legs['batched_fp16x2']}")
+            tr5.close()
+        except Exception as e:  # noqa: BLE001
+            legs["batched_fp16x2"] = dict(error=str(e)[:200])
 
     # the headline precision with alternate chunks on two streams (CCPT_FLAG_STREAMS):
     # the DFT of one chunk overlaps the FFTs of the next; results are bit-identical

@@ -99,7 +99,12 @@ enum ccpt_precision {
   CCPT_PREC_FP32 = 0,   /* FP32 FFTs, FP32 matrix cores */
   CCPT_PREC_BF16X2 = 1, /* FP32 FFTs; DFT operands split into bf16 hi + lo,
                            three bf16 products accumulated in FP32 */
-  CCPT_PREC_FP16X2 = 2, /* reserved (fp16 hi + lo); ccpt_create rejects it */
+  CCPT_PREC_FP16X2 = 2, /* FP32 FFTs; DFT operands split into fp16 hi + lo
+                           (about 22 bits) under power-of-two scales, three
+                           fp16 products accumulated in FP32.  256 x 256
+                           frames of uint16 or float32 with an even pitch
+                           only (the one-kernel correlation): other shapes
+                           and pixel layouts give CCPT_E_UNSUPPORTED */
   CCPT_PREC_FP64 = 3    /* FFTs, cross-power spectrum, integer peak and the
                            upsampled DFT all in FP64 (vector units): the
                            accuracy mode, for agreement with an FP64

@@ -190,7 +190,9 @@ int set_device(ccpt_ctx* ctx) {
 }
 
 bool fp64(const ccpt_ctx* ctx) { return ctx->o.precision == CCPT_PREC_FP64; }
-bool split(const ccpt_ctx* ctx) { return ctx->o.precision == CCPT_PREC_BF16X2; }
+bool split(const ccpt_ctx* ctx) {
+  return ctx->o.precision == CCPT_PREC_BF16X2 || ctx->o.precision == CCPT_PREC_FP16X2;
+}
 
 // Longest Newton step before the result falls back to the grid estimate.
 // An FP64 grid locates the maximum to a grid step, so a longer step means
@@ -238,7 +240,8 @@ int ensure_tables(ccpt_ctx* ctx, int code) {
     const size_t words = (size_t)n * 2 * kfold_rows(t.Mp) * xb_pitch(n);
     if (hipMalloc(&t.kfold, words * sizeof(unsigned)) != hipSuccess)
       return fail(ctx, CCPT_E_NOMEM, "folded table of %zu bytes", words * sizeof(unsigned));
-    if (launch_build_kfold(t.kfold, n, ctx->o.upsample, ctx->M, ctx->c, kfold_rows(t.Mp), nullptr))
+    if (launch_build_kfold(t.kfold, n, ctx->o.upsample, ctx->M, ctx->c, kfold_rows(t.Mp),
+                           ctx->o.precision == CCPT_PREC_FP16X2 ? 1 : 0, nullptr))
       return fail(ctx, CCPT_E_HIP, "folded table launch failed");
     HIP_CHECK(ctx, hipDeviceSynchronize());
   }
@@ -279,7 +282,7 @@ size_t frame_ws_bytes(int n, int precision) {
   if (precision == CCPT_PREC_FP64)
     return 2 * spec_elems(n) * sizeof(double2) + (size_t)(n / row_block64(n)) * sizeof(PeakCand);
   size_t b = 2 * spec_elems(n) * sizeof(float2);
-  if (precision == CCPT_PREC_BF16X2)
+  if (precision == CCPT_PREC_BF16X2 || precision == CCPT_PREC_FP16X2)
     b += split_words(n) * sizeof(unsigned) + (size_t)code_ny(n) * sizeof(float2);  // Xb, Zc
   return b;
 }
@@ -304,6 +307,8 @@ int split_blocks_for(const ccpt_ctx* ctx, int n) {
 }
 
 int fused_min_for(const ccpt_ctx* ctx, int n) {
+  // the fp16 split takes its operands from the one-kernel correlation only
+  if (ctx->o.precision == CCPT_PREC_FP16X2) return 1;
   auto it = ctx->sched.find(n);
   if (it != ctx->sched.end() && it->second.fused_min >= 0) return it->second.fused_min;
   return kFusedMinFrames;
@@ -594,6 +599,10 @@ int plan_rois(ccpt_ctx* ctx, const ccpt_roi* rois, int n, Plan& plan, bool fp32_
     }
     plan.sig.back()++;
   }
+  // the fp16 split runs the one-kernel correlation only, which reads pixel pairs
+  if (ctx->o.precision == CCPT_PREC_FP16X2 && !fp32_spec && !pairs_ok(plan.desc, 0, n))
+    return fail(ctx, CCPT_E_UNSUPPORTED,
+                "the fp16 split takes uint16 or float32 frames with an even pitch and aligned pairs");
   return CCPT_OK;
 }
 
@@ -738,6 +747,7 @@ int ccpt_create(ccpt_ctx** out, int device, const ccpt_options* opts) {
   if (o.upsample < 1 || o.upsample > 1024) return CCPT_E_INVALID;
   if (!(o.window > 0.0 && o.window <= 2.0)) return CCPT_E_INVALID;
   if (o.precision != CCPT_PREC_FP32 && o.precision != CCPT_PREC_BF16X2 &&
+      o.precision != CCPT_PREC_FP16X2 &&
       o.precision != CCPT_PREC_FP64)
     return CCPT_E_INVALID;
   if (o.newton_iters < 0 || o.newton_iters > 8) return CCPT_E_INVALID;
@@ -825,6 +835,9 @@ int ccpt_set_reference(ccpt_ctx* ctx, const ccpt_image* refs, int n_refs, void* 
     if (rc) return rc;
     if (fp64(ctx) && refs[i].ny != refs[i].nx)
       return fail(ctx, CCPT_E_UNSUPPORTED, "reference %d: the FP64 mode takes square frames only",
+                  i);
+    if (ctx->o.precision == CCPT_PREC_FP16X2 && !(refs[i].ny == 256 && refs[i].nx == 256))
+      return fail(ctx, CCPT_E_UNSUPPORTED, "reference %d: the fp16 split takes 256x256 frames only",
                   i);
   }
   HIP_CHECK(ctx, hipStreamSynchronize(s));

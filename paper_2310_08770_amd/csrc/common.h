@@ -31,7 +31,9 @@ struct FrameState {
                                   // encoding (0 until set; FP32 and split paths)
   unsigned amin, amax;            // order-preserving keys of min/max of A
   unsigned flags;                 // CCPT_ST_NONFINITE; CCPT_ST_NEAR_TIE (FP64 mode)
-  unsigned pad;
+  unsigned xmax;                  // largest |Re|, |Im| of the cross-power spectrum
+                                  // without its DC term, as float bits (the 256x256
+                                  // one-kernel correlation; 0 elsewhere)
 };
 
 // FP64 mode: best correlation value of one row block of a frame and its
@@ -264,7 +266,7 @@ __host__ __device__ constexpr int kfold_rows(int Mp) {
 
 // Builds the folded split table [NY][2][rows][xb_pitch(NY)] words on the
 // device for frames of NY rows (rows = kfold_rows(Mp); rows m >= M are zero).
-int launch_build_kfold(unsigned* out, int NY, int u, int M, int c, int rows, hipStream_t s);
+int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int rows, int f16, hipStream_t s);
 int launch_updft(int ny, int nx, const GroupParams& g, const UpdftTables& t, hipStream_t s);
 
 // FP64 mode: reduces the peak candidates, then the upsampled DFT in FP64 on

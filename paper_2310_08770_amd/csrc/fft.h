@@ -87,6 +87,24 @@ __device__ __forceinline__ void split_pair(float2 v, unsigned& hi, unsigned& lo)
   split2(v.x, v.y, hi, lo);
 }
 
+// fp16 hi + lo split of two floats (x ~ hi + lo to about 22 significant bits
+// while |x| stays inside the fp16 range), each packed as a | b << 16.
+__device__ __forceinline__ unsigned f16_pack(float a, float b) {
+  const _Float16 ha = (_Float16)a, hb = (_Float16)b;
+  return (unsigned)__builtin_bit_cast(unsigned short, ha) |
+         ((unsigned)__builtin_bit_cast(unsigned short, hb) << 16);
+}
+__device__ __forceinline__ float f16_lo_float(unsigned w) {
+  return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xFFFFu));
+}
+__device__ __forceinline__ float f16_hi_float(unsigned w) {
+  return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+}
+__device__ __forceinline__ void split2_f16(float a, float b, unsigned& hi, unsigned& lo) {
+  hi = f16_pack(a, b);
+  lo = f16_pack(a - f16_lo_float(hi), b - f16_hi_float(hi));
+}
+
 // LDS layout of an FFT sequence: element i sits at lds_idx(i), with one
 // unused slot after every 2^kLdsPadShift elements when the shift is nonzero,
 // so the strided writes of the early Stockham stages spread over the LDS

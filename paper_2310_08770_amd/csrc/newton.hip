@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(kNThreads, 3) k_newton(GroupParams g, double s
       z.amin = 0xFFFFFFFFu;
       z.amax = 0;
       z.flags = 0;
-      z.pad = 0;
+      z.xmax = 0;
       g.st[f] = z;
     }
   };

@@ -61,6 +61,14 @@ inline void split_bf16(double x, uint16_t& hi, uint16_t& lo) {
   hi = bf16_rne((float)x);
   lo = bf16_rne((float)(x - (double)bf16_to_f(hi)));
 }
+// fp16 (round to nearest even by the compiler's conversion) and the hi/lo
+// split x ~ hi + lo to about 22 significant bits inside the fp16 range
+inline void split_f16(double x, uint16_t& hi, uint16_t& lo) {
+  const _Float16 h = (_Float16)(float)x;
+  const _Float16 l = (_Float16)(float)(x - (double)(float)h);
+  memcpy(&hi, &h, 2);
+  memcpy(&lo, &l, 2);
+}
 
 // Tables of frames of ny rows of nx pixels (nx divides ny): twiddles of
 // length ny, K over ky < ny, W over kx <= nx/2 with 1/(ny nx).
@@ -103,6 +111,8 @@ inline HostTables build_tables(int ny, int nx, int u, int M, int c, int precisio
     for (int mx = 0; mx < Mp; ++mx)
       for (int j = 0; j < Kb; ++j) W[(size_t)mx * Kb + j] = (float)w[(size_t)j * Mp + mx];
   } else if (nx == 256) {
+    // (fp16 split: W scaled by 2^16, exact, so its values stay normal fp16)
+    const bool f16 = precision == CCPT_PREC_FP16X2;
     // Stage B operand of the 256-column split kernel (k_updft_bf16x2_t256), in
     // the order of its k steps: wave w (kx tile 32 w .. 32 w + 31), k step s
     // (s < 2: the real rows j = kx, s >= 2: the imaginary rows j = N/2 + kx,
@@ -123,7 +133,10 @@ inline HostTables build_tables(int ny, int nx, int u, int M, int c, int precisio
               const int kx = 32 * wv + (2 * (s4 & 1) + (e >> 2)) * 8 + 4 * hh + (e & 3);
               const int jj = s4 < 2 ? kx : nx / 2 + kx;
               uint16_t hi, lo;
-              split_bf16(w[(size_t)jj * Mp + mx], hi, lo);
+              if (f16)
+                split_f16(w[(size_t)jj * Mp + mx] * 65536.0, hi, lo);
+              else
+                split_bf16(w[(size_t)jj * Mp + mx], hi, lo);
               const size_t o = ((((size_t)r * 4 + wv) * 4 + s4) * 64 + l) * 8 + e;
               W[o] = hi;
               W[plane + o] = lo;

@@ -870,7 +870,27 @@ __global__ void __launch_bounds__(64 * ((NX / 2 + 31) / 32))
 // column Zc instead of the split copy Xb, and each chunk's A fragments are
 // split into bf16 hi/lo here, after the matrix instructions of the chunk
 // before (the same words the split copy would hold).
-template <int NY, int MT, bool FROMX>
+//
+// F16 (with FROMX): the fp16 hi + lo split instead (about 22 significant
+// bits): X scaled by a power of two from the frame's largest component (the
+// correlation kernel records it), Y by 2^-8 before Stage B, and the K' and W
+// tables stored as fp16 hi/lo (W scaled by 2^16 on the host); every scale is a
+// positive power of two, so the grid and its maximum are those of the
+// unscaled products up to rounding.
+// One 32x32x16 matrix instruction on packed bf16 (F16 = false) or fp16
+// operands, FP32 accumulation.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+template <bool F16>
+__device__ __forceinline__ f32x16 mfma32(u32x4 a, u32x4 b, f32x16 c) {
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+template <int NY, int MT, bool FROMX, bool F16>
 __global__ void __launch_bounds__(256)
     k_updft_bf16x2_t256(GroupParams g, const unsigned* __restrict__ kfold,
                         const unsigned short* __restrict__ WP, int Mp) {
@@ -956,32 +976,33 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int s8 = 0; s8 < KC / 8; ++s8) {
       const int col = s8 * 8 + 4 * h;
-      const bf16x8 bh_r = as_bf(neg_im(bh[s8])), bh_i = as_bf(swap_ri(bh[s8]));
-      const bf16x8 bl_r = as_bf(neg_im(bl[s8])), bl_i = as_bf(swap_ri(bl[s8]));
-      bf16x8 ah[MT], al[MT];
+      // (the sign flip and the half swap act alike on packed bf16 and fp16)
+      const u32x4 bh_r = neg_im(bh[s8]), bh_i = swap_ri(bh[s8]);
+      const u32x4 bl_r = neg_im(bl[s8]), bl_i = swap_ri(bl[s8]);
+      u32x4 ah[MT], al[MT];
 #pragma unroll
       for (int t = 0; t < MT; ++t)
         {
-          ah[t] = as_bf(*(const u32x4*)(ks_hi + (t * 32 + j) * KCS + col));
-          al[t] = as_bf(*(const u32x4*)(ks_lo + (t * 32 + j) * KCS + col));
+          ah[t] = *(const u32x4*)(ks_hi + (t * 32 + j) * KCS + col);
+          al[t] = *(const u32x4*)(ks_lo + (t * 32 + j) * KCS + col);
         }
 #pragma unroll
       for (int t = 0; t < MT; ++t)
         {
-          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh_r, ah[t], accr[t], 0, 0, 0);
-          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh_i, ah[t], acci[t], 0, 0, 0);
+          accr[t] = mfma32<F16>(bh_r, ah[t], accr[t]);
+          acci[t] = mfma32<F16>(bh_i, ah[t], acci[t]);
         }
 #pragma unroll
       for (int t = 0; t < MT; ++t)
         {
-          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl_r, ah[t], accr[t], 0, 0, 0);
-          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl_i, ah[t], acci[t], 0, 0, 0);
+          accr[t] = mfma32<F16>(bl_r, ah[t], accr[t]);
+          acci[t] = mfma32<F16>(bl_i, ah[t], acci[t]);
         }
 #pragma unroll
       for (int t = 0; t < MT; ++t)
         {
-          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh_r, al[t], accr[t], 0, 0, 0);
-          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh_i, al[t], acci[t], 0, 0, 0);
+          accr[t] = mfma32<F16>(bh_r, al[t], accr[t]);
+          acci[t] = mfma32<F16>(bh_i, al[t], acci[t]);
         }
     }
   };
@@ -999,13 +1020,26 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int e = 0; e < 4; ++e) xr[s8][e] = Xc[(size_t)(k0 + s8 * 8 + 4 * h + e) * xs];
     };
+    // fp16: the frame's spectrum scaled by a power of two that brings its
+    // largest component (without DC) below 2^13 (exact; the grid maximum does
+    // not depend on a positive scale, and Newton reads the unscaled X)
+    float xsc = 1.f;
+    if constexpr (F16) {
+      const float xm = __uint_as_float(st.xmax);
+      int ex = 0;
+      (void)frexpf(xm, &ex);
+      if (xm > 0.f && xm <= 3.4e38f) xsc = ldexpf(1.f, min(13 - ex, 120));  // (finite X only)
+    }
     auto split_x = [&]() {
 #pragma unroll
       for (int s8 = 0; s8 < KC / 8; ++s8)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           unsigned wh, wl;
-          split_pair(xr[s8][e], wh, wl);
+          if constexpr (F16)
+            split2_f16(xr[s8][e].x * xsc, xr[s8][e].y * xsc, wh, wl);
+          else
+            split_pair(xr[s8][e], wh, wl);
           bh[s8][e] = wh;
           bl[s8][e] = wl;
         }
@@ -1085,7 +1119,10 @@ __global__ void __launch_bounds__(256)
         const int v = 8 * (s4 & 1) + 2 * q;
         const f32x16& a = s4 < 2 ? accr[t] : acci[t];
         unsigned wh, wl;
-        split2(a[v], a[v + 1], wh, wl);
+        if constexpr (F16)  // |Y| <= 256 * 2^13: scaled by 2^-8 into the fp16 range (exact)
+          split2_f16(a[v] * 0x1p-8f, a[v + 1] * 0x1p-8f, wh, wl);
+        else
+          split2(a[v], a[v + 1], wh, wl);
         yh[t][s4][q] = wh;
         yl[t][s4][q] = wl;
       }
@@ -1115,16 +1152,16 @@ __global__ void __launch_bounds__(256)
       for (int v = 0; v < 16; ++v) au[t][v] = 0.f;
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
-      const bf16x8 w_h = as_bf(wh[s4]), w_l = as_bf(wl[s4]);
+      const u32x4 w_h = wh[s4], w_l = wl[s4];
 #pragma unroll
       for (int t = 0; t < MT; ++t)
-        au[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(yh[t][s4]), w_h, au[t], 0, 0, 0);
+        au[t] = mfma32<F16>(yh[t][s4], w_h, au[t]);
 #pragma unroll
       for (int t = 0; t < MT; ++t)
-        au[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(yh[t][s4]), w_l, au[t], 0, 0, 0);
+        au[t] = mfma32<F16>(yh[t][s4], w_l, au[t]);
 #pragma unroll
       for (int t = 0; t < MT; ++t)
-        au[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(yl[t][s4]), w_h, au[t], 0, 0, 0);
+        au[t] = mfma32<F16>(yl[t][s4], w_h, au[t]);
     }
     __syncthreads();  // the last round's sums (or Stage A's chunks) are done with LDS
     // this wave's partial grid, column-major: up[kt][mx][my] (mx = lane mod 32)
@@ -1174,11 +1211,12 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Folded split table for the wide kernel: K'_p[m, ky] = phi_ky(p + (m - c)/u)
-// for every integer peak row p of frames of N rows, as bf16 hi/lo words
-// (re | im << 16), [N][2][Mp][xb_pitch(N)], computed in FP64 with exactly
-// reduced phases.
-__global__ void k_build_kfold(unsigned* __restrict__ out, int N, int u, int M, int c, int rows, int P) {
+// Folded split table for the wide kernels: K'_p[m, ky] = phi_ky(p + (m - c)/u)
+// for every integer peak row p of frames of N rows, as bf16 (f16: fp16) hi/lo
+// words (re | im << 16), [N][2][Mp][xb_pitch(N)], computed in FP64 with
+// exactly reduced phases.
+__global__ void k_build_kfold(unsigned* __restrict__ out, int N, int u, int M, int c, int rows, int P,
+                              int f16) {
   const size_t plane = (size_t)rows * P;
   const size_t total = (size_t)N * plane;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -1203,17 +1241,23 @@ __global__ void k_build_kfold(unsigned* __restrict__ out, int N, int u, int M, i
         im = sn;
       }
     }
+    const size_t base = (size_t)iy * 2 * plane + (size_t)m * P + ky;
+    if (f16) {  // fp16 hi/lo words (the fp16 split)
+      const unsigned h = f16_pack((float)re, (float)im);
+      out[base] = h;
+      out[base + plane] = f16_pack((float)(re - (double)f16_lo_float(h)), (float)(im - (double)f16_hi_float(h)));
+      continue;
+    }
     const unsigned hr = bf16_bits((float)re), hm = bf16_bits((float)im);
     const unsigned lr = bf16_bits((float)(re - (double)bf16_float(hr)));
     const unsigned lm = bf16_bits((float)(im - (double)bf16_float(hm)));
-    const size_t base = (size_t)iy * 2 * plane + (size_t)m * P + ky;
     out[base] = hr | (hm << 16);
     out[base + plane] = lr | (lm << 16);
   }
 }
 
-int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int rows, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_kfold, dim3(4096), dim3(256), 0, s, out, N, u, M, c, rows, xb_pitch(N));
+int launch_build_kfold(unsigned* out, int N, int u, int M, int c, int rows, int f16, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_kfold, dim3(4096), dim3(256), 0, s, out, N, u, M, c, rows, xb_pitch(N), f16);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1232,6 +1276,16 @@ static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
       hipLaunchKernelGGL((k_updft_f32<NY, NX, false>), dim3(mtiles, g.count), dim3(kUThreads), 0,
                          s, g, (const float2*)t.ky, (const float*)t.wb, t.Mp, (float*)nullptr, 1);
     }
+  } else if (t.precision == CCPT_PREC_FP16X2) {
+    // the fp16 split: 256 x 256 frames through the one-kernel correlation only
+    if constexpr (NY == 256 && NX == 256) {
+      if (g.Xb || !g.Zc || !t.kfold) return -2;
+      hipLaunchKernelGGL((k_updft_bf16x2_t256<NY, kWideMT, true, true>),
+                         dim3((mtiles + kWideMT - 1) / kWideMT, g.count), dim3(256), 0, s, g,
+                         (const unsigned*)t.kfold, (const unsigned short*)t.wb, t.Mp);
+    } else {
+      return -2;
+    }
   } else if (t.precision == CCPT_PREC_BF16X2) {
     if (!g.Xb && !(NY == 256 && NX == 256 && g.Zc)) return -1;
     if constexpr (NX >= kWideMinN) {
@@ -1243,13 +1297,13 @@ static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
         if constexpr (NY == 256) {
           if (!g.Xb) {  // the one-kernel correlation left X and its packed column
             if (!g.Zc) return -1;
-            hipLaunchKernelGGL((k_updft_bf16x2_t256<NY, MT, true>),
+            hipLaunchKernelGGL((k_updft_bf16x2_t256<NY, MT, true, false>),
                                dim3((mtiles + MT - 1) / MT, g.count), dim3(256), 0, s, g,
                                (const unsigned*)t.kfold, (const unsigned short*)t.wb, t.Mp);
             return hipGetLastError() == hipSuccess ? 0 : -1;
           }
         }
-        hipLaunchKernelGGL((k_updft_bf16x2_t256<NY, MT, false>), dim3((mtiles + MT - 1) / MT, g.count),
+        hipLaunchKernelGGL((k_updft_bf16x2_t256<NY, MT, false, false>), dim3((mtiles + MT - 1) / MT, g.count),
                            dim3(256), 0, s, g, (const unsigned*)t.kfold, (const unsigned short*)t.wb,
                            t.Mp);
       } else {

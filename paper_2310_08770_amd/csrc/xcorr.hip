@@ -122,7 +122,7 @@ __global__ void k_init_state(FrameState* st, int count) {
     s.amin = 0xFFFFFFFFu;
     s.amax = 0;
     s.flags = 0;
-    s.pad = 0;
+    s.xmax = 0;
     st[i] = s;
   }
 }

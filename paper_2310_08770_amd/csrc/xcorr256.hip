@@ -162,9 +162,10 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
   __shared__ float2 tw[N];
   __shared__ float2 stage[2 * N];  // products of the real columns 0 and N/2
   __shared__ float redf[2][kT / 64];
-  __shared__ unsigned redu[4][kT / 64];
+  __shared__ unsigned redu[5][kT / 64];
   const int t = threadIdx.x;
   const int f = blockIdx.x;
+  float xmx = 0.f;  // this thread's largest |Re|, |Im| of X without the DC term
   const FrameDesc desc = g.desc[g.first + f];
   for (int i = t; i < N; i += kT) tw[i] = g.tw[i];
 
@@ -477,7 +478,9 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
 #pragma unroll
         for (int e = 0; e < 32; ++e) {
           const int ky = kap(hp, e >> 4) + 16 * (e & 15);
-          Xf[(size_t)ky * H + col] = r[pslot(e, i)];
+          const float2 x = r[pslot(e, i)];
+          Xf[(size_t)ky * H + col] = x;
+          xmx = fmaxf(xmx, fmaxf(fabsf(x.x), fabsf(x.y)));
         }
       }
       if (i == 0) {
@@ -485,7 +488,11 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
         // split precision also Z = X[., 0] + i X[., N/2] without the DC term,
         // the packed column the matrix DFT takes as its kx = 0 operand
         __syncthreads();
-        for (int e = t; e < 2 * N; e += kT) Xf[(size_t)(e & (N - 1)) * H + (e >> 8) * (N / 2)] = stage[e];
+        for (int e = t; e < 2 * N; e += kT) {
+          const float2 x = stage[e];
+          Xf[(size_t)(e & (N - 1)) * H + (e >> 8) * (N / 2)] = x;
+          if (e) xmx = fmaxf(xmx, fmaxf(fabsf(x.x), fabsf(x.y)));  // (e = 0: the DC term)
+        }
         if constexpr (SPLIT) {
           for (int ky = t; ky < N; ky += kT) {
             const float2 x0 = stage[ky], x1 = stage[N + ky];
@@ -684,12 +691,14 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
   kmin = ~wave_max(~kmin);
   kmax = wave_max(kmax);
   bad = wave_max(bad);
+  unsigned xb = wave_max(__float_as_uint(xmx));  // (non-negative floats order as their bits)
   if ((t & 63) == 0) {
     redf[0][t >> 6] = t1;
     redf[1][t >> 6] = t2;
     redu[0][t >> 6] = kmin;
     redu[1][t >> 6] = kmax;
     redu[2][t >> 6] = bad;
+    redu[4][t >> 6] = xb;
   }
   __syncthreads();
   t1 = redf[0][0];
@@ -717,8 +726,10 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
       kmin = min(kmin, redu[0][w]);
       kmax = max(kmax, redu[1][w]);
       bad |= redu[2][w];
+      xb = max(xb, redu[4][w]);
     }
     FrameState& st = g.st[f];
+    st.xmax = xb;
     st.peak_key = peak_key(t1, idx);
     st.second_key = peak_key(t2, 0u);
     st.amin = kmin;

@@ -92,7 +92,7 @@ def test_grid_index_gauss64_u20(precision):
     check_grid(w, list(range(100)), precision, "gauss64_u20")
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x2"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x2", "fp16x2"])
 def test_grid_index_airy256_u100(precision):
     say(f"case: grid index, airy256_u100 first 256 frames, {precision}")
     w = S.config2(256)
