@@ -76,48 +76,70 @@ constexpr int ym_stride() {
 // consecutive k = 16 q4 + i over the block's 16 MFMA steps (the same k for
 // A and B), so a lane loads its W values as four 16-byte runs per block.
 // Every thread of the block calls this.
+// Whole 64-wide K blocks of Stage B whose W values a lane loads at once: the
+// largest divisor of the block count not above 4.
+constexpr int stage_b_batch(int nb) {
+  int b = 1;
+  for (int d = 1; d <= 4 && d <= nb; ++d)
+    if (nb % d == 0) b = d;
+  return b;
+}
+
 template <int NY, int NX>
 __device__ void stage_b_f32(const GroupParams& g, const float* ym, const float* __restrict__ WtT,
-                            int Mp, int m0, int f, unsigned long long* red) {
+                            int Mp, int m0, int f, unsigned long long* red, int nt0, int nt1) {
   const bool tr = transposed<NY, NX>(g.trans);
   constexpr int KB = (NX + 31) / 32 * 32;
   constexpr int YR = ym_stride<NX>();
+  constexpr int NB = KB / 64;            // whole 64-wide blocks of K
+  constexpr bool TAIL = (KB % 64) != 0;  // then one of 32
+  constexpr int BB = stage_b_batch(NB);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ntb = 2 * (Mp / 16);
+  const int ntb = 2 * (nt1 - nt0);
   unsigned long long best = 0;
   const int l16 = lane & 15, q4 = lane >> 4;
   for (int T = wave; T < ntb; T += 4) {
-    const int mt = T & 1, nt = T >> 1;
+    const int mt = T & 1, nt = nt0 + (T >> 1);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     const float* arow = ym + (mt * 16 + l16) * YR + 16 * q4;
     const float* bcol = WtT + (size_t)(nt * 16 + l16) * KB + 16 * q4;
-    // KB is a multiple of 32: whole 64-wide blocks, then at most one of 32
-    for (int k0 = 0; k0 < KB; k0 += 64) {
-      if (k0 + 64 <= KB) {
-        float4 w[4];
+    // the W values of BB blocks are requested together (one memory round trip
+    // per BB blocks, not per block), then the blocks' products in k order
+    if constexpr (NB > 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = *(const float4*)(bcol + k0 + 4 * i);
+      for (int b0 = 0; b0 < NB; b0 += BB) {
+        float4 w[BB][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i], w[i].x, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i + 1], w[i].y, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i + 2], w[i].z, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i + 3], w[i].w, acc, 0, 0, 0);
+        for (int b = 0; b < BB; ++b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) w[b][i] = *(const float4*)(bcol + (b0 + b) * 64 + 4 * i);
+#pragma unroll
+        for (int b = 0; b < BB; ++b) {
+          const int k0 = (b0 + b) * 64;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i], w[b][i].x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i + 1], w[b][i].y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i + 2], w[b][i].z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k0 + 4 * i + 3], w[b][i].w, acc, 0, 0, 0);
+          }
         }
-      } else {
-        // last 32 of K: lane group q4 takes k = k0 + 8 q4 + i
-        const float* ar = arow - 8 * q4;
-        const float* bc = bcol - 8 * q4;
-        float4 w[2];
+      }
+    }
+    if constexpr (TAIL) {
+      // last 32 of K: lane group q4 takes k = k0 + 8 q4 + i
+      constexpr int k0 = NB * 64;
+      const float* ar = arow - 8 * q4;
+      const float* bc = bcol - 8 * q4;
+      float4 w[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) w[i] = *(const float4*)(bc + k0 + 4 * i);
+      for (int i = 0; i < 2; ++i) w[i] = *(const float4*)(bc + k0 + 4 * i);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i], w[i].x, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i + 1], w[i].y, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i + 2], w[i].z, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i + 3], w[i].w, acc, 0, 0, 0);
-        }
+      for (int i = 0; i < 2; ++i) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i], w[i].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i + 1], w[i].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i + 2], w[i].z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[k0 + 4 * i + 3], w[i].w, acc, 0, 0, 0);
       }
     }
 #pragma unroll
@@ -192,20 +214,52 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
   constexpr int NCH = NY / KC;
   const int ch0 = SPLIT ? (int)blockIdx.z * NCH / nsl : 0;
   const int ch1 = SPLIT ? ((int)blockIdx.z + 1) * NCH / nsl : NCH;
-  for (int k0 = ch0 * KC; k0 < ch1 * KC; k0 += KC) {
-    for (int i = tid; i < XS; i += kUThreads) {
+  // A chunk's X and K values are held in registers between their loads and
+  // the LDS stores, so the next chunk's loads are in flight during this
+  // chunk's matrix instructions (indices clamped: every load in bounds)
+  constexpr int XQ = (XS + kUThreads - 1) / kUThreads;
+  constexpr int KQ = (32 * KC + kUThreads - 1) / kUThreads;
+  float2 xr[XQ], kr[KQ];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < XQ; ++q) {
+      const int i = min(tid + q * kUThreads, XS - 1);
       const int kk = i / H, kx = i - kk * H;
-      const int ky = k0 + kk;
-      float2 v = Xf[(size_t)ky * H + kx];
-      v = cmul(v, twf[(ky * iy + kx * ix * RX) % NY]);
-      if (ky == 0 && kx == 0) v = make_float2(0.f, 0.f);  // DC only shifts U by a constant
-      xs[i] = v;
+      xr[q] = Xf[(size_t)(k0 + kk) * H + kx];
     }
-    for (int i = tid; i < 32 * KC; i += kUThreads) {
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int i = min(tid + q * kUThreads, 32 * KC - 1);
       const int m = i / KC, kk = i - m * KC;
-      ks[m * KCS + kk] = Ktab[(size_t)(m0 + m) * NY + k0 + kk];
+      kr[q] = Ktab[(size_t)(m0 + m) * NY + k0 + kk];
     }
+  };
+  auto store_chunk = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < XQ; ++q) {
+      const int i = tid + q * kUThreads;
+      if (XS % kUThreads == 0 || i < XS) {
+        const int kk = i / H, kx = i - kk * H;
+        const int ky = k0 + kk;
+        float2 v = cmul(xr[q], twf[(ky * iy + kx * ix * RX) % NY]);
+        if (ky == 0 && kx == 0) v = make_float2(0.f, 0.f);  // DC only shifts U by a constant
+        xs[i] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int i = tid + q * kUThreads;
+      if ((32 * KC) % kUThreads == 0 || i < 32 * KC) {
+        const int m = i / KC, kk = i - m * KC;
+        ks[m * KCS + kk] = kr[q];
+      }
+    }
+  };
+  load_chunk(ch0 * KC);
+  for (int k0 = ch0 * KC; k0 < ch1 * KC; k0 += KC) {
+    store_chunk(k0);
     __syncthreads();
+    load_chunk(min(k0 + KC, (ch1 - 1) * KC));  // (the last chunk reloads itself)
 #pragma unroll 4
     for (int kk = 0; kk < KC; ++kk) {
       const float2 kv = ks[l32 * KCS + kk];
@@ -263,11 +317,15 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32(GroupParams g, const fl
     float* dst = ypart + (((size_t)f * mtiles + blockIdx.x) * nsl + blockIdx.z) * 32 * KB;
     for (int i = tid; i < 32 * KB; i += kUThreads) dst[i] = ym[(i / KB) * YR + i % KB];
   } else {
-    stage_b_f32<NY, NX>(g, ym, Wtab, Mp, m0, f, red);
+    stage_b_f32<NY, NX>(g, ym, Wtab, Mp, m0, f, red, 0, Mp / 16);
   }
 }
 
-// Sums the ky-slice partials of one 32-row tile in a fixed order, then Stage B.
+// Sums the ky-slice partials of one 32-row tile in a fixed order, then Stage B
+// over kSumColTiles 16-column tiles of the grid (blockIdx.z picks them: a
+// single frame's Stage B is spread over (Mp/32) x (Mp/16/kSumColTiles) blocks,
+// each summing the partials of its rows).
+constexpr int kSumColTiles = 2;
 template <int NY, int NX>
 __global__ void __launch_bounds__(kUThreads) k_updft_f32_sum(GroupParams g, const float* __restrict__ Wtab,
                                                              int Mp, const float* __restrict__ ypart,
@@ -285,15 +343,26 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32_sum(GroupParams g, cons
   // come from other XCDs: one round trip per slice, not per element); each
   // element is summed over the slices in order
   constexpr int PER = 32 * KB / kUThreads;  // KB is a multiple of 32
+  // SG slices are requested together (a clamped slice index keeps every load
+  // in bounds; slices past nsl are not added)
+  constexpr int SG = PER >= 128 ? 1 : (128 / PER < kSplitSlices ? 128 / PER : kSplitSlices);
   float v[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) v[e] = 0.f;
-  for (int q = 0; q < nsl; ++q) {
-    float p[PER];
+  for (int q0 = 0; q0 < nsl; q0 += SG) {
+    float p[SG][PER];
 #pragma unroll
-    for (int e = 0; e < PER; ++e) p[e] = src[(size_t)q * 32 * KB + threadIdx.x + e * kUThreads];
+    for (int j = 0; j < SG; ++j) {
+      const int q = min(q0 + j, nsl - 1);
 #pragma unroll
-    for (int e = 0; e < PER; ++e) v[e] += p[e];
+      for (int e = 0; e < PER; ++e) p[j][e] = src[(size_t)q * 32 * KB + threadIdx.x + e * kUThreads];
+    }
+#pragma unroll
+    for (int j = 0; j < SG; ++j)
+      if (q0 + j < nsl) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) v[e] += p[j][e];
+      }
   }
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
@@ -301,7 +370,8 @@ __global__ void __launch_bounds__(kUThreads) k_updft_f32_sum(GroupParams g, cons
     ym[(i / KB) * YR + i % KB] = v[e];
   }
   __syncthreads();
-  stage_b_f32<NY, NX>(g, ym, Wtab, Mp, blockIdx.x * 32, f, red);
+  const int nt0 = (int)blockIdx.z * kSumColTiles;
+  stage_b_f32<NY, NX>(g, ym, Wtab, Mp, blockIdx.x * 32, f, red, nt0, min(nt0 + kSumColTiles, Mp / 16));
 }
 
 
@@ -1270,8 +1340,9 @@ static int updft_n(const GroupParams& g, const UpdftTables& t, hipStream_t s) {
     if (g.ypart && nsl > 1) {  // (the plan decided the split: a partials buffer)
       hipLaunchKernelGGL((k_updft_f32<NY, NX, true>), dim3(mtiles, g.count, nsl), dim3(kUThreads),
                          0, s, g, (const float2*)t.ky, (const float*)t.wb, t.Mp, g.ypart, nsl);
-      hipLaunchKernelGGL((k_updft_f32_sum<NY, NX>), dim3(mtiles, g.count), dim3(kUThreads), 0, s, g,
-                         (const float*)t.wb, t.Mp, (const float*)g.ypart, nsl);
+      const int ncg = (t.Mp / 16 + kSumColTiles - 1) / kSumColTiles;
+      hipLaunchKernelGGL((k_updft_f32_sum<NY, NX>), dim3(mtiles, g.count, ncg), dim3(kUThreads), 0, s,
+                         g, (const float*)t.wb, t.Mp, (const float*)g.ypart, nsl);
     } else {
       hipLaunchKernelGGL((k_updft_f32<NY, NX, false>), dim3(mtiles, g.count), dim3(kUThreads), 0,
                          s, g, (const float2*)t.ky, (const float*)t.wb, t.Mp, (float*)nullptr, 1);
