@@ -162,10 +162,11 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
   __shared__ float2 tw[N];
   __shared__ float2 stage[2 * N];  // products of the real columns 0 and N/2
   __shared__ float redf[2][kT / 64];
-  __shared__ unsigned redu[5][kT / 64];
+  __shared__ unsigned redu[4][kT / 64];
+  __shared__ unsigned xmax_s;  // split precision: largest |Re|, |Im| of X without DC (float bits)
   const int t = threadIdx.x;
   const int f = blockIdx.x;
-  float xmx = 0.f;  // this thread's largest |Re|, |Im| of X without the DC term
+  if (t == 0) xmax_s = 0u;
   const FrameDesc desc = g.desc[g.first + f];
   for (int i = t; i < N; i += kT) tw[i] = g.tw[i];
 
@@ -394,6 +395,16 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
       }
       const int col = cp + 64 * i;
       const bool packed = i == 0 && cp == 0;
+      // split precision: the largest |Re|, |Im| of the X values this thread
+      // stores, merged into xmax_s right after the stores (non-negative floats
+      // order as their bits), so no register carries it further
+      float xmx = 0.f;
+      auto merge_xmax = [&]() {
+        if constexpr (SPLIT) {
+          const unsigned xw = wave_max(__float_as_uint(xmx));
+          if ((t & 63) == 0) atomicMax(&xmax_s, xw);
+        }
+      };
       if (packed) {
         // P = F0 + i F128 with F0, F128 the spectra of the real columns 0 and
         // N/2: F0[ky] = (P[ky] + conj P[-ky]) / 2, F128 = (P[ky] - conj P[-ky]) / 2i;
@@ -480,9 +491,10 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
           const int ky = kap(hp, e >> 4) + 16 * (e & 15);
           const float2 x = r[pslot(e, i)];
           Xf[(size_t)ky * H + col] = x;
-          xmx = fmaxf(xmx, fmaxf(fabsf(x.x), fabsf(x.y)));
+          if constexpr (SPLIT) xmx = fmaxf(xmx, fmaxf(fabsf(x.x), fabsf(x.y)));
         }
       }
+      merge_xmax();
       if (i == 0) {
         // the two real columns' products, staged by the packed lanes; in
         // split precision also Z = X[., 0] + i X[., N/2] without the DC term,
@@ -491,8 +503,10 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
         for (int e = t; e < 2 * N; e += kT) {
           const float2 x = stage[e];
           Xf[(size_t)(e & (N - 1)) * H + (e >> 8) * (N / 2)] = x;
-          if (e) xmx = fmaxf(xmx, fmaxf(fabsf(x.x), fabsf(x.y)));  // (e = 0: the DC term)
+          if constexpr (SPLIT)
+            if (e) xmx = fmaxf(xmx, fmaxf(fabsf(x.x), fabsf(x.y)));  // (e = 0: the DC term)
         }
+        merge_xmax();
         if constexpr (SPLIT) {
           for (int ky = t; ky < N; ky += kT) {
             const float2 x0 = stage[ky], x1 = stage[N + ky];
@@ -691,14 +705,12 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
   kmin = ~wave_max(~kmin);
   kmax = wave_max(kmax);
   bad = wave_max(bad);
-  unsigned xb = wave_max(__float_as_uint(xmx));  // (non-negative floats order as their bits)
   if ((t & 63) == 0) {
     redf[0][t >> 6] = t1;
     redf[1][t >> 6] = t2;
     redu[0][t >> 6] = kmin;
     redu[1][t >> 6] = kmax;
     redu[2][t >> 6] = bad;
-    redu[4][t >> 6] = xb;
   }
   __syncthreads();
   t1 = redf[0][0];
@@ -726,10 +738,9 @@ __global__ void __launch_bounds__(kT) k_xcorr256(GroupParams g) {
       kmin = min(kmin, redu[0][w]);
       kmax = max(kmax, redu[1][w]);
       bad |= redu[2][w];
-      xb = max(xb, redu[4][w]);
     }
     FrameState& st = g.st[f];
-    st.xmax = xb;
+    st.xmax = SPLIT ? xmax_s : 0u;
     st.peak_key = peak_key(t1, idx);
     st.second_key = peak_key(t2, 0u);
     st.amin = kmin;
