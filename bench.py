@@ -8,7 +8,8 @@ N(0, 0.3 px) steps; upsampling factor u = 100 on the 1.5-px window.
 
 A "step" is one batched call of the whole path (correlation FFTs, integer
 peak, upsampled matrix DFT, FP64 Newton) over all frames, inputs already
-resident in HBM.  Also reported: the plain per-frame path (one call and one
+resident in HBM; by default its launch chunks alternate between two streams
+(--streams 2; the one-stream figure is reported beside it).  Also reported: the plain per-frame path (one call and one
 synchronisation per frame), the same with a captured hipGraph, the
 roofline of the dominant kernel from HIP events, and the FP64 CPU oracle
 timed on a bounded sample of the same frames (also used to check the GPU
@@ -354,6 +355,11 @@ def main():
     ap.add_argument("--chunk", type=int, default=768,
                     help="frames per launch chunk of the headline leg (768, three frames per CU, as in "
                          "the committed rocprofv3 summary); 0: the autotuner's choice")
+    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
+                    help="streams of the timed headline leg: 2 runs alternate launch chunks on two streams "
+                         "(CCPT_FLAG_STREAMS: one chunk's DFT overlaps the next chunk's correlation; results "
+                         "bit-identical to one stream); the per-kernel roofline always comes from a one-stream "
+                         "pass with HIP events around each launch")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -401,7 +407,7 @@ def main():
     M = int(np.ceil(1.5 * w.u - 1e-9))
 
     # ---- batched, headline precision: the timed steps (no per-kernel events)
-    tr = Tracker(upsample=w.u, precision=args.precision)
+    tr = Tracker(upsample=w.u, precision=args.precision, streams=args.streams)
     tr.set_reference(ref_t)
     if args.chunk > 0:
         tr.set_chunk(N, args.chunk)
@@ -413,7 +419,8 @@ def main():
     total, lat = time_batched(tr, frames_t, rois, out, args.steps, args.warmup, torch)
     res = decode(out)
     value = n * args.steps / total
-    log(f"[bench] batched {args.precision}: {value:,.0f} frames/s, step p50 {np.median(lat)*1e3:.2f} ms")
+    log(f"[bench] batched {args.precision} ({args.streams} stream{'s' if args.streams > 1 else ''}): "
+        f"{value:,.0f} frames/s, step p50 {np.median(lat)*1e3:.2f} ms")
     clocks = gpu_clocks()  # right after the timed steps, while the clocks are still up
     log(f"[bench] clocks {clocks}")
     tr.close()
@@ -474,7 +481,7 @@ def main():
     # with its agreement with the headline results
     if not args.no_extra and args.precision == "bf16x2":
         try:
-            tr5 = Tracker(upsample=w.u, precision="fp16x2")
+            tr5 = Tracker(upsample=w.u, precision="fp16x2", streams=args.streams)
             tr5.set_reference(ref_t)
             tr5.set_chunk(N, chunk)
             out5 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
@@ -491,12 +498,14 @@ def main():
         except Exception as e:  # noqa: BLE001
             legs["batched_fp16x2"] = dict(error=str(e)[:200])
 
-    # the headline precision with alternate chunks on two streams (CCPT_FLAG_STREAMS):
-    # the DFT of one chunk overlaps the FFTs of the next; results are bit-identical
-    # (an extra leg: its overlapping launches would also blur per-kernel traces)
+    # the headline precision on the other stream setting (one stream: every launch
+    # after the previous one; two: alternate chunks on two streams, the DFT of one
+    # chunk overlapping the FFTs of the next); results are bit-identical
+    other_streams = 3 - args.streams
+    sname = "one_stream" if other_streams == 1 else "two_streams"
     if not args.no_extra:
         try:
-            tr3 = Tracker(upsample=w.u, precision=args.precision, streams=2)
+            tr3 = Tracker(upsample=w.u, precision=args.precision, streams=other_streams)
             tr3.set_reference(ref_t)
             if args.chunk > 0:
                 tr3.set_chunk(N, args.chunk)
@@ -504,19 +513,19 @@ def main():
             out3 = torch.empty((n, 72), dtype=torch.uint8, device=dev)
             k3 = max(3, args.steps // 3)
             tot3, lat3 = time_batched(tr3, frames_t, tr3.rois(frames_t), out3, k3, 2, torch)
-            legs[f"batched_{args.precision}_two_streams"] = dict(
+            legs[f"batched_{args.precision}_{sname}"] = dict(
                 frames_per_s=round(n * k3 / tot3, 1), chunk=chunk3,
                 p50_ms=round(float(np.median(lat3)) * 1e3, 3),
                 bit_identical=bool(torch.equal(out3, out)))
-            log(f"[bench] two streams: {n * k3 / tot3:,.0f} frames/s (chunk {chunk3})")
+            log(f"[bench] {sname.replace('_', ' ')}: {n * k3 / tot3:,.0f} frames/s (chunk {chunk3})")
             tr3.close()
         except Exception as e:  # noqa: BLE001
-            legs[f"batched_{args.precision}_two_streams"] = dict(error=str(e)[:200])
+            legs[f"batched_{args.precision}_{sname}"] = dict(error=str(e)[:200])
 
     # the headline precision with the launch plan the autotuner picks on this machine
     if not args.no_extra and not args.no_tune and args.chunk > 0:
         try:
-            tr4 = Tracker(upsample=w.u, precision=args.precision)
+            tr4 = Tracker(upsample=w.u, precision=args.precision, streams=args.streams)
             tr4.set_reference(ref_t)
             chunk4 = tr4.autotune(N, n)
             k4 = max(3, args.steps // 3)
@@ -661,6 +670,7 @@ def main():
             "frames_per_step": n,
             "upsample": w.u,
             "chunk": chunk,
+            "streams": args.streams,
         },
         "batched_latency": {"p50_ms": round(float(np.median(lat)) * 1e3, 4),
                             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4)},
