@@ -479,6 +479,7 @@ def main():
 
     # the fp16 split (same kernels, fp16 hi + lo operands) at the headline chunk,
     # with its agreement with the headline results
+    r5 = None
     if not args.no_extra and args.precision == "bf16x2":
         try:
             tr5 = Tracker(upsample=w.u, precision="fp16x2", streams=args.streams)
@@ -616,9 +617,10 @@ def main():
             # oracle's: same grid point on every frame, and on the frames whose
             # oracle top-two grid values differ by more than the precision's
             # rounding (2^-20 of the grid maximum's AC part in FP32, 2^-17 with
-            # bf16 hi + lo operands; the rest are decided by rounding)
+            # bf16 hi + lo operands, 2^-18 with fp16 hi + lo; the rest are
+            # decided by rounding)
             same = np.max(np.abs(r["d_grid"][:k].astype(np.float64) - cpu["d_grid"]), axis=1) < 0.5 / w.u
-            tol = 2.0 ** -20 if prec == "fp32" else 2.0 ** -17
+            tol = {"fp32": 2.0 ** -20, "fp16x2": 2.0 ** -18}.get(prec, 2.0 ** -17)
             firm = cpu["grid_gap"] > tol * cpu["grid_ac"]
             gerr = np.max(np.abs(r["d_grid"][:k].astype(np.float64) - cpu["d_grid"]), axis=1)
             return dict(grid_index_agreement=float(same.mean()),
@@ -635,6 +637,10 @@ def main():
             e2 = np.max(np.abs(r2["d"][:k] - cpu["d"]), axis=1)
             accuracy[other] = dict(max_err_px=float(e2[ok].max()), p99_err_px=float(np.percentile(e2[ok], 99)),
                                    **grid_stats(r2, other))
+        if r5 is not None:
+            e5 = np.max(np.abs(r5["d"][:k] - cpu["d"]), axis=1)
+            accuracy["fp16x2"] = dict(max_err_px=float(e5[ok].max()), p99_err_px=float(np.percentile(e5[ok], 99)),
+                                      **grid_stats(r5, "fp16x2"))
         cpu_json = {
             "value": round(k / cpu["wall"], 2),
             "unit": "frames/s",
