@@ -1159,43 +1159,43 @@ __global__ void __launch_bounds__(256)
     }
   }
   // kx phase of the fold, per register (kx of register v); column 0 holds
-  // (Y[., 0], Y[., N/2]): phase 1, and the Nyquist output takes exp(i pi p_x)
+  // (Y[., 0], Y[., N/2]): phase 1 (the table's entry 0), and the Nyquist
+  // output takes exp(i pi p_x)
   const float nyq_sign = (ix & 1) ? -1.f : 1.f;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
+  auto rotate = [&](int v) {
     const int kx = kt * 32 + (v >> 2) * 8 + 4 * h + (v & 3);
-    if (kx > 0) {
-      const float2 ph = twf[(kx * ix * RX) % NY];
+    const float2 ph = twf[(kx * ix * RX) % NY];
+    const float sg = kx > 0 ? 1.f : nyq_sign;
 #pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        const float yr = accr[t][v], yi = acci[t][v];
-        accr[t][v] = yr * ph.x - yi * ph.y;
-        acci[t][v] = yr * ph.y + yi * ph.x;
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < MT; ++t) acci[t][v] *= nyq_sign;
+    for (int t = 0; t < MT; ++t) {
+      const float yr = accr[t][v], yi = acci[t][v];
+      accr[t][v] = yr * ph.x - yi * ph.y;
+      acci[t][v] = (yr * ph.y + yi * ph.x) * sg;
     }
-  }
+  };
   // Y as bf16 hi/lo A operands: k step s < 2 takes Yr, s >= 2 Yi, registers
   // 8 (s mod 2) .. 8 (s mod 2) + 7
   u32x4 yh[MT][4], yl[MT][4];
+  auto split_y = [&](int t, int s4, int q) {
+    const int v = 8 * (s4 & 1) + 2 * q;
+    const f32x16& a = s4 < 2 ? accr[t] : acci[t];
+    unsigned wh, wl;
+    if constexpr (F16)  // |Y| <= 256 * 2^13: scaled by 2^-8 into the fp16 range (exact)
+      split2_f16(a[v] * 0x1p-8f, a[v + 1] * 0x1p-8f, wh, wl);
+    else
+      split2(a[v], a[v + 1], wh, wl);
+    yh[t][s4][q] = wh;
+    yl[t][s4][q] = wl;
+  };
+  // before the first round only what its first k step needs (registers
+  // 0..7 rotated, k step 0 split); the rest is placed between the first
+  // round's matrix instructions (transition_hook below)
+#pragma unroll
+  for (int v = 0; v < 8; ++v) rotate(v);
 #pragma unroll
   for (int t = 0; t < MT; ++t)
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int v = 8 * (s4 & 1) + 2 * q;
-        const f32x16& a = s4 < 2 ? accr[t] : acci[t];
-        unsigned wh, wl;
-        if constexpr (F16)  // |Y| <= 256 * 2^13: scaled by 2^-8 into the fp16 range (exact)
-          split2_f16(a[v] * 0x1p-8f, a[v + 1] * 0x1p-8f, wh, wl);
-        else
-          split2(a[v], a[v + 1], wh, wl);
-        yh[t][s4][q] = wh;
-        yl[t][s4][q] = wl;
-      }
+    for (int q = 0; q < 4; ++q) split_y(t, 0, q);
   // Stage B per 32-column tile r of the grid: this wave's partial over its kx
   // slice, then the four partials added in wave order
   const int nr = Mp / 32;
@@ -1212,64 +1212,147 @@ __global__ void __launch_bounds__(256)
   };
   float* up = (float*)raw;
   unsigned long long best = 0;
-  load_w(0, wh, wl);
-  for (int r = 0; r < nr; ++r) {
-    if (r + 1 < nr) load_w(r + 1, nwh, nwl);
-    f32x16 au[MT];
+  // One round's products: au = this wave's partial grid of one 32-column
+  // tile over its kx slice; hook(slot) after each of the 60 instructions.
+  auto round_mma = [&](f32x16* au, auto&& hook) {
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int v = 0; v < 16; ++v) au[t][v] = 0.f;
+    int slot = 0;
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       const u32x4 w_h = wh[s4], w_l = wl[s4];
 #pragma unroll
-      for (int t = 0; t < MT; ++t)
+      for (int t = 0; t < MT; ++t) {
         au[t] = mfma32<F16>(yh[t][s4], w_h, au[t]);
+        hook(slot++);
+      }
 #pragma unroll
-      for (int t = 0; t < MT; ++t)
+      for (int t = 0; t < MT; ++t) {
         au[t] = mfma32<F16>(yh[t][s4], w_l, au[t]);
+        hook(slot++);
+      }
 #pragma unroll
-      for (int t = 0; t < MT; ++t)
+      for (int t = 0; t < MT; ++t) {
         au[t] = mfma32<F16>(yl[t][s4], w_h, au[t]);
+        hook(slot++);
+      }
     }
-    __syncthreads();  // the last round's sums (or Stage A's chunks) are done with LDS
-    // this wave's partial grid, column-major: up[kt][mx][my] (mx = lane mod 32)
+  };
+  // this wave's partial grid, column-major: up[kt][mx][my] (mx = lane mod 32)
+  auto write_up = [&](const f32x16* au) {
 #pragma unroll
     for (int t = 0; t < MT; ++t)
-      {
 #pragma unroll
-        for (int v4 = 0; v4 < 4; ++v4)
-          *(f32x4*)(up + kt * UW + j * UST + t * 32 + v4 * 8 + 4 * h) =
-              f32x4{au[t][4 * v4], au[t][4 * v4 + 1], au[t][4 * v4 + 2], au[t][4 * v4 + 3]};
-      }
-    __syncthreads();
-    for (int i = tid; i < 32 * ROWS / 4; i += NTH) {
-      const int mxl = i / (ROWS / 4), my4 = i - mxl * (ROWS / 4);
+      for (int v4 = 0; v4 < 4; ++v4)
+        *(f32x4*)(up + kt * UW + j * UST + t * 32 + v4 * 8 + 4 * h) =
+            f32x4{au[t][4 * v4], au[t][4 * v4 + 1], au[t][4 * v4 + 2], au[t][4 * v4 + 3]};
+  };
+  // The four partials of round r are added in wave order and their maximum
+  // taken in MT items per thread (item it: four grid rows of one column),
+  // each split into phases: its LDS reads, the sums, then one grid point's
+  // key at a time.
+  static_assert(32 * ROWS / 4 == MT * NTH, "MT reduction items per thread");
+  f32x4 rq[NKT];
+  f32x4 rsum;
+  auto reduce_phase = [&](int r, int it, int ph) {
+    const int i = tid + it * NTH;
+    const int mxl = i / (ROWS / 4), my4 = i - mxl * (ROWS / 4);
+    if (ph == 0) {
       const float* q = up + mxl * UST + 4 * my4;
-      f32x4 sum = *(const f32x4*)q;
+#pragma unroll
+      for (int w = 0; w < NKT; ++w) rq[w] = *(const f32x4*)(q + w * UW);
+    } else if (ph == 1) {
+      rsum = rq[0];
 #pragma unroll
       for (int w = 1; w < NKT; ++w) {
-        const f32x4 o = *(const f32x4*)(q + w * UW);
-        sum[0] += o[0];
-        sum[1] += o[1];
-        sum[2] += o[2];
-        sum[3] += o[3];
+        rsum[0] += rq[w][0];
+        rsum[1] += rq[w][1];
+        rsum[2] += rq[w][2];
+        rsum[3] += rq[w][3];
       }
+    } else {
+      const int e = ph - 2;
       const int mx = r * 32 + mxl;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int my = m0 + 4 * my4 + e;
-        if (my < g.M && mx < g.M) {
-          const unsigned long long key = peak_key(sum[e], grid_index(my, mx, g.M, tr));
-          best = key > best ? key : best;
-        }
-      }
+      const int my = m0 + 4 * my4 + e;
+      // (a select, not a branch: grid points past M count as key 0)
+      unsigned long long key = peak_key(rsum[e], grid_index(my, mx, g.M, tr));
+      key = (my < g.M && mx < g.M) ? key : 0ull;
+      best = key > best ? key : best;
     }
+  };
+  // round r + 1's matrix instructions carry round r's reduction: item it's
+  // phases after instructions 12 it, 12 it + 4, 12 it + 6, ... (the phases
+  // are fenced in place, so the VALU work issues in the shadow of the
+  // instructions around it and each item's LDS reads have three
+  // instructions to land)
+  auto reduce_hook = [&](int r) {
+    return [&, r](int slot) {
+      const int it = slot / 12, k = slot - 12 * it;
+      const int ph = k == 0 ? 0 : k == 4 ? 1 : k == 6 ? 2 : k == 8 ? 3 : k == 10 ? 4 : k == 11 ? 5 : -1;
+      if (ph >= 0) {
+        __builtin_amdgcn_sched_barrier(0);
+        reduce_phase(r, it, ph);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+  };
+  static_assert(12 * MT == 4 * 3 * MT, "twelve instructions per reduction item");
+  // the first round's k steps 0..2 carry the rest of the rotation (registers
+  // 8..15, before the split of k step 1) and the splits of k steps 1..3, each
+  // done before the k step that reads it
+  auto transition_hook = [&](int slot) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (slot < 15) {
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      wh[s4] = nwh[s4];
-      wl[s4] = nwl[s4];
+      for (int p = 2 * slot; p < 2 * slot + 2; ++p) {
+        if (p < 8)
+          rotate(8 + p);
+        else if (p < 28)
+          split_y((p - 8) / 4, 1, (p - 8) % 4);
+      }
+    } else if (slot < 45) {
+      const int s4 = slot < 30 ? 2 : 3, base = slot < 30 ? 15 : 30;
+#pragma unroll
+      for (int i = 0; i < 4 * MT; ++i)
+        if (base + (i * 15) / (4 * MT) == slot) split_y(i / 4, s4, i % 4);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  static_assert(8 + 4 * MT <= 30, "the first k step's slots hold the rotation and the k step 1 split");
+  f32x16 au[MT];
+  load_w(0, wh, wl);
+  if (nr > 1) load_w(1, nwh, nwl);
+  round_mma(au, transition_hook);
+  __syncthreads();  // Stage A's chunks are done with LDS
+  write_up(au);
+  __syncthreads();
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    wh[s4] = nwh[s4];
+    wl[s4] = nwl[s4];
+  }
+  for (int r = 0; r < nr; ++r) {
+    const bool more = r + 1 < nr;
+    if (r + 2 < nr) load_w(r + 2, nwh, nwl);
+    if (more) {
+      round_mma(au, reduce_hook(r));
+    } else {
+#pragma unroll
+      for (int it = 0; it < MT; ++it)
+#pragma unroll
+        for (int ph = 0; ph < 6; ++ph) reduce_phase(r, it, ph);
+    }
+    __syncthreads();  // every wave is done reading round r's partials
+    if (more) {
+      write_up(au);
+      __syncthreads();
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        wh[s4] = nwh[s4];
+        wl[s4] = nwl[s4];
+      }
     }
   }
   best = wmax64(best);
