@@ -1041,8 +1041,11 @@ __global__ void __launch_bounds__(256)
   };
   // Stage A products of one ky chunk, transposed: the spectrum fragment is the
   // A operand (rows kx), the K' fragment the B operand (columns m)
-  auto mma_chunk = [&](const unsigned* ks_hi, const u32x4* bh, const u32x4* bl) {
+  // hook(slot) after each pair of matrix instructions (slot 15 s8 + j for
+  // MT = 5): work the caller places in the shadow of the instructions
+  auto mma_chunk = [&](const unsigned* ks_hi, const u32x4* bh, const u32x4* bl, auto&& hook) {
     const unsigned* ks_lo = ks_hi + ROWS * KCS;
+    int slot = 0;
 #pragma unroll
     for (int s8 = 0; s8 < KC / 8; ++s8) {
       const int col = s8 * 8 + 4 * h;
@@ -1061,18 +1064,21 @@ __global__ void __launch_bounds__(256)
         {
           accr[t] = mfma32<F16>(bh_r, ah[t], accr[t]);
           acci[t] = mfma32<F16>(bh_i, ah[t], acci[t]);
+          hook(slot++);
         }
 #pragma unroll
       for (int t = 0; t < MT; ++t)
         {
           accr[t] = mfma32<F16>(bl_r, ah[t], accr[t]);
           acci[t] = mfma32<F16>(bl_i, ah[t], acci[t]);
+          hook(slot++);
         }
 #pragma unroll
       for (int t = 0; t < MT; ++t)
         {
           accr[t] = mfma32<F16>(bh_r, al[t], accr[t]);
           acci[t] = mfma32<F16>(bh_i, al[t], acci[t]);
+          hook(slot++);
         }
     }
   };
@@ -1100,37 +1106,68 @@ __global__ void __launch_bounds__(256)
       (void)frexpf(xm, &ex);
       if (xm > 0.f && xm <= 3.4e38f) xsc = ldexpf(1.f, min(13 - ex, 120));  // (finite X only)
     }
-    auto split_x = [&]() {
+    // Stage A pipelined by k step: at the top of chunk c, bh/bl[0] hold the
+    // split of X(c)'s k step 0 and xr[1..3] its raw k steps 1..3.  Between
+    // the matrix instructions of k step s the split of k step s + 1 is made
+    // and its register group reloaded with the next chunk's values (so each
+    // X load has a whole chunk to arrive), and between those of the last
+    // k step the next chunk's K' fragments go to the other LDS buffer; after
+    // the barrier only the next chunk's k step 0 is split.  The last chunk
+    // requests itself again (no branch in the loop body).
+    auto load_x8 = [&](int k0, int s8) {
 #pragma unroll
-      for (int s8 = 0; s8 < KC / 8; ++s8)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          unsigned wh, wl;
-          if constexpr (F16)
-            split2_f16(xr[s8][e].x * xsc, xr[s8][e].y * xsc, wh, wl);
-          else
-            split_pair(xr[s8][e], wh, wl);
-          bh[s8][e] = wh;
-          bl[s8][e] = wl;
-        }
+      for (int e = 0; e < 4; ++e) xr[s8][e] = Xc[(size_t)(k0 + s8 * 8 + 4 * h + e) * xs];
     };
+    auto split_x8 = [&](int s8, int e) {
+      unsigned wh, wl;
+      if constexpr (F16)
+        split2_f16(xr[s8][e].x * xsc, xr[s8][e].y * xsc, wh, wl);
+      else
+        split_pair(xr[s8][e], wh, wl);
+      bh[s8][e] = wh;
+      bl[s8][e] = wl;
+    };
+    static_assert(KC / 8 == 4 && MT == 5 && KQ <= 6, "hook slots laid out for 4 k steps of 15 pairs");
     load_x(0);
     load_k(0);
-    split_x();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) split_x8(0, e);
     store_k(raw);
     __syncthreads();
     for (int c = 0; c < NCH; ++c) {
-      const bool more = c + 1 < NCH;
-      if (more) {
-        load_x((c + 1) * KC);
-        load_k((c + 1) * KC);
-      }
+      const int cn = (c + 1 < NCH ? c + 1 : c) * KC;
+      unsigned* knext = raw + ((c + 1) & 1) * KW;
+      load_k(cn);
+      load_x8(cn, 0);
       __builtin_amdgcn_sched_barrier(0);
-      mma_chunk(raw + (c & 1) * KW, bh, bl);
+      mma_chunk(raw + (c & 1) * KW, bh, bl, [&](int slot) {
+        const int s8 = slot / 15, j = slot - 15 * s8;
+        if (s8 < 3) {
+          if (j == 2 || j == 4 || j == 6 || j == 8) {
+            __builtin_amdgcn_sched_barrier(0);
+            split_x8(s8 + 1, (j - 2) / 2);
+            __builtin_amdgcn_sched_barrier(0);
+          } else if (j == 10) {
+            __builtin_amdgcn_sched_barrier(0);
+            load_x8(cn, s8 + 1);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        } else if (j >= 2 && (j & 1) == 0 && (j - 2) / 2 < KQ) {
+          const int q = (j - 2) / 2;
+          const int i = tid + q * NTH;
+          if (KCOPY % NTH == 0 || i < KCOPY) {
+            __builtin_amdgcn_sched_barrier(0);
+            const int r = i / (KC / 4), c4 = i - r * (KC / 4);
+            *(u32x4*)(knext + r * KCS + 4 * c4) = kh[q];
+            *(u32x4*)(knext + ROWS * KCS + r * KCS + 4 * c4) = kl[q];
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      });
       __builtin_amdgcn_sched_barrier(0);
-      if (more) store_k(raw + ((c + 1) & 1) * KW);
       __syncthreads();
-      if (more) split_x();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) split_x8(0, e);
     }
   } else {
     u32x4 nh[KC / 8], nl[KC / 8];
@@ -1145,7 +1182,7 @@ __global__ void __launch_bounds__(256)
         load_k((c + 1) * KC);
       }
       __builtin_amdgcn_sched_barrier(0);
-      mma_chunk(raw + (c & 1) * KW, bh, bl);
+      mma_chunk(raw + (c & 1) * KW, bh, bl, [](int) {});
       __builtin_amdgcn_sched_barrier(0);
       if (more) store_k(raw + ((c + 1) & 1) * KW);
       __syncthreads();
