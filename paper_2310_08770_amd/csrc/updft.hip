@@ -1107,13 +1107,15 @@ __global__ void __launch_bounds__(256)
       if (xm > 0.f && xm <= 3.4e38f) xsc = ldexpf(1.f, min(13 - ex, 120));  // (finite X only)
     }
     // Stage A pipelined by k step: at the top of chunk c, bh/bl[0] hold the
-    // split of X(c)'s k step 0 and xr[1..3] its raw k steps 1..3.  Between
-    // the matrix instructions of k step s the split of k step s + 1 is made
-    // and its register group reloaded with the next chunk's values (so each
-    // X load has a whole chunk to arrive), and between those of the last
-    // k step the next chunk's K' fragments go to the other LDS buffer; after
-    // the barrier only the next chunk's k step 0 is split.  The last chunk
-    // requests itself again (no branch in the loop body).
+    // split of X(c)'s k step 0, xr[1..3] its raw k steps 1..3 and xr[0] the
+    // raw k step 0 of chunk c + 1.  Between the matrix instructions of k step
+    // s < 3 the split of k step s + 1 is made and its register group reloaded
+    // with the next chunk's values; between those of the last k step the next
+    // chunk's K' fragments go to the other LDS buffer, its k step 0 is split
+    // (bh/bl[0] are free once k step 0 is done) and xr[0] reloaded with the
+    // chunk after it.  So every X load has a whole chunk to arrive and nothing
+    // but the barrier separates two chunks' matrix instructions.  The last
+    // chunks request themselves again (no branch in the loop body).
     auto load_x8 = [&](int k0, int s8) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) xr[s8][e] = Xc[(size_t)(k0 + s8 * 8 + 4 * h + e) * xs];
@@ -1132,13 +1134,14 @@ __global__ void __launch_bounds__(256)
     load_k(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) split_x8(0, e);
+    load_x8((NCH > 1 ? 1 : 0) * KC, 0);
     store_k(raw);
     __syncthreads();
     for (int c = 0; c < NCH; ++c) {
       const int cn = (c + 1 < NCH ? c + 1 : c) * KC;
+      const int cnn = (c + 2 < NCH ? c + 2 : NCH - 1) * KC;
       unsigned* knext = raw + ((c + 1) & 1) * KW;
       load_k(cn);
-      load_x8(cn, 0);
       __builtin_amdgcn_sched_barrier(0);
       mma_chunk(raw + (c & 1) * KW, bh, bl, [&](int slot) {
         const int s8 = slot / 15, j = slot - 15 * s8;
@@ -1162,12 +1165,18 @@ __global__ void __launch_bounds__(256)
             *(u32x4*)(knext + ROWS * KCS + r * KCS + 4 * c4) = kl[q];
             __builtin_amdgcn_sched_barrier(0);
           }
+        } else if (j == 3 || j == 5 || j == 7 || j == 9) {
+          __builtin_amdgcn_sched_barrier(0);
+          split_x8(0, (j - 3) / 2);
+          __builtin_amdgcn_sched_barrier(0);
+        } else if (j == 11) {
+          __builtin_amdgcn_sched_barrier(0);
+          load_x8(cnn, 0);
+          __builtin_amdgcn_sched_barrier(0);
         }
       });
       __builtin_amdgcn_sched_barrier(0);
       __syncthreads();
-#pragma unroll
-      for (int e = 0; e < 4; ++e) split_x8(0, e);
     }
   } else {
     u32x4 nh[KC / 8], nl[KC / 8];
@@ -1277,14 +1286,36 @@ __global__ void __launch_bounds__(256)
       }
     }
   };
-  // this wave's partial grid, column-major: up[kt][mx][my] (mx = lane mod 32)
-  auto write_up = [&](const f32x16* au) {
+  // the same products tile by tile (each tile's accumulation order as above,
+  // so the sums are identical); hook(slot) after each instruction
+  auto round_mma_t = [&](f32x16* au, auto&& hook) {
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
-      for (int v4 = 0; v4 < 4; ++v4)
-        *(f32x4*)(up + kt * UW + j * UST + t * 32 + v4 * 8 + 4 * h) =
-            f32x4{au[t][4 * v4], au[t][4 * v4 + 1], au[t][4 * v4 + 2], au[t][4 * v4 + 3]};
+      for (int v = 0; v < 16; ++v) au[t][v] = 0.f;
+    int slot = 0;
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        au[t] = mfma32<F16>(yh[t][s4], wh[s4], au[t]);
+        hook(slot++);
+        au[t] = mfma32<F16>(yh[t][s4], wl[s4], au[t]);
+        hook(slot++);
+        au[t] = mfma32<F16>(yl[t][s4], wh[s4], au[t]);
+        hook(slot++);
+      }
+  };
+  // this wave's partial grid, column-major: up[kt][mx][my] (mx = lane mod 32)
+  auto write_tile = [&](const f32x16* au, int t) {
+#pragma unroll
+    for (int v4 = 0; v4 < 4; ++v4)
+      *(f32x4*)(up + kt * UW + j * UST + t * 32 + v4 * 8 + 4 * h) =
+          f32x4{au[t][4 * v4], au[t][4 * v4 + 1], au[t][4 * v4 + 2], au[t][4 * v4 + 3]};
+  };
+  auto write_up = [&](const f32x16* au) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t) write_tile(au, t);
   };
   // The four partials of round r are added in wave order and their maximum
   // taken in MT items per thread (item it: four grid rows of one column),
@@ -1370,26 +1401,61 @@ __global__ void __launch_bounds__(256)
     wh[s4] = nwh[s4];
     wl[s4] = nwl[s4];
   }
+  // rounds after the first, tile by tile: round r's reduction in the first
+  // 30 instruction slots (item it: reads after slot 6 it, sums after 6 it + 3,
+  // keys after 6 it + 4 and 6 it + 5), then a barrier (every wave is done
+  // reading round r's partials), then each finished tile's partial written
+  // two instructions after its last one; the last tile's after the round
+  static_assert(MT == 5, "tile-by-tile rounds laid out for five row tiles");
+  auto round_hook = [&](int r, const f32x16* au) {
+    return [&, r, au](int slot) {
+      if (slot < 30) {
+        const int it = slot / 6, k = slot - 6 * it;
+        if (k == 0 || k == 3 || k == 4 || k == 5) {
+          __builtin_amdgcn_sched_barrier(0);
+          if (k == 0) {
+            reduce_phase(r, it, 0);
+          } else if (k == 3) {
+            reduce_phase(r, it, 1);
+          } else {
+            reduce_phase(r, it, 2 * k - 6);
+            reduce_phase(r, it, 2 * k - 5);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (slot == 29) {
+          __builtin_amdgcn_sched_barrier(0);
+          __syncthreads();
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        // tiles 0 and 1 are complete by the barrier; tile t >= 2 after slot 12 t + 11
+        const int t = slot == 30 ? 0 : slot == 31 ? 1 : (slot >= 37 && (slot - 37) % 12 == 0) ? 2 + (slot - 37) / 12 : -1;
+        if (t >= 0 && t < MT - 1) {
+          __builtin_amdgcn_sched_barrier(0);
+          write_tile(au, t);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    };
+  };
   for (int r = 0; r < nr; ++r) {
     const bool more = r + 1 < nr;
     if (r + 2 < nr) load_w(r + 2, nwh, nwl);
     if (more) {
-      round_mma(au, reduce_hook(r));
-    } else {
-#pragma unroll
-      for (int it = 0; it < MT; ++it)
-#pragma unroll
-        for (int ph = 0; ph < 6; ++ph) reduce_phase(r, it, ph);
-    }
-    __syncthreads();  // every wave is done reading round r's partials
-    if (more) {
-      write_up(au);
+      round_mma_t(au, round_hook(r, au));
+      write_tile(au, MT - 1);
       __syncthreads();
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         wh[s4] = nwh[s4];
         wl[s4] = nwl[s4];
       }
+    } else {
+#pragma unroll
+      for (int it = 0; it < MT; ++it)
+#pragma unroll
+        for (int ph = 0; ph < 6; ++ph) reduce_phase(r, it, ph);
     }
   }
   best = wmax64(best);
