@@ -1324,6 +1324,8 @@ __global__ void __launch_bounds__(256)
   static_assert(32 * ROWS / 4 == MT * NTH, "MT reduction items per thread");
   f32x4 rq[NKT];
   f32x4 rsum;
+  float rbv;  // the item's largest sum and its row offset
+  int rbe;
   auto reduce_phase = [&](int r, int it, int ph) {
     const int i = tid + it * NTH;
     const int mxl = i / (ROWS / 4), my4 = i - mxl * (ROWS / 4);
@@ -1340,33 +1342,31 @@ __global__ void __launch_bounds__(256)
         rsum[2] += rq[w][2];
         rsum[3] += rq[w][3];
       }
-    } else {
-      const int e = ph - 2;
+    } else if (ph == 2) {
+      // the item's four grid points share a column and have increasing rows,
+      // so increasing grid indices in either orientation: a strict compare in
+      // that order keeps the lowest index among equal values, as the key
+      // order does; points past M take part as -inf
       const int mx = r * 32 + mxl;
-      const int my = m0 + 4 * my4 + e;
-      // (a select, not a branch: grid points past M count as key 0)
-      unsigned long long key = peak_key(rsum[e], grid_index(my, mx, g.M, tr));
-      key = (my < g.M && mx < g.M) ? key : 0ull;
+      const int my0 = m0 + 4 * my4;
+      const bool cin = mx < g.M;
+      rbv = (cin && my0 < g.M) ? rsum[0] : -INFINITY;
+      rbe = 0;
+#pragma unroll
+      for (int e = 1; e < 4; ++e) {
+        const float v = (cin && my0 + e < g.M) ? rsum[e] : -INFINITY;
+        const bool gt = v > rbv;
+        rbv = gt ? v : rbv;
+        rbe = gt ? e : rbe;
+      }
+    } else if (ph == 3) {
+      const int mx = r * 32 + mxl;
+      // one key per item (a select, not a branch: an item with no grid point counts as key 0)
+      unsigned long long key = peak_key(rbv, grid_index(m0 + 4 * my4 + rbe, mx, g.M, tr));
+      key = rbv > -INFINITY ? key : 0ull;
       best = key > best ? key : best;
     }
   };
-  // round r + 1's matrix instructions carry round r's reduction: item it's
-  // phases after instructions 12 it, 12 it + 4, 12 it + 6, ... (the phases
-  // are fenced in place, so the VALU work issues in the shadow of the
-  // instructions around it and each item's LDS reads have three
-  // instructions to land)
-  auto reduce_hook = [&](int r) {
-    return [&, r](int slot) {
-      const int it = slot / 12, k = slot - 12 * it;
-      const int ph = k == 0 ? 0 : k == 4 ? 1 : k == 6 ? 2 : k == 8 ? 3 : k == 10 ? 4 : k == 11 ? 5 : -1;
-      if (ph >= 0) {
-        __builtin_amdgcn_sched_barrier(0);
-        reduce_phase(r, it, ph);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    };
-  };
-  static_assert(12 * MT == 4 * 3 * MT, "twelve instructions per reduction item");
   // the first round's k steps 0..2 carry the rest of the rotation (registers
   // 8..15, before the split of k step 1) and the splits of k steps 1..3, each
   // done before the k step that reads it
@@ -1403,7 +1403,7 @@ __global__ void __launch_bounds__(256)
   }
   // rounds after the first, tile by tile: round r's reduction in the first
   // 30 instruction slots (item it: reads after slot 6 it, sums after 6 it + 3,
-  // keys after 6 it + 4 and 6 it + 5), then a barrier (every wave is done
+  // its largest point after 6 it + 4, its key after 6 it + 5), then a barrier (every wave is done
   // reading round r's partials), then each finished tile's partial written
   // two instructions after its last one; the last tile's after the round
   static_assert(MT == 5, "tile-by-tile rounds laid out for five row tiles");
@@ -1413,14 +1413,7 @@ __global__ void __launch_bounds__(256)
         const int it = slot / 6, k = slot - 6 * it;
         if (k == 0 || k == 3 || k == 4 || k == 5) {
           __builtin_amdgcn_sched_barrier(0);
-          if (k == 0) {
-            reduce_phase(r, it, 0);
-          } else if (k == 3) {
-            reduce_phase(r, it, 1);
-          } else {
-            reduce_phase(r, it, 2 * k - 6);
-            reduce_phase(r, it, 2 * k - 5);
-          }
+          reduce_phase(r, it, k == 0 ? 0 : k - 2);
           __builtin_amdgcn_sched_barrier(0);
         }
         if (slot == 29) {
@@ -1455,7 +1448,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int it = 0; it < MT; ++it)
 #pragma unroll
-        for (int ph = 0; ph < 6; ++ph) reduce_phase(r, it, ph);
+        for (int ph = 0; ph < 4; ++ph) reduce_phase(r, it, ph);
     }
   }
   best = wmax64(best);
