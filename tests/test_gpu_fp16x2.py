@@ -155,3 +155,19 @@ def test_fp16x2_refuses_what_it_does_not_run():
     out = tr.track(t(np.stack(w.frames)))
     assert out.shape[0] == 4
     tr.close()
+
+
+@pytest.mark.parametrize("u", [256, 1024])
+def test_fp16x2_large_upsampling_matches_the_oracle(u):
+    """Table I's larger factors at 256x256 (grids of 384 and 1536 points a
+    side: more Stage B rounds and, at u = 1024, several row-tile blocks per
+    frame), CC-SN, 3 frames against the oracle and against the bf16 split."""
+    say(f"case: fp16x2 at u = {u}, 256x256 Airy frames, CC-SN eps=200, 3 frames vs oracle")
+    w = S.table1_frames(256, 256, 3)
+    ref = w.refs[0].astype(np.float32)
+    fr = np.stack(w.frames)
+    a = track(fr, ref, u, precision="fp16x2", mode="ccsn", eps=200.0)
+    b = track(fr, ref, u, precision="bf16x2", mode="ccsn", eps=200.0)
+    assert np.array_equal(a["p"], b["p"])
+    errs = check_oracle(a, fr, ref, u, O.MODE_CCSN)
+    say(f"  max |dd| {errs.max():.2e} px; vs bf16x2 {np.max(np.abs(a['d'] - b['d'])):.2e} px")
